@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package holds no part of the method's arithmetic: it only draws random
+numbers and arranges them into integral tensors and flat value streams.  Both
+the CPU oracle and the HIP library consume exactly these arrays.
+"""
+
+from .integrals import (  # noqa: F401
+    Integrals,
+    random_integrals_cfg1,
+    chain_integrals,
+    config_integrals,
+    batched_instances,
+    mps_values,
+    CONFIGS,
+)
