@@ -1,0 +1,218 @@
+/*
+ * dmrg.h -- C ABI of the MI355X two-site ab initio DMRG library.
+ *
+ * The library computes the ground state of the ab initio Hamiltonian
+ *     H = sum_pq t_pq a+_p a_q + 1/2 sum_pqrs v_pqrs a+_p a+_q a_r a_s
+ * (Chan et al., arXiv:1605.02611, Sec. 2.4, Eq. longrangeh) as a matrix
+ * product state, by the two-site DMRG sweep of Sec. 2.1 (blocking, solving,
+ * decimation) written in MPO form (Secs. 2.3-2.5).  Everything that scales
+ * with the bond dimension runs on one GPU in hand-written HIP kernels; the
+ * host keeps only integer bookkeeping and scalars.
+ *
+ * Conventions shared by every entry point
+ *   - Sites are spatial orbitals 0..K-1 with local states
+ *     s = 0 |0>, 1 |up>, 2 |dn>, 3 |up dn> = a+_up a+_dn |0>,
+ *     spin orbitals in Jordan-Wigner order (0up, 0dn, 1up, 1dn, ...).
+ *   - Quantum numbers are (N, 2S_z) pairs of ints; a bond is labelled by the
+ *     quantum numbers of its left block; sectors are sorted lexicographically.
+ *   - Integrals are chemists' notation (ij|kl): h[K*K] and v[K^4] row-major
+ *     FP64; the library maps them to the paper's spin-orbital t and v with
+ *     v_PQRS = (ps|qr) d(sP,sS) d(sQ,sR).
+ *   - Every function returns dmrg_status; DMRG_OK is 0.  On error no output
+ *     argument is written and dmrg_last_error(ctx) describes the failure
+ *     until the next call on that context.  No exception or abort crosses
+ *     the ABI.
+ *   - Host arrays passed in are borrowed for the duration of the call;
+ *     handles are owned by the library and released with the *_free /
+ *     *_destroy functions; arrays written by the library are caller-owned.
+ *   - A context is single-threaded: all work is ordered on its HIP stream.
+ *     Functions that return host values synchronise that stream first.
+ *
+ * Two-site vector layout ("merged sector" layout, used by dmrg_sigma and the
+ * psi export/import): the two-site wavefunction at the pair (j, j+1) is
+ * block diagonal in the middle-bond sector q (left-block quantum numbers at
+ * bond j+1).  Sectors are stored in sorted order, each as a dense row-major
+ * matrix.  Rows are the (left state, site-j state s) pairs with
+ * Q_l + q_s = q ordered by Q_l (that is s = 3, 1, 2, 0), states of a sector
+ * in basis order; columns are the (site-(j+1) state t, right state) pairs
+ * ordered by t = 0..3, right states of bond j+2 sector q + q_t in basis
+ * order.
+ *
+ * Site-tensor layout for import/export ("fine blocks"): for site j, blocks
+ * (Q_l, s) for Q_l in the sorted sectors of bond j and s = 0..3 whenever
+ * Q_l + q_s is a sector of bond j+1, in that order, each block
+ * m_j(Q_l) x m_{j+1}(Q_l + q_s) row-major.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMRG_OK = 0,
+    DMRG_E_INVAL = 1,   /* bad argument: sizes, symmetry, quantum numbers */
+    DMRG_E_NOMEM = 2,   /* device or host allocation failed */
+    DMRG_E_HIP = 3,     /* a HIP / rocSOLVER call failed */
+    DMRG_E_NOCONV = 4,  /* an eigensolver hit its iteration limit (result kept) */
+    DMRG_E_NUMERIC = 5, /* NaN or Inf in a vector or an SVD failure */
+    DMRG_E_STATE = 6    /* call made on an object in the wrong state */
+} dmrg_status;
+
+typedef enum {
+    DMRG_FP64 = 0,  /* contractions in FP64 */
+    DMRG_FP32 = 1,  /* contractions in FP32 (FP32 accumulation) */
+    DMRG_BF16 = 2   /* contraction inputs rounded to BF16, FP32 accumulation */
+} dmrg_prec;
+
+typedef struct dmrg_ctx dmrg_ctx;
+typedef struct dmrg_mpo dmrg_mpo;
+typedef struct dmrg_mps dmrg_mps;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * order all work on, or NULL for a stream owned by the context.  device = -1
+ * gives a host-only context that can build and query MPOs; every call that
+ * needs the GPU then fails with DMRG_E_STATE. */
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out);
+void dmrg_ctx_destroy(dmrg_ctx* ctx);
+/* Text of the last error on ctx (never NULL; "" after success). */
+const char* dmrg_last_error(const dmrg_ctx* ctx);
+
+/* ---- MPO (Sec. 2.4, Eqs. Hdecomp, Sm, norm_complementary, prenormrule) --- */
+
+typedef struct {
+    int switch_bond;     /* bonds k <= switch_bond keep normal two-index
+                            operators on the left; -1 = floor(K/2) */
+    double compress_tol; /* reserved; must be 0 (exact MPO) */
+} dmrg_mpo_opts;
+
+/* Build the normal/complementary MPO of H for K sites, N electrons and
+ * target 2S_z.  h: K*K, v: K^4 (host, FP64, chemists' notation).
+ * Errors: DMRG_E_INVAL if K < 1, N outside [0, 2K], parity(2S_z) !=
+ * parity(N), |2S_z| > min(N, 2K-N), h not symmetric or v without the
+ * 8-fold symmetry (relative tolerance 1e-12). */
+dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
+                           int n_elec, int two_sz, const dmrg_mpo_opts* opts,
+                           dmrg_mpo** out);
+/* MPO bond dimensions D[0..K] (caller-owned array of K+1). */
+dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D);
+/* Channel labels of bond k: 3*D[k] ints (kind, p, q), kinds
+ * 0 I, 1 H, 2 a+_p, 3 a_p, 4 S^L_p, 5 S^L+_p, 6 a+_p a+_q, 7 a_q a_p,
+ * 8 a+_p a_q, 9 P^L_pq, 10 P^L+_pq, 11 Q^L_pq (p, q spin orbitals, -1 unused). */
+dmrg_status dmrg_mpo_channels(const dmrg_mpo* mpo, int bond, int32_t* labels);
+/* Nonzero entries of W[site]: call with xy == NULL to get *n; then xy (2n:
+ * left channel, right channel) and mats (16n: 4x4 row-major, row = output
+ * state) receive the entries. */
+dmrg_status dmrg_mpo_site_entries(const dmrg_mpo* mpo, int site, int64_t* n,
+                                  int32_t* xy, double* mats);
+void dmrg_mpo_free(dmrg_mpo* mpo);
+
+/* ---- MPS state ----------------------------------------------------------- */
+
+/* Number of FP64 values a random initial MPS of bond dimension M consumes. */
+dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n);
+/* Random initial MPS: sector dimensions from the fixed integer rule (full
+ * dimension min(left count, right count, M), apportioned to M by largest
+ * remainders, then made consistent between neighbouring bonds), blocks
+ * filled from `values` in fine-block order site by site, then made
+ * right-canonical on the GPU.  The center is left at the pair (0, 1) with
+ * its environments built. */
+dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M,
+                            const double* values, int64_t n_values, dmrg_mps** out);
+/* MPS from explicit site tensors (test hook).  sectors: for bonds 0..K in
+ * order, n_sectors[k] triples (N, 2S_z, dim), sorted.  site_values: the K
+ * site tensors concatenated, each in fine-block layout.  Sites < center are
+ * taken as left-canonical, sites > center+1 as right-canonical; the center
+ * pair is contracted into the two-site vector and environments are built. */
+dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n_sectors,
+                            const int32_t* sectors, const double* site_values,
+                            int center, dmrg_mps** out);
+/* Sectors of bond k: call with sectors == NULL to get *n; then 3n ints. */
+dmrg_status dmrg_mps_bond(const dmrg_mps* mps, int bond, int32_t* n, int32_t* sectors);
+/* Current center pair j (the two-site vector lives on sites j, j+1). */
+dmrg_status dmrg_mps_center(const dmrg_mps* mps, int* j);
+void dmrg_mps_free(dmrg_mps* mps);
+
+/* ---- sigma (Eq. Hpartition at the center bond) --------------------------- */
+
+/* Length of the two-site vector at the current center. */
+dmrg_status dmrg_psi_size(const dmrg_mps* mps, int64_t* n);
+/* Copy the current two-site vector to host memory (merged sector layout). */
+dmrg_status dmrg_psi_export(dmrg_ctx* ctx, const dmrg_mps* mps, double* psi_host);
+/* out = H_eff psi, with H_eff the Hamiltonian in the two-site basis of the
+ * current center: sum_y (sum_x L[x] (x) W_j[x,y]) (x) (sum_z W_j+1[y,z] (x) R[z])
+ * (Eq. Hpartition; blocked operators of Eq. prenormmatrix).  psi and out are
+ * DEVICE pointers of dmrg_psi_size FP64 values in merged sector layout; they
+ * must not overlap.  prec selects the contraction precision; inputs and
+ * outputs stay FP64.  Model flops of the call are added to *flops if it is
+ * not NULL. */
+dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
+                       double* out, dmrg_prec prec, double* flops);
+/* Diagonal of H_eff at the current center (DEVICE pointer, FP64). */
+dmrg_status dmrg_sigma_diag(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* out);
+/* Dense copy of environment operators (test hook): side 0 = left block of
+ * bond `bond`, 1 = right block.  Only the environments the current center
+ * uses are stored: left bonds <= center, right bonds >= center+2.
+ * out receives D[bond] x m x m FP64 (m = bond dimension), row-major. */
+dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bond,
+                            double* out);
+
+/* Test hook for the grouped GEMM kernel: C = alpha op(A) op(B) (+ C when
+ * accumulate != 0).  A, B, C are DEVICE FP64 pointers, row-major with leading
+ * dimensions lda, ldb, ldc; op(A) is m x k (ta != 0: A is stored k x m),
+ * op(B) is k x n (tb != 0: B is stored n x k).  With DMRG_FP32 / DMRG_BF16
+ * the operands are rounded to FP32 first and the result converted back. */
+dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
+                            double alpha, const double* A, int lda, const double* B, int ldb,
+                            double* C, int ldc, int accumulate);
+
+/* ---- sweeps (Sec. 2.1) ---------------------------------------------------- */
+
+typedef struct {
+    dmrg_prec prec;     /* sigma precision during Davidson */
+    double dav_tol;     /* stop when ||H x - theta x|| <= dav_tol */
+    int dav_max_iter;   /* max sigma applications per step */
+    int dav_max_space;  /* max Davidson subspace */
+    int dav_keep;       /* Ritz vectors kept at a restart */
+    double svd_cutoff;  /* drop singular values <= cutoff * sigma_max */
+    double refine_tol;  /* low-precision runs: switch to FP64 sigma once
+                           ||r|| <= refine_tol (0 = never) */
+} dmrg_sweep_opts;
+
+typedef struct {
+    double energy;          /* theta at the sweep's last step */
+    double discarded;       /* largest discarded weight of the sweep */
+    double seconds;         /* wall time of the sweep */
+    double sigma_flops;     /* model flops of all sigma calls */
+    double sigma_seconds;   /* GPU time of all sigma calls */
+    int64_t sigma_calls;
+    int64_t dav_iters;      /* Davidson iterations summed over steps */
+    int32_t max_bond;       /* largest bond dimension after the sweep */
+    int32_t n_steps;
+} dmrg_sweep_stat;
+
+/* Default options (FP64, tol 1e-9, 200 iterations, subspace 24, keep 4). */
+void dmrg_sweep_opts_default(dmrg_sweep_opts* o);
+/* Run n_sweeps sweeps (pairs 0..K-2 forward, then K-2..0 backward) with bond
+ * dimension M.  stats: caller-owned array of n_sweeps.  thetas, if not NULL,
+ * receives theta of every step of the last sweep (2(K-1) values). */
+dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
+                       int n_sweeps, const dmrg_sweep_opts* opts, dmrg_sweep_stat* stats,
+                       double* thetas);
+/* One two-site step at the current center (forward = 1 moves right). */
+dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
+                      const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat);
+/* <Psi|H|Psi>/<Psi|Psi> of the current state, accumulated in FP64
+ * (Eqs. transferop, energy_expect, at the center bond). */
+dmrg_status dmrg_energy(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* E);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRG_H */

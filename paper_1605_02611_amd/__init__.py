@@ -1,0 +1,8 @@
+"""MI355X-native two-site ab initio DMRG (arXiv 1605.02611 hot path).
+
+The compute lives in libdmrg.so (HIP kernels for gfx950 behind the C ABI of
+include/dmrg.h); this package only marshals arguments to it.
+"""
+
+from ._lib import DMRG_BF16, DMRG_FP32, DMRG_FP64, LIB_PATH, load  # noqa: F401
+from .api import Context, DmrgError, Mpo, Mps, default_opts  # noqa: F401

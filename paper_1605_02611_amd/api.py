@@ -1,0 +1,243 @@
+"""Python front end of the C ABI: argument marshalling and handle lifetime.
+
+PyTorch is used only for device memory (two-site vectors passed to
+``sigma``) and for the HIP stream the context orders its work on.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class DmrgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (L.STATUS.get(status, status), msg))
+        self.status = status
+
+
+def C_void(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _dptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _torch_sync():
+    """Order the library's stream after work torch has queued on its own."""
+    import torch
+    torch.cuda.current_stream().synchronize()
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        self.lib = L.load()
+        if stream is None and device >= 0:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream or None
+            except ImportError:
+                pass
+        h = C.c_void_p()
+        st = self.lib.dmrg_ctx_create(device, stream, C.byref(h))
+        if st != 0:
+            raise DmrgError(st, "dmrg_ctx_create failed")
+        self.h = h
+
+    def gemm(self, A, B, C, m, n, k, ta=False, tb=False, alpha=1.0, accumulate=False,
+             prec=L.DMRG_FP64):
+        """C[:m, :n] = alpha op(A) op(B) (+ C) on 2-D float64 device tensors (test hook)."""
+        assert C.shape[0] >= m and C.shape[1] >= n
+        assert A.shape == ((k, A.shape[1]) if ta else (m, A.shape[1]))
+        assert B.shape == ((n, B.shape[1]) if tb else (k, B.shape[1]))
+        _torch_sync()
+        self.check(self.lib.dmrg_debug_gemm(
+            self.h, prec, m, n, k, int(ta), int(tb), alpha, C_void(A), A.stride(0), C_void(B),
+            B.stride(0), C_void(C), C.stride(0), int(accumulate)))
+
+    def check(self, st):
+        if st != 0:
+            raise DmrgError(st, self.lib.dmrg_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dmrg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mpo:
+    """Normal/complementary MPO of H (dmrg_build_mpo)."""
+
+    def __init__(self, ctx, h, v, n_elec, two_sz=None, switch_bond=-1):
+        self.ctx, self.lib = ctx, ctx.lib
+        h = np.asarray(h, dtype=np.float64)
+        K = h.shape[0]
+        self.K = K
+        if two_sz is None:
+            two_sz = n_elec % 2
+        hh, hp = _dptr(h)
+        vv, vp = _dptr(v)
+        opts = L.MpoOpts(switch_bond, 0.0)
+        out = C.c_void_p()
+        ctx.check(self.lib.dmrg_build_mpo(ctx.h, hp, vp, K, n_elec, two_sz, C.byref(opts),
+                                          C.byref(out)))
+        self.h = out
+        self.n_elec, self.two_sz = n_elec, two_sz
+
+    def bond_dims(self):
+        D = np.zeros(self.K + 1, dtype=np.int32)
+        self.ctx.check(self.lib.dmrg_mpo_bond_dims(self.h, D.ctypes.data_as(C.POINTER(C.c_int32))))
+        return D
+
+    def channels(self, k):
+        D = self.bond_dims()[k]
+        lab = np.zeros(3 * D, dtype=np.int32)
+        self.ctx.check(self.lib.dmrg_mpo_channels(self.h, k, lab.ctypes.data_as(C.POINTER(C.c_int32))))
+        return lab.reshape(D, 3)
+
+    def site_entries(self, j):
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_mpo_site_entries(self.h, j, C.byref(n), None, None))
+        xy = np.zeros(2 * n.value, dtype=np.int32)
+        mats = np.zeros(16 * n.value)
+        self.ctx.check(self.lib.dmrg_mpo_site_entries(
+            self.h, j, C.byref(n), xy.ctypes.data_as(C.POINTER(C.c_int32)),
+            mats.ctypes.data_as(C.POINTER(C.c_double))))
+        return xy.reshape(-1, 2), mats.reshape(-1, 4, 4)
+
+    def n_values(self, M):
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_mps_n_values(self.h, M, C.byref(n)))
+        return n.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.dmrg_mpo_free(self.h)
+            self.h = None
+
+
+def default_opts(**kw):
+    o = L.SweepOpts()
+    L.load().dmrg_sweep_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Mps:
+    """MPS state with environments and the two-site center."""
+
+    def __init__(self, ctx, mpo, handle):
+        self.ctx, self.lib, self.mpo, self.h = ctx, ctx.lib, mpo, handle
+
+    @classmethod
+    def random(cls, ctx, mpo, M, values):
+        vv, vp = _dptr(values)
+        out = C.c_void_p()
+        ctx.check(ctx.lib.dmrg_mps_random(ctx.h, mpo.h, M, vp, len(vv), C.byref(out)))
+        return cls(ctx, mpo, out)
+
+    @classmethod
+    def from_tensors(cls, ctx, mpo, bonds, site_values, center):
+        """bonds: list over k of [(N, 2Sz, dim), ...]; site_values: flat FP64."""
+        ns = np.array([len(b) for b in bonds], dtype=np.int32)
+        secs = np.array([x for b in bonds for t in b for x in t], dtype=np.int32)
+        nn, np_ = _iptr(ns)
+        ss, sp = _iptr(secs)
+        vv, vp = _dptr(site_values)
+        out = C.c_void_p()
+        ctx.check(ctx.lib.dmrg_mps_import(ctx.h, mpo.h, np_, sp, vp, center, C.byref(out)))
+        return cls(ctx, mpo, out)
+
+    def bond(self, k):
+        n = C.c_int32()
+        self.ctx.check(self.lib.dmrg_mps_bond(self.h, k, C.byref(n), None))
+        out = np.zeros(3 * n.value, dtype=np.int32)
+        self.ctx.check(self.lib.dmrg_mps_bond(self.h, k, C.byref(n),
+                                              out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return [tuple(int(v) for v in r) for r in out.reshape(-1, 3)]
+
+    def center(self):
+        j = C.c_int()
+        self.ctx.check(self.lib.dmrg_mps_center(self.h, C.byref(j)))
+        return j.value
+
+    def psi_size(self):
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_psi_size(self.h, C.byref(n)))
+        return n.value
+
+    def psi(self):
+        out = np.zeros(self.psi_size())
+        self.ctx.check(self.lib.dmrg_psi_export(self.ctx.h, self.h,
+                                                out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def sigma(self, x_dev, y_dev, prec=L.DMRG_FP64):
+        """y = H_eff x on device tensors (torch, float64, contiguous)."""
+        n = self.psi_size()
+        assert x_dev.numel() == n and y_dev.numel() == n
+        assert x_dev.dtype == y_dev.dtype and str(x_dev.dtype) == "torch.float64"
+        f = C.c_double(0.0)
+        _torch_sync()
+        self.ctx.check(self.lib.dmrg_sigma(self.ctx.h, self.h, self.mpo.h, C.c_void_p(x_dev.data_ptr()),
+                                           C.c_void_p(y_dev.data_ptr()), prec, C.byref(f)))
+        return f.value
+
+    def diag(self, y_dev):
+        assert y_dev.numel() == self.psi_size()
+        _torch_sync()
+        self.ctx.check(self.lib.dmrg_sigma_diag(self.ctx.h, self.h, self.mpo.h,
+                                                C.c_void_p(y_dev.data_ptr())))
+
+    def env(self, side, bond):
+        D = int(self.mpo.bond_dims()[bond])
+        m = sum(d for _, _, d in self.bond(bond))
+        out = np.zeros(D * m * m)
+        self.ctx.check(self.lib.dmrg_env_export(self.ctx.h, self.h, side, bond,
+                                                out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(D, m, m)
+
+    def sweep(self, M, n_sweeps, opts=None):
+        opts = opts or default_opts()
+        st = (L.SweepStat * max(1, n_sweeps))()
+        th = np.zeros(2 * (self.mpo.K - 1))
+        self.ctx.check(self.lib.dmrg_sweep(self.ctx.h, self.h, self.mpo.h, M, n_sweeps,
+                                           C.byref(opts), st, th.ctypes.data_as(C.POINTER(C.c_double))))
+        stats = [{f: getattr(st[i], f) for f, _ in L.SweepStat._fields_} for i in range(n_sweeps)]
+        return stats, th
+
+    def step(self, M, forward, opts=None):
+        opts = opts or default_opts()
+        st = L.SweepStat()
+        th = C.c_double()
+        self.ctx.check(self.lib.dmrg_step(self.ctx.h, self.h, self.mpo.h, M, int(bool(forward)),
+                                          C.byref(opts), C.byref(th), C.byref(st)))
+        return th.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
+
+    def energy(self):
+        e = C.c_double()
+        self.ctx.check(self.lib.dmrg_energy(self.ctx.h, self.h, self.mpo.h, C.byref(e)))
+        return e.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.dmrg_mps_free(self.h)
+            self.h = None

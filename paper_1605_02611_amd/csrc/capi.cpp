@@ -1,0 +1,461 @@
+// C ABI of the DMRG library (declared in include/dmrg.h).  Every entry point
+// catches internal errors, stores the message on the context and returns a
+// status code.
+#include <chrono>
+#include <cstring>
+
+#include "../../include/dmrg.h"
+#include "engine.h"
+
+using namespace dmrg;
+
+struct dmrg_ctx {
+    Ctx c;
+};
+struct dmrg_mpo {
+    std::unique_ptr<MPO> m;
+};
+struct dmrg_mps {
+    std::unique_ptr<State> st;
+};
+
+namespace dmrg {
+int64_t initial_value_count(const MPO& m, int M);
+}
+
+namespace {
+
+template <class F>
+dmrg_status guard(dmrg_ctx* ctx, F&& f) {
+    try {
+        if (ctx) ctx->c.err.clear();
+        f();
+        return DMRG_OK;
+    } catch (const Error& e) {
+        if (ctx) ctx->c.err = e.what();
+        return dmrg_status(e.code);
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->c.err = "host allocation failed";
+        return DMRG_E_NOMEM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->c.err = e.what();
+        return DMRG_E_INVAL;
+    }
+}
+
+SweepOpts to_opts(const dmrg_sweep_opts* o) {
+    SweepOpts r;
+    if (!o) return r;
+    require(o->prec >= DMRG_FP64 && o->prec <= DMRG_BF16, "unknown precision");
+    require(o->dav_tol > 0 && o->dav_max_iter >= 1 && o->dav_max_space >= 2 &&
+                o->dav_max_space <= 40 && o->dav_keep >= 1 && o->dav_keep < o->dav_max_space,
+            "invalid Davidson options");
+    require(o->svd_cutoff >= 0, "invalid SVD cutoff");
+    r.prec = Prec(o->prec);
+    r.dav_tol = o->dav_tol;
+    r.dav_max_iter = o->dav_max_iter;
+    r.dav_max_space = o->dav_max_space;
+    r.dav_keep = o->dav_keep;
+    r.svd_cutoff = o->svd_cutoff;
+    r.refine_tol = o->refine_tol;
+    return r;
+}
+
+void use_device(const Ctx& c) {
+    require(c.device >= 0, "host-only context (device -1) cannot run GPU work", E_STATE);
+    DMRG_HIP(hipSetDevice(c.device));
+}
+
+}  // namespace
+
+extern "C" {
+
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
+    if (!out) return DMRG_E_INVAL;
+    auto* ctx = new (std::nothrow) dmrg_ctx();
+    if (!ctx) return DMRG_E_NOMEM;
+    dmrg_status st = guard(ctx, [&] {
+        if (device == -1) {  // host-only context: MPO construction and queries
+            ctx->c.device = -1;
+            return;
+        }
+        int n = 0;
+        DMRG_HIP(hipGetDeviceCount(&n));
+        require(device >= 0 && device < n, "no such HIP device");
+        ctx->c.device = device;
+        DMRG_HIP(hipSetDevice(device));
+        if (hip_stream) {
+            ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            DMRG_HIP(hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking));
+            ctx->c.own_stream = true;
+        }
+        // keep freed stream-ordered memory cached in the pool
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        DMRG_HIP(hipEventCreate(&ctx->c.ev0));
+        DMRG_HIP(hipEventCreate(&ctx->c.ev1));
+        if (rocblas_create_handle(&ctx->c.blas) != rocblas_status_success)
+            throw Error(E_HIP, "rocblas_create_handle failed");
+        if (rocblas_set_stream(ctx->c.blas, ctx->c.stream) != rocblas_status_success)
+            throw Error(E_HIP, "rocblas_set_stream failed");
+    });
+    if (st != DMRG_OK) {
+        dmrg_ctx_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return DMRG_OK;
+}
+
+void dmrg_ctx_destroy(dmrg_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->c.device < 0) {
+        delete ctx;
+        return;
+    }
+    (void)hipSetDevice(ctx->c.device);
+    if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.blas) rocblas_destroy_handle(ctx->c.blas);
+    if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
+    if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
+    if (ctx->c.own_stream && ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+}
+
+const char* dmrg_last_error(const dmrg_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K, int n_elec,
+                           int two_sz, const dmrg_mpo_opts* opts, dmrg_mpo** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(h && v && out, "null argument");
+        int sw = -1;
+        if (opts) {
+            require(opts->compress_tol == 0.0, "MPO compression is not available (compress_tol must be 0)");
+            require(opts->switch_bond >= -1 && opts->switch_bond <= K, "switch_bond out of range");
+            sw = opts->switch_bond;
+        }
+        auto m = build_mpo(h, v, K, n_elec, two_sz, sw);
+        auto* r = new dmrg_mpo();
+        r->m = std::move(m);
+        *out = r;
+    });
+}
+
+dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D) {
+    if (!mpo || !D) return DMRG_E_INVAL;
+    for (size_t k = 0; k < mpo->m->chans.size(); ++k) D[k] = int32_t(mpo->m->chans[k].size());
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_mpo_channels(const dmrg_mpo* mpo, int bond, int32_t* labels) {
+    if (!mpo || !labels || bond < 0 || bond > mpo->m->K) return DMRG_E_INVAL;
+    const auto& ch = mpo->m->chans[bond];
+    for (size_t i = 0; i < ch.size(); ++i) {
+        labels[3 * i] = ch[i].kind;
+        labels[3 * i + 1] = ch[i].p;
+        labels[3 * i + 2] = ch[i].q;
+    }
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_mpo_site_entries(const dmrg_mpo* mpo, int site, int64_t* n, int32_t* xy,
+                                  double* mats) {
+    if (!mpo || !n || site < 0 || site >= mpo->m->K) return DMRG_E_INVAL;
+    const auto& W = mpo->m->W[site];
+    if (!xy) {
+        *n = int64_t(W.size());
+        return DMRG_OK;
+    }
+    if (*n < int64_t(W.size()) || !mats) return DMRG_E_INVAL;
+    for (size_t i = 0; i < W.size(); ++i) {
+        xy[2 * i] = W[i].first.first;
+        xy[2 * i + 1] = W[i].first.second;
+        std::memcpy(mats + 16 * i, W[i].second.a, 16 * sizeof(double));
+    }
+    *n = int64_t(W.size());
+    return DMRG_OK;
+}
+
+void dmrg_mpo_free(dmrg_mpo* mpo) { delete mpo; }
+
+dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n) {
+    if (!mpo || !n || M < 1) return DMRG_E_INVAL;
+    try {
+        *n = initial_value_count(*mpo->m, M);
+    } catch (...) {
+        return DMRG_E_INVAL;
+    }
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M, const double* values,
+                            int64_t n_values, dmrg_mps** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mpo && values && out, "null argument");
+        use_device(ctx->c);
+        require(mpo->m->K >= 2, "two-site DMRG needs K >= 2");
+        auto st = std::make_unique<State>(&ctx->c, mpo->m.get());
+        st->init_random(M, values, n_values);
+        auto* r = new dmrg_mps();
+        r->st = std::move(st);
+        *out = r;
+    });
+}
+
+dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n_sectors,
+                            const int32_t* sectors, const double* site_values, int center,
+                            dmrg_mps** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mpo && n_sectors && sectors && site_values && out, "null argument");
+        use_device(ctx->c);
+        const int K = mpo->m->K;
+        require(K >= 2, "two-site DMRG needs K >= 2");
+        std::vector<std::vector<std::pair<QN, int>>> b(K + 1);
+        int64_t p = 0;
+        for (int k = 0; k <= K; ++k) {
+            require(n_sectors[k] >= 1, "every bond needs a sector");
+            for (int i = 0; i < n_sectors[k]; ++i, p += 3) {
+                require(sectors[p + 2] >= 1, "sector dimensions must be >= 1");
+                b[k].push_back({QN{sectors[p], sectors[p + 1]}, sectors[p + 2]});
+            }
+        }
+        auto st = std::make_unique<State>(&ctx->c, mpo->m.get());
+        st->import_tensors(b, site_values, center);
+        auto* r = new dmrg_mps();
+        r->st = std::move(st);
+        *out = r;
+    });
+}
+
+dmrg_status dmrg_mps_bond(const dmrg_mps* mps, int bond, int32_t* n, int32_t* sectors) {
+    if (!mps || !n) return DMRG_E_INVAL;
+    const auto& bonds = mps->st->bonds;
+    if (bond < 0 || bond >= int(bonds.size())) return DMRG_E_INVAL;
+    const Bond& b = bonds[bond];
+    if (!sectors) {
+        *n = int32_t(b.q.size());
+        return DMRG_OK;
+    }
+    if (*n < int32_t(b.q.size())) return DMRG_E_INVAL;
+    for (size_t i = 0; i < b.q.size(); ++i) {
+        sectors[3 * i] = b.q[i].n;
+        sectors[3 * i + 1] = b.q[i].sz;
+        sectors[3 * i + 2] = b.dim[i];
+    }
+    *n = int32_t(b.q.size());
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_mps_center(const dmrg_mps* mps, int* j) {
+    if (!mps || !j) return DMRG_E_INVAL;
+    *j = mps->st->center;
+    return DMRG_OK;
+}
+
+void dmrg_mps_free(dmrg_mps* mps) {
+    if (!mps) return;
+    if (mps->st && mps->st->ctx) {
+        (void)hipSetDevice(mps->st->ctx->device);
+        (void)hipStreamSynchronize(mps->st->ctx->stream);
+    }
+    delete mps;
+}
+
+dmrg_status dmrg_psi_size(const dmrg_mps* mps, int64_t* n) {
+    if (!mps || !n) return DMRG_E_INVAL;
+    *n = mps->st->ts.n;
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_psi_export(dmrg_ctx* ctx, const dmrg_mps* mps, double* psi_host) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && psi_host, "null argument");
+        use_device(ctx->c);
+        const State& st = *mps->st;
+        DMRG_HIP(hipMemcpyAsync(psi_host, st.psi.p, st.ts.n * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
+                       double* out, dmrg_prec prec, double* flops) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo && psi && out, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
+        const int64_t n = mps->st->ts.n;
+        require(psi + n <= out || out + n <= psi, "psi and out overlap");
+        use_device(ctx->c);
+        double f = 0, sec = 0;
+        mps->st->sigma(psi, out, Prec(prec), &f, &sec);
+        if (flops) *flops += f;
+    });
+}
+
+dmrg_status dmrg_sigma_diag(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo && out, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        use_device(ctx->c);
+        State& st = *mps->st;
+        st.build_diag();
+        launch_copy(out, st.diag.as<double>(), st.ts.n, ctx->c.stream);
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bond, double* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && out && (side == 0 || side == 1), "bad argument");
+        use_device(ctx->c);
+        std::vector<double> h;
+        mps->st->env_dense(side, bond, h);
+        std::memcpy(out, h.data(), h.size() * sizeof(double));
+    });
+}
+
+dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
+                            double alpha, const double* A, int lda, const double* B, int ldb,
+                            double* C, int ldc, int accumulate) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
+        require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
+        use_device(ctx->c);
+        hipStream_t s = ctx->c.stream;
+        const int64_t na = ta ? int64_t(k - 1) * lda + m : int64_t(m - 1) * lda + k;
+        const int64_t nb = tb ? int64_t(n - 1) * ldb + k : int64_t(k - 1) * ldb + n;
+        const int64_t nc = int64_t(m - 1) * ldc + n;
+        GemmList L;
+        std::vector<UTerm> terms = {{0, 0, lda, ta != 0, 1, 0, ldb, tb != 0, k, alpha, true}};
+        add_unit(L, 2, 0, ldc, m, n, accumulate ? 1 : 0, terms);
+        int64_t sz[kMaxBufs] = {na, nb, nc};
+        validate_list(L, sz);
+        L.upload(s);
+        Bases b{};
+        DevBuf a32, b32, c32;
+        if (prec == DMRG_FP64) {
+            b.p[0] = const_cast<double*>(A);
+            b.p[1] = const_cast<double*>(B);
+            b.p[2] = C;
+        } else {
+            a32.alloc(na * sizeof(float), s);
+            b32.alloc(nb * sizeof(float), s);
+            c32.alloc(nc * sizeof(float), s);
+            launch_to_f32(a32.as<float>(), A, na, s);
+            launch_to_f32(b32.as<float>(), B, nb, s);
+            launch_to_f32(c32.as<float>(), C, nc, s);
+            b.p[0] = a32.p;
+            b.p[1] = b32.p;
+            b.p[2] = c32.p;
+        }
+        L.launch(Prec(prec), b, s);
+        if (prec != DMRG_FP64) launch_f32_to_f64(C, c32.as<float>(), nc, s);
+        DMRG_HIP(hipStreamSynchronize(s));
+    });
+}
+
+void dmrg_sweep_opts_default(dmrg_sweep_opts* o) {
+    if (!o) return;
+    o->prec = DMRG_FP64;
+    o->dav_tol = 1e-9;
+    o->dav_max_iter = 200;
+    o->dav_max_space = 24;
+    o->dav_keep = 4;
+    o->svd_cutoff = 1e-12;
+    o->refine_tol = 0.0;
+}
+
+dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
+                      const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        require(M >= 1, "M must be >= 1");
+        use_device(ctx->c);
+        SweepOpts o = to_opts(opts);
+        StepStats s;
+        auto t0 = std::chrono::steady_clock::now();
+        double th = mps->st->step(M, forward != 0, o, s);
+        auto t1 = std::chrono::steady_clock::now();
+        if (theta) *theta = th;
+        if (stat) {
+            stat->energy = th;
+            stat->discarded = s.discarded;
+            stat->seconds = std::chrono::duration<double>(t1 - t0).count();
+            stat->sigma_flops = s.sigma_flops;
+            stat->sigma_seconds = s.sigma_seconds;
+            stat->sigma_calls = s.sigma_calls;
+            stat->dav_iters = s.dav_iters;
+            stat->max_bond = s.max_bond;
+            stat->n_steps = 1;
+        }
+    });
+}
+
+dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int n_sweeps,
+                       const dmrg_sweep_opts* opts, dmrg_sweep_stat* stats, double* thetas) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        require(M >= 1 && n_sweeps >= 0, "bad M or n_sweeps");
+        use_device(ctx->c);
+        State& st = *mps->st;
+        const int K = mpo->m->K;
+        require(st.center == 0, "a sweep starts with the center at the pair (0, 1)", E_STATE);
+        SweepOpts o = to_opts(opts);
+        for (int sw = 0; sw < n_sweeps; ++sw) {
+            StepStats s;
+            auto t0 = std::chrono::steady_clock::now();
+            double th = 0;
+            int step = 0;
+            for (int j = 0; j <= K - 2; ++j, ++step) {
+                th = st.step(M, true, o, s);
+                if (thetas && sw == n_sweeps - 1) thetas[step] = th;
+            }
+            for (int j = K - 2; j >= 0; --j, ++step) {
+                th = st.step(M, false, o, s);
+                if (thetas && sw == n_sweeps - 1) thetas[step] = th;
+            }
+            auto t1 = std::chrono::steady_clock::now();
+            if (stats) {
+                stats[sw].energy = th;
+                stats[sw].discarded = s.discarded;
+                stats[sw].seconds = std::chrono::duration<double>(t1 - t0).count();
+                stats[sw].sigma_flops = s.sigma_flops;
+                stats[sw].sigma_seconds = s.sigma_seconds;
+                stats[sw].sigma_calls = s.sigma_calls;
+                stats[sw].dav_iters = s.dav_iters;
+                stats[sw].max_bond = s.max_bond;
+                stats[sw].n_steps = step;
+            }
+        }
+    });
+}
+
+dmrg_status dmrg_energy(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* E) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo && E, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        use_device(ctx->c);
+        *E = mps->st->energy();
+    });
+}
+
+}  // extern "C"

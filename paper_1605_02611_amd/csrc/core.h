@@ -1,0 +1,252 @@
+// Internal types of the DMRG library: quantum numbers, bonds, operator
+// layouts, the MPO, device buffers and the kernel launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace dmrg {
+
+// ---------------------------------------------------------------------------
+// errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+enum { E_INVAL = 1, E_NOMEM = 2, E_HIP = 3, E_NOCONV = 4, E_NUMERIC = 5, E_STATE = 6 };
+
+#define DMRG_HIP(call)                                                             \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            throw ::dmrg::Error(e_ == hipErrorOutOfMemory ? ::dmrg::E_NOMEM        \
+                                                          : ::dmrg::E_HIP,         \
+                                std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline void require(bool ok, const std::string& msg, int code = E_INVAL) {
+    if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------------------------
+// quantum numbers (N, 2 S_z), lexicographic order
+struct QN {
+    int n = 0, sz = 0;
+    bool operator<(const QN& o) const { return n < o.n || (n == o.n && sz < o.sz); }
+    bool operator==(const QN& o) const { return n == o.n && sz == o.sz; }
+    bool operator!=(const QN& o) const { return !(*this == o); }
+    QN operator+(const QN& o) const { return {n + o.n, sz + o.sz}; }
+    QN operator-(const QN& o) const { return {n - o.n, sz - o.sz}; }
+};
+// local site states s = 0 |0>, 1 |up>, 2 |dn>, 3 |updn>
+constexpr QN kSiteQN[4] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
+// sys fine rows of a sector ordered by Q_l = q - q_s ascending
+constexpr int kSysOrder[4] = {3, 1, 2, 0};
+
+// ---------------------------------------------------------------------------
+// a bond: sorted sectors with dimensions
+struct Bond {
+    std::vector<QN> q;
+    std::vector<int> dim;
+    std::vector<int> off;  // state offset of each sector
+    int total = 0;
+    std::map<QN, int> index;
+    void finalize() {
+        off.assign(q.size(), 0);
+        index.clear();
+        total = 0;
+        for (size_t i = 0; i < q.size(); ++i) {
+            off[i] = total;
+            total += dim[i];
+            index[q[i]] = int(i);
+        }
+    }
+    int find(const QN& x) const {
+        auto it = index.find(x);
+        return it == index.end() ? -1 : it->second;
+    }
+    int dim_of(const QN& x) const {
+        int i = find(x);
+        return i < 0 ? 0 : dim[i];
+    }
+};
+
+// Layout of a block-sparse operator on a bond with quantum-number shift dq:
+// one dense block (q_in + dq <- q_in) per sector pair, row-major.
+struct OpBlock {
+    int in, out;   // sector indices
+    int rows, cols;
+    int64_t off;   // element offset inside the operator
+};
+struct OpLayout {
+    QN dq;
+    std::vector<OpBlock> blocks;
+    std::vector<int> by_in;  // block index for each input sector, -1 if none
+    int64_t size = 0;
+};
+OpLayout make_layout(const Bond& b, QN dq);
+
+// ---------------------------------------------------------------------------
+// 4x4 site operators (row = output state)
+struct Mat4 {
+    double a[16] = {0};
+    double& operator()(int i, int j) { return a[i * 4 + j]; }
+    double operator()(int i, int j) const { return a[i * 4 + j]; }
+    bool zero() const {
+        for (double x : a)
+            if (x != 0.0) return false;
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// MPO: channels per bond and sparse site tensors
+enum ChanKind { CK_I = 0, CK_H, CK_Cd, CK_C, CK_SL, CK_SLd, CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q };
+struct Chan {
+    int kind, p, q;
+};
+QN chan_qn(const Chan& c);
+bool chan_odd(const Chan& c);
+
+// one nonzero element of W[site][x][y] between local states (sp <- s)
+struct FineW {
+    int x, y;
+    int8_t sp, s;
+    double c;
+};
+
+struct MPO {
+    int K = 0, n_elec = 0, two_sz = 0, switch_bond = 0;
+    std::vector<std::vector<Chan>> chans;        // bonds 0..K
+    std::vector<std::vector<QN>> chan_dq;        // per bond
+    std::vector<std::vector<std::pair<std::pair<int, int>, Mat4>>> W;  // per site
+    std::vector<std::vector<FineW>> fine;        // per site, sorted by (y, sp, s, x)
+    QN target() const { return {n_elec, two_sz}; }
+};
+std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
+                               int switch_bond);
+
+// ---------------------------------------------------------------------------
+// kernels (kernels.hip)
+
+// One output tile of a grouped GEMM: C[m x n] (+)= sum_l alpha_l op(A_l) op(B_l).
+// Operands are addressed as (buffer id, element offset) so that one task list
+// serves the FP64 buffers and their FP32 copies alike.
+struct GemmTask {
+    int64_t c_off;
+    int c_buf, ldc, m, n;  // m, n <= kTile
+    int accumulate;
+    int l_begin, l_end;
+};
+struct GemmTerm {
+    int64_t a_off, b_off;  // origin of the m x k slice of A and k x n slice of B
+    int a_buf, b_buf;
+    int k, lda, ldb;
+    int flags;  // bit 0: A stored transposed (A[r][kk] = a[kk*lda + r])
+                // bit 1: B stored transposed (B[kk][c] = b[c*ldb + kk])
+    double alpha;
+};
+enum { GT_TA = 1, GT_TB = 2 };
+constexpr int kTile = 64;
+constexpr int kMaxBufs = 8;
+struct Bases {
+    void* p[kMaxBufs];
+};
+
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                 const Bases& bases, hipStream_t s);
+
+// Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]
+struct SumItem {
+    double* out;
+    int64_t begin, end;  // element range of this work item
+    int t_begin, t_end;
+};
+struct SumTerm {
+    const double* src;
+    double coef;
+};
+void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s);
+
+// Davidson / vector kernels (FP64)
+constexpr int kDotBlocks = 512;
+void launch_multidot(const double* V, int64_t stride, int k, const double* w, int64_t n,
+                     double* partial, hipStream_t s);  // partial[kDotBlocks * k]
+void launch_reduce_partials(const double* partial, int k, double* out, hipStream_t s);
+struct Coefs {
+    double c[40];
+};
+void launch_lincomb(double* out, const double* V, int64_t stride, int k, Coefs c, int64_t n,
+                    hipStream_t s);
+void launch_axpy_many(double* t, const double* V, int64_t stride, int k, Coefs c, int64_t n,
+                      hipStream_t s);  // t -= sum c_i V_i
+void launch_precond(double* t, const double* r, const double* diag, double theta, int64_t n,
+                    hipStream_t s);
+void launch_residual(double* r, const double* wx, const double* x, double theta, int64_t n,
+                     hipStream_t s);
+void launch_scale(double* x, double a, int64_t n, hipStream_t s);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+void launch_fill(double* dst, double v, int64_t n, hipStream_t s);
+void launch_to_f32(float* dst, const double* src, int64_t n, hipStream_t s);
+void launch_to_bf16(uint16_t* dst, const double* src, int64_t n, hipStream_t s);
+void launch_f32_to_f64(double* dst, const float* src, int64_t n, hipStream_t s);
+// out[i] = sum_s part[s * n + i] (+ out[i] if accumulate)
+void launch_sum_slices(double* out, const double* part, int n_slices, int64_t n, int accumulate,
+                       hipStream_t s);
+void launch_sum_slices_f32(float* out, const float* part, int n_slices, int64_t n,
+                           int accumulate, hipStream_t s);
+// strided diagonal gather: out[i] = src[off_i + i*(ld+1)] for a list of blocks
+struct DiagItem {
+    const double* src;
+    int ld;
+    int len;
+    double* dst;
+};
+void launch_diag_gather(const DiagItem* items, int n_items, hipStream_t s);
+// gather columns: dst[r*dld + c] = src[r*sld + col[c]] (c < ncol, r < nrow), times scale[c]
+void launch_gather_cols(double* dst, int dld, const double* src, int sld, const int* cols,
+                        const double* scale, int nrow, int ncol, hipStream_t s);
+void launch_gather_rows(double* dst, int dld, const double* src, int sld, const int* rows,
+                        const double* scale, int nrow, int ncol, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device memory: stream-ordered allocations
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t b, hipStream_t st) { alloc(b, st); }
+    void alloc(size_t b, hipStream_t st);
+    void free();
+    ~DevBuf() { free(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            free();
+            p = o.p;
+            bytes = o.bytes;
+            s = o.s;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+}  // namespace dmrg

@@ -1,0 +1,1598 @@
+// DMRG engine (Chan et al., Secs. 2.1-2.5): renormalized operators as
+// block-sparse matrices on the GPU, blocking (Eq. prenormmatrix), the
+// two-site sigma vector (Eq. Hpartition), Davidson solving, sector-wise SVD
+// decimation (Eqs. blockdecimation, MPSCform) and the environment update
+// (Eq. prenormdec).
+#include "engine.h"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <set>
+
+namespace dmrg {
+
+// ---------------------------------------------------------------------------
+// spaces and layouts
+
+Space sys_space(const Bond& left, QN q) {
+    Space sp;
+    sp.q = q;
+    for (int s : kSysOrder) {
+        int i = left.find(q - kSiteQN[s]);
+        if (i < 0) continue;
+        sp.seg_of[s] = int(sp.segs.size());
+        sp.segs.push_back({s, i, sp.dim, left.dim[i]});
+        sp.dim += left.dim[i];
+    }
+    return sp;
+}
+
+Space env_space(const Bond& right, QN q) {
+    Space sp;
+    sp.q = q;
+    for (int t = 0; t < 4; ++t) {
+        int i = right.find(q + kSiteQN[t]);
+        if (i < 0) continue;
+        sp.seg_of[t] = int(sp.segs.size());
+        sp.segs.push_back({t, i, sp.dim, right.dim[i]});
+        sp.dim += right.dim[i];
+    }
+    return sp;
+}
+
+TwoSite make_two_site(const Bond& left, const Bond& right) {
+    std::set<QN> cand;
+    for (const QN& ql : left.q)
+        for (int s = 0; s < 4; ++s) cand.insert(ql + kSiteQN[s]);
+    TwoSite ts;
+    for (const QN& q : cand) {
+        Space a = sys_space(left, q), b = env_space(right, q);
+        if (a.dim == 0 || b.dim == 0) continue;
+        ts.idx[q] = int(ts.q.size());
+        ts.q.push_back(q);
+        ts.off.push_back(ts.n);
+        ts.n += int64_t(a.dim) * b.dim;
+        ts.sys.push_back(std::move(a));
+        ts.env.push_back(std::move(b));
+    }
+    return ts;
+}
+
+// ---------------------------------------------------------------------------
+// grouped GEMM task lists
+
+void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
+              const std::vector<UTerm>& terms, int splits, int64_t slice) {
+    if (m <= 0 || n <= 0) return;
+    int64_t ktot = 0;
+    for (const UTerm& u : terms) {
+        const double f = 2.0 * m * n * u.k;
+        L.flops += f;
+        if (u.model) L.model_flops += f;
+        ktot += u.k;
+    }
+    if (splits < 1) splits = 1;
+    std::vector<size_t> cut(splits + 1, terms.size());
+    cut[0] = 0;
+    {
+        int64_t cum = 0;
+        int part = 1;
+        for (size_t i = 0; i < terms.size() && part < splits; ++i) {
+            cum += terms[i].k;
+            while (part < splits && cum * splits >= ktot * part) cut[part++] = i + 1;
+        }
+        for (; part < splits; ++part) cut[part] = terms.size();
+    }
+    for (int r0 = 0; r0 < m; r0 += kTile)
+        for (int c0 = 0; c0 < n; c0 += kTile) {
+            const int tm = std::min(kTile, m - r0), tn = std::min(kTile, n - c0);
+            for (int sp = 0; sp < splits; ++sp) {
+                GemmTask tk;
+                tk.c_buf = c_buf;
+                tk.c_off = c_off + int64_t(sp) * slice + int64_t(r0) * ldc + c0;
+                tk.ldc = ldc;
+                tk.m = tm;
+                tk.n = tn;
+                tk.accumulate = accumulate;
+                tk.l_begin = int(L.terms.size());
+                for (size_t i = cut[sp]; i < cut[sp + 1]; ++i) {
+                    const UTerm& u = terms[i];
+                    GemmTerm g;
+                    g.a_buf = u.a_buf;
+                    g.a_off = u.ta ? u.a_off + r0 : u.a_off + int64_t(r0) * u.lda;
+                    g.b_buf = u.b_buf;
+                    g.b_off = u.tb ? u.b_off + int64_t(c0) * u.ldb : u.b_off + c0;
+                    g.k = u.k;
+                    g.lda = u.lda;
+                    g.ldb = u.ldb;
+                    g.flags = (u.ta ? GT_TA : 0) | (u.tb ? GT_TB : 0);
+                    g.alpha = u.alpha;
+                    L.terms.push_back(g);
+                }
+                tk.l_end = int(L.terms.size());
+                L.tasks.push_back(tk);
+            }
+        }
+}
+
+void GemmList::upload(hipStream_t s) {
+    dtasks.alloc(std::max<size_t>(1, tasks.size()) * sizeof(GemmTask), s);
+    dterms.alloc(std::max<size_t>(1, terms.size()) * sizeof(GemmTerm), s);
+    if (!tasks.empty())
+        DMRG_HIP(hipMemcpyAsync(dtasks.p, tasks.data(), tasks.size() * sizeof(GemmTask),
+                                hipMemcpyHostToDevice, s));
+    if (!terms.empty())
+        DMRG_HIP(hipMemcpyAsync(dterms.p, terms.data(), terms.size() * sizeof(GemmTerm),
+                                hipMemcpyHostToDevice, s));
+}
+
+void GemmList::launch(Prec p, const Bases& b, hipStream_t s) const {
+    launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
+}
+
+void validate_list(const GemmList& L, const int64_t* sizes) {
+    auto bad = [](const char* what) { throw Error(E_STATE, std::string("internal: task list ") + what + " out of bounds"); };
+    for (const GemmTask& t : L.tasks) {
+        if (t.c_buf < 0 || t.c_buf >= kMaxBufs || t.m < 1 || t.n < 1 || t.m > kTile || t.n > kTile) bad("task shape");
+        if (t.c_off < 0 || t.c_off + int64_t(t.m - 1) * t.ldc + t.n > sizes[t.c_buf]) bad("output");
+        if (t.l_begin < 0 || t.l_end < t.l_begin || t.l_end > int(L.terms.size())) bad("term range");
+        for (int l = t.l_begin; l < t.l_end; ++l) {
+            const GemmTerm& g = L.terms[l];
+            if (g.a_buf < 0 || g.a_buf >= kMaxBufs || g.b_buf < 0 || g.b_buf >= kMaxBufs || g.k < 1) bad("term shape");
+            const int64_t ea = (g.flags & GT_TA) ? g.a_off + int64_t(g.k - 1) * g.lda + t.m
+                                                 : g.a_off + int64_t(t.m - 1) * g.lda + g.k;
+            const int64_t eb = (g.flags & GT_TB) ? g.b_off + int64_t(t.n - 1) * g.ldb + g.k
+                                                 : g.b_off + int64_t(g.k - 1) * g.ldb + t.n;
+            if (g.a_off < 0 || ea > sizes[g.a_buf]) bad("A operand");
+            if (g.b_off < 0 || eb > sizes[g.b_buf]) bad("B operand");
+        }
+    }
+}
+
+static void run_list(GemmList& L, Prec p, const Bases& b, hipStream_t s, const int64_t* sizes) {
+    validate_list(L, sizes);
+    L.upload(s);
+    L.launch(p, b, s);
+}
+
+static int64_t elems(const DevBuf& d) { return int64_t(d.bytes / sizeof(double)); }
+
+// ---------------------------------------------------------------------------
+// small dense symmetric eigensolver (cyclic Jacobi), eigenvalues ascending,
+// eigenvectors in columns of U (row-major n x n)
+static void sym_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& U) {
+    U.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) U[i * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+    double scale = 0;
+    for (double x : A) scale = std::max(scale, std::fabs(x));
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off = std::max(off, std::fabs(a(p, q)));
+        if (off <= 1e-17 * std::max(scale, 1e-300)) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a(p, q);
+                if (std::fabs(apq) <= 1e-300) continue;
+                const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // rotate columns p, q
+                    const double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = c * akp - s * akq;
+                    a(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rotate rows p, q
+                    const double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = c * apk - s * aqk;
+                    a(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double ukp = U[k * n + p], ukq = U[k * n + q];
+                    U[k * n + p] = c * ukp - s * ukq;
+                    U[k * n + q] = s * ukp + c * ukq;
+                }
+            }
+    }
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+    w.resize(n);
+    std::vector<double> U2(size_t(n) * n);
+    for (int i = 0; i < n; ++i) {
+        w[i] = a(ord[i], ord[i]);
+        for (int k = 0; k < n; ++k) U2[k * n + i] = U[k * n + ord[i]];
+    }
+    U.swap(U2);
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+namespace {
+
+struct Dots {
+    DevBuf part, out;
+    std::vector<double> host;
+    void init(hipStream_t s) {
+        part.alloc(sizeof(double) * kDotBlocks * 40, s);
+        out.alloc(sizeof(double) * 40, s);
+        host.resize(40);
+    }
+    // c_i = V_i . w for i < k
+    const std::vector<double>& run(const double* V, int64_t stride, int k, const double* w,
+                                   int64_t n, hipStream_t s) {
+        launch_multidot(V, stride, k, w, n, part.as<double>(), s);
+        launch_reduce_partials(part.as<double>(), k, out.as<double>(), s);
+        DMRG_HIP(hipMemcpyAsync(host.data(), out.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipStreamSynchronize(s));
+        return host;
+    }
+};
+
+void check_finite(double x, const char* what) {
+    if (!std::isfinite(x)) throw Error(E_NUMERIC, std::string("non-finite value in ") + what);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// State: bonds and trivial environments
+
+void State::set_bond(int k, const std::vector<std::pair<QN, int>>& secs) {
+    BondL b;
+    for (auto& [q, d] : secs)
+        if (d > 0) {
+            b.q.push_back(q);
+            b.dim.push_back(d);
+        }
+    b.finalize();
+    bonds[k] = std::move(b);
+}
+
+std::unique_ptr<Env> State::trivial_env(int bond) {
+    auto e = std::make_unique<Env>();
+    e->bond = bond;
+    e->off = {0};
+    e->total = 1;
+    e->buf.alloc(sizeof(double), ctx->stream);
+    launch_fill(e->buf.as<double>(), 1.0, 1, ctx->stream);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// blocking: Y_(y,sp,s) = sum_x W_j[x,y](sp,s) L_j[x]   (left block (x) site j)
+//           Z_(x,sp,s) = sum_y W_k[x,y](sp,s) R_{k+1}[y] (site k (x) right block)
+
+static void run_wsum(Blocked& B, const double* src_base, const std::vector<int64_t>& src_off,
+                     hipStream_t s) {
+    std::vector<SumItem> items;
+    std::vector<SumTerm> terms;
+    terms.reserve(B.terms.size());
+    for (auto& [x, c] : B.terms) terms.push_back({src_base + src_off[x], c});
+    constexpr int64_t kChunk = 16384;
+    for (const BRow& r : B.rows) {
+        const int64_t n = r.lay->size;
+        for (int64_t e = 0; e < n; e += kChunk)
+            items.push_back({B.buf.as<double>() + r.off, e, std::min(n, e + kChunk), r.t_begin,
+                             r.t_end});
+    }
+    if (items.empty()) return;
+    DevBuf di(items.size() * sizeof(SumItem), s), dt(std::max<size_t>(1, terms.size()) * sizeof(SumTerm), s);
+    DMRG_HIP(hipMemcpyAsync(di.p, items.data(), items.size() * sizeof(SumItem), hipMemcpyHostToDevice, s));
+    if (!terms.empty())
+        DMRG_HIP(hipMemcpyAsync(dt.p, terms.data(), terms.size() * sizeof(SumTerm),
+                                hipMemcpyHostToDevice, s));
+    launch_wsum(di.as<SumItem>(), int64_t(items.size()), dt.as<SumTerm>(), s);
+    DMRG_HIP(hipStreamSynchronize(s));
+}
+
+Blocked State::block_sys(int j, const Env& Lj) {
+    const auto& f = mpo->fine[j];
+    Blocked B;
+    B.bond = j;
+    B.n_chan = int(mpo->chans[j + 1].size());
+    B.find.assign(size_t(B.n_chan) * 16, -1);
+    std::vector<int> idx(f.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const FineW &p = f[a], &q = f[b];
+        if (p.y != q.y) return p.y < q.y;
+        if (p.sp != q.sp) return p.sp < q.sp;
+        if (p.s != q.s) return p.s < q.s;
+        return p.x < q.x;
+    });
+    const BondL& bond = bonds[j];
+    for (size_t i = 0; i < idx.size();) {
+        const FineW& h = f[idx[i]];
+        size_t e = i;
+        while (e < idx.size() && f[idx[e]].y == h.y && f[idx[e]].sp == h.sp && f[idx[e]].s == h.s) ++e;
+        const QN dq = mpo->chan_dq[j][h.x];
+        const OpLayout& lay = bond.layout(dq);
+        if (lay.size > 0) {
+            BRow r;
+            r.y = h.y;
+            r.sp = h.sp;
+            r.s = h.s;
+            r.dq = dq;
+            r.off = B.total;
+            r.lay = &lay;
+            r.t_begin = int(B.terms.size());
+            for (size_t k = i; k < e; ++k) {
+                require(bond.layout(mpo->chan_dq[j][f[idx[k]].x]).size == lay.size,
+                        "internal: blocking terms with different layouts", E_STATE);
+                B.terms.push_back({f[idx[k]].x, f[idx[k]].c});
+            }
+            r.t_end = int(B.terms.size());
+            r.identity = mpo->chans[j + 1][h.y].kind == CK_I;
+            B.find[size_t(h.y) * 16 + h.sp * 4 + h.s] = int(B.rows.size());
+            B.rows.push_back(r);
+            B.total += lay.size;
+        }
+        i = e;
+    }
+    B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
+    run_wsum(B, Lj.buf.as<double>(), Lj.off, ctx->stream);
+    return B;
+}
+
+Blocked State::block_env(int k, const Env& Rk1) {
+    const auto& f = mpo->fine[k];
+    Blocked B;
+    B.bond = k + 1;
+    B.n_chan = int(mpo->chans[k].size());
+    B.find.assign(size_t(B.n_chan) * 16, -1);
+    std::vector<int> idx(f.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const FineW &p = f[a], &q = f[b];
+        if (p.x != q.x) return p.x < q.x;
+        if (p.sp != q.sp) return p.sp < q.sp;
+        if (p.s != q.s) return p.s < q.s;
+        return p.y < q.y;
+    });
+    const BondL& bond = bonds[k + 1];
+    for (size_t i = 0; i < idx.size();) {
+        const FineW& h = f[idx[i]];
+        size_t e = i;
+        while (e < idx.size() && f[idx[e]].x == h.x && f[idx[e]].sp == h.sp && f[idx[e]].s == h.s) ++e;
+        const QN dq = mpo->chan_dq[k + 1][h.y];
+        const OpLayout& lay = bond.layout(dq);
+        if (lay.size > 0) {
+            BRow r;
+            r.y = h.x;
+            r.sp = h.sp;
+            r.s = h.s;
+            r.dq = dq;
+            r.off = B.total;
+            r.lay = &lay;
+            r.t_begin = int(B.terms.size());
+            for (size_t q = i; q < e; ++q) {
+                require(bond.layout(mpo->chan_dq[k + 1][f[idx[q]].y]).size == lay.size,
+                        "internal: blocking terms with different layouts", E_STATE);
+                B.terms.push_back({f[idx[q]].y, f[idx[q]].c});
+            }
+            r.t_end = int(B.terms.size());
+            r.identity = mpo->chans[k][h.x].kind == CK_H;
+            B.find[size_t(h.x) * 16 + h.sp * 4 + h.s] = int(B.rows.size());
+            B.rows.push_back(r);
+            B.total += lay.size;
+        }
+        i = e;
+    }
+    B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
+    run_wsum(B, Rk1.buf.as<double>(), Rk1.off, ctx->stream);
+    return B;
+}
+
+// ---------------------------------------------------------------------------
+// decimation (Eq. prenormdec): L_{j+1}[y] = A^T O^sys_y A ; R_k[x] = B O^env_x B^T
+
+std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged& A) {
+    hipStream_t s = ctx->stream;
+    const BondL& bl = bonds[j];
+    const BondL& bn = bonds[j + 1];
+    const int nch = int(mpo->chans[j + 1].size());
+    const int nq = int(bn.q.size());
+    std::vector<Space> sys(nq);
+    for (int i = 0; i < nq; ++i) sys[i] = sys_space(bl, bn.q[i]);
+    // X_y(q) = O^sys_y[q' <- q] A(q): rows sys(q'), cols m(q)
+    std::vector<int64_t> xoff(size_t(nch) * nq, -1);
+    int64_t xtot = 0;
+    std::vector<char> has(nch, 0);
+    for (const BRow& r : Yb.rows) has[r.y] = 1;
+    for (int y = 0; y < nch; ++y) {
+        if (!has[y]) continue;
+        const QN dq = mpo->chan_dq[j + 1][y];
+        for (int iq = 0; iq < nq; ++iq) {
+            int iq2 = bn.find(bn.q[iq] + dq);
+            if (iq2 < 0) continue;
+            xoff[size_t(y) * nq + iq] = xtot;
+            xtot += int64_t(sys[iq2].dim) * bn.dim[iq];
+        }
+    }
+    DevBuf X(std::max<int64_t>(1, xtot) * sizeof(double), s);
+    GemmList p1;
+    std::vector<UTerm> terms;
+    for (int y = 0; y < nch; ++y)
+        for (int iq = 0; iq < nq; ++iq) {
+            const int64_t xo = xoff[size_t(y) * nq + iq];
+            if (xo < 0) continue;
+            const QN dq = mpo->chan_dq[j + 1][y];
+            const int iq2 = bn.find(bn.q[iq] + dq);
+            const int ncol = bn.dim[iq];
+            for (const Seg& so : sys[iq2].segs) {
+                terms.clear();
+                for (int st = 0; st < 4; ++st) {
+                    const int ri = Yb.row(y, so.st, st);
+                    if (ri < 0) continue;
+                    const int si = sys[iq].seg_of[st];
+                    if (si < 0) continue;
+                    const Seg& sg = sys[iq].segs[si];
+                    const BRow& r = Yb.rows[ri];
+                    const int bi = r.lay->by_in[sg.sec];
+                    if (bi < 0) continue;
+                    const OpBlock& blk = r.lay->blocks[bi];
+                    if (blk.out != so.sec) continue;
+                    terms.push_back({0, r.off + blk.off, blk.cols, false, 1,
+                                     A.off[iq] + int64_t(sg.off) * ncol, ncol, false, blk.cols, 1.0,
+                                     true});
+                }
+                add_unit(p1, 2, xo + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
+            }
+        }
+    Bases b1{};
+    b1.p[0] = Yb.buf.p;
+    b1.p[1] = A.buf.p;
+    b1.p[2] = X.p;
+    {
+        int64_t sz[kMaxBufs] = {elems(Yb.buf), elems(A.buf), elems(X)};
+        run_list(p1, Prec::F64, b1, s, sz);
+    }
+
+    auto E = std::make_unique<Env>();
+    E->bond = j + 1;
+    E->off.resize(nch);
+    for (int y = 0; y < nch; ++y) {
+        E->off[y] = E->total;
+        E->total += bn.layout(mpo->chan_dq[j + 1][y]).size;
+    }
+    E->buf.alloc(std::max<int64_t>(1, E->total) * sizeof(double), s);
+    GemmList p2;
+    for (int y = 0; y < nch; ++y) {
+        const OpLayout& lay = bn.layout(mpo->chan_dq[j + 1][y]);
+        for (const OpBlock& blk : lay.blocks) {
+            terms.clear();
+            const int64_t xo = xoff[size_t(y) * nq + blk.in];
+            if (xo >= 0)
+                terms.push_back({1, A.off[blk.out], bn.dim[blk.out], true, 2, xo, bn.dim[blk.in],
+                                 false, sys[blk.out].dim, 1.0, true});
+            add_unit(p2, 3, E->off[y] + blk.off, blk.cols, blk.rows, blk.cols, 0, terms);
+        }
+    }
+    Bases b2{};
+    b2.p[1] = A.buf.p;
+    b2.p[2] = X.p;
+    b2.p[3] = E->buf.p;
+    {
+        int64_t sz[kMaxBufs] = {0, elems(A.buf), elems(X), elems(E->buf)};
+        run_list(p2, Prec::F64, b2, s, sz);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+    return E;
+}
+
+std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merged& B) {
+    hipStream_t s = ctx->stream;
+    const BondL& bn = bonds[k];
+    const BondL& br = bonds[k + 1];
+    const int nch = int(mpo->chans[k].size());
+    const int nq = int(bn.q.size());
+    std::vector<Space> env(nq);
+    for (int i = 0; i < nq; ++i) env[i] = env_space(br, bn.q[i]);
+    // X_x(q) = O^env_x[q' <- q] B(q)^T: rows env(q'), cols m(q)
+    std::vector<int64_t> xoff(size_t(nch) * nq, -1);
+    int64_t xtot = 0;
+    std::vector<char> has(nch, 0);
+    for (const BRow& r : Zb.rows) has[r.y] = 1;
+    for (int x = 0; x < nch; ++x) {
+        if (!has[x]) continue;
+        const QN dq = mpo->chan_dq[k][x];
+        for (int iq = 0; iq < nq; ++iq) {
+            int iq2 = bn.find(bn.q[iq] + dq);
+            if (iq2 < 0) continue;
+            xoff[size_t(x) * nq + iq] = xtot;
+            xtot += int64_t(env[iq2].dim) * bn.dim[iq];
+        }
+    }
+    DevBuf X(std::max<int64_t>(1, xtot) * sizeof(double), s);
+    GemmList p1;
+    std::vector<UTerm> terms;
+    for (int x = 0; x < nch; ++x)
+        for (int iq = 0; iq < nq; ++iq) {
+            const int64_t xo = xoff[size_t(x) * nq + iq];
+            if (xo < 0) continue;
+            const int iq2 = bn.find(bn.q[iq] + mpo->chan_dq[k][x]);
+            const int ncol = bn.dim[iq];
+            for (const Seg& so : env[iq2].segs) {
+                terms.clear();
+                for (int t = 0; t < 4; ++t) {
+                    const int ri = Zb.row(x, so.st, t);
+                    if (ri < 0) continue;
+                    const int si = env[iq].seg_of[t];
+                    if (si < 0) continue;
+                    const Seg& sg = env[iq].segs[si];
+                    const BRow& r = Zb.rows[ri];
+                    const int bi = r.lay->by_in[sg.sec];
+                    if (bi < 0) continue;
+                    const OpBlock& blk = r.lay->blocks[bi];
+                    if (blk.out != so.sec) continue;
+                    terms.push_back({0, r.off + blk.off, blk.cols, false, 1, B.off[iq] + sg.off,
+                                     env[iq].dim, true, blk.cols, 1.0, true});
+                }
+                add_unit(p1, 2, xo + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
+            }
+        }
+    Bases b1{};
+    b1.p[0] = Zb.buf.p;
+    b1.p[1] = B.buf.p;
+    b1.p[2] = X.p;
+    {
+        int64_t sz[kMaxBufs] = {elems(Zb.buf), elems(B.buf), elems(X)};
+        run_list(p1, Prec::F64, b1, s, sz);
+    }
+
+    auto E = std::make_unique<Env>();
+    E->bond = k;
+    E->off.resize(nch);
+    for (int x = 0; x < nch; ++x) {
+        E->off[x] = E->total;
+        E->total += bn.layout(mpo->chan_dq[k][x]).size;
+    }
+    E->buf.alloc(std::max<int64_t>(1, E->total) * sizeof(double), s);
+    GemmList p2;
+    for (int x = 0; x < nch; ++x) {
+        const OpLayout& lay = bn.layout(mpo->chan_dq[k][x]);
+        for (const OpBlock& blk : lay.blocks) {
+            terms.clear();
+            const int64_t xo = xoff[size_t(x) * nq + blk.in];
+            if (xo >= 0)
+                terms.push_back({1, B.off[blk.out], env[blk.out].dim, false, 2, xo, bn.dim[blk.in],
+                                 false, env[blk.out].dim, 1.0, true});
+            add_unit(p2, 3, E->off[x] + blk.off, blk.cols, blk.rows, blk.cols, 0, terms);
+        }
+    }
+    Bases b2{};
+    b2.p[1] = B.buf.p;
+    b2.p[2] = X.p;
+    b2.p[3] = E->buf.p;
+    {
+        int64_t sz[kMaxBufs] = {0, elems(B.buf), elems(X), elems(E->buf)};
+        run_list(p2, Prec::F64, b2, s, sz);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+    return E;
+}
+
+// ---------------------------------------------------------------------------
+// two-site center
+
+// psi_q = A(q) B(q) for the sectors q of bond center+1 (A left-merged, B right-merged)
+void State::form_center_from_pair(const Merged& A, const Merged& B) {
+    hipStream_t s = ctx->stream;
+    const int j = center;
+    ts = make_two_site(bonds[j], bonds[j + 2]);
+    psi.alloc(std::max<int64_t>(1, ts.n) * sizeof(double), s);
+    launch_fill(psi.as<double>(), 0.0, ts.n, s);
+    GemmList Lg;
+    std::vector<UTerm> terms;
+    const BondL& bm = bonds[j + 1];
+    for (size_t i = 0; i < bm.q.size(); ++i) {
+        const int iq = ts.find(bm.q[i]);
+        const int ia = A.find(bm.q[i]), ib = B.find(bm.q[i]);
+        if (iq < 0 || ia < 0 || ib < 0) continue;
+        require(A.rows[ia] == ts.sys[iq].dim && B.cols[ib] == ts.env[iq].dim,
+                "internal: center shapes disagree", E_STATE);
+        terms.clear();
+        terms.push_back({0, A.off[ia], A.cols[ia], false, 1, B.off[ib], B.cols[ib], false,
+                         A.cols[ia], 1.0, true});
+        add_unit(Lg, 2, ts.off[iq], ts.env[iq].dim, ts.sys[iq].dim, ts.env[iq].dim, 0, terms);
+    }
+    Bases b{};
+    b.p[0] = A.buf.p;
+    b.p[1] = B.buf.p;
+    b.p[2] = psi.p;
+    int64_t sz[kMaxBufs] = {elems(A.buf), elems(B.buf), elems(psi)};
+    run_list(Lg, Prec::F64, b, s, sz);
+    DMRG_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// setup
+
+namespace {
+
+using U128 = unsigned __int128;
+const U128 kSat = U128(1) << 100;
+U128 sat_mul(U128 a, U128 b) {
+    if (a == 0 || b == 0) return 0;
+    if (a > kSat / b) return kSat;
+    return std::min(kSat, a * b);
+}
+
+std::vector<std::vector<U128>> binomials(int n) {
+    std::vector<std::vector<U128>> C(n + 1);
+    for (int i = 0; i <= n; ++i) {
+        C[i].assign(i + 1, 1);
+        for (int k = 1; k < i; ++k) C[i][k] = std::min(kSat, C[i - 1][k - 1] + C[i - 1][k]);
+    }
+    return C;
+}
+
+}  // namespace
+
+// Integer rule for the sector dimensions of the random initial MPS.
+static std::vector<std::map<QN, int64_t>> initial_dims(int K, int N, int tsz, int M) {
+    const int nu_t = (N + tsz) / 2, nd_t = (N - tsz) / 2;
+    auto C = binomials(K);
+    auto comb = [&](int n, int k) -> U128 { return (k < 0 || k > n) ? 0 : C[n][k]; };
+    std::vector<std::map<QN, int64_t>> dims(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        std::map<QN, int64_t> d;
+        for (int nu = 0; nu <= k; ++nu)
+            for (int nd = 0; nd <= k; ++nd) {
+                const int ru = nu_t - nu, rd = nd_t - nd;
+                if (ru < 0 || rd < 0 || ru > K - k || rd > K - k) continue;
+                U128 fl = sat_mul(comb(k, nu), comb(k, nd));
+                U128 fr = sat_mul(comb(K - k, ru), comb(K - k, rd));
+                U128 f = std::min(std::min(fl, fr), U128(M));
+                d[{nu + nd, nu - nd}] = int64_t(f);
+            }
+        int64_t tot = 0;
+        for (auto& kv : d) tot += kv.second;
+        if (tot > M) {
+            std::vector<std::pair<QN, int64_t>> num;  // M * full
+            std::map<QN, int64_t> nd;
+            for (auto& [q, x] : d) {
+                num.push_back({q, int64_t(M) * x});
+                nd[q] = int64_t(M) * x / tot;
+            }
+            int64_t extra = M;
+            for (auto& kv : nd) extra -= kv.second;
+            std::stable_sort(num.begin(), num.end(), [&](const auto& a, const auto& b) {
+                const int64_t ra = a.second % tot, rb = b.second % tot;
+                if (ra != rb) return ra > rb;
+                return a.first < b.first;
+            });
+            for (int64_t i = 0; i < extra && i < int64_t(num.size()); ++i) nd[num[i].first] += 1;
+            d = nd;
+        }
+        std::map<QN, int64_t> pos;
+        for (auto& [q, x] : d)
+            if (x > 0) pos[q] = x;
+        dims[k] = pos;
+    }
+    bool changed = true;
+    auto get = [](const std::map<QN, int64_t>& m, QN q) -> int64_t {
+        auto it = m.find(q);
+        return it == m.end() ? 0 : it->second;
+    };
+    while (changed) {
+        changed = false;
+        for (int k = 1; k <= K; ++k) {
+            for (auto& [q, x] : dims[k]) {
+                int64_t cap = 0;
+                for (int s = 0; s < 4; ++s) cap += get(dims[k - 1], q - kSiteQN[s]);
+                if (x > cap) {
+                    x = cap;
+                    changed = true;
+                }
+            }
+            for (auto it = dims[k].begin(); it != dims[k].end();)
+                it = it->second > 0 ? std::next(it) : dims[k].erase(it);
+        }
+        for (int k = K - 1; k >= 0; --k) {
+            for (auto& [q, x] : dims[k]) {
+                int64_t cap = 0;
+                for (int s = 0; s < 4; ++s) cap += get(dims[k + 1], q + kSiteQN[s]);
+                if (x > cap) {
+                    x = cap;
+                    changed = true;
+                }
+            }
+            for (auto it = dims[k].begin(); it != dims[k].end();)
+                it = it->second > 0 ? std::next(it) : dims[k].erase(it);
+        }
+    }
+    return dims;
+}
+
+int64_t initial_value_count(const MPO& m, int M) {
+    auto dims = initial_dims(m.K, m.n_elec, m.two_sz, M);
+    int64_t n = 0;
+    for (int j = 0; j < m.K; ++j)
+        for (auto& [q, d] : dims[j])
+            for (int s = 0; s < 4; ++s) {
+                auto it = dims[j + 1].find(q + kSiteQN[s]);
+                if (it != dims[j + 1].end()) n += d * it->second;
+            }
+    return n;
+}
+
+// Place fine blocks (site j, canonical order) into a merged tensor on the host.
+static void merge_site(const BondL& bl, const BondL& br, int form, const double* vals,
+                       int64_t& pos, Merged& Mg, std::vector<double>& host) {
+    Mg.form = form;
+    Mg.q.clear();
+    Mg.rows.clear();
+    Mg.cols.clear();
+    Mg.off.clear();
+    Mg.idx.clear();
+    Mg.size = 0;
+    const BondL& mb = form == 1 ? br : bl;
+    for (size_t i = 0; i < mb.q.size(); ++i) {
+        const QN q = mb.q[i];
+        int r, c;
+        if (form == 1) {
+            r = sys_space(bl, q).dim;
+            c = mb.dim[i];
+        } else {
+            r = mb.dim[i];
+            c = env_space(br, q).dim;
+        }
+        Mg.idx[q] = int(Mg.q.size());
+        Mg.q.push_back(q);
+        Mg.rows.push_back(r);
+        Mg.cols.push_back(c);
+        Mg.off.push_back(Mg.size);
+        Mg.size += int64_t(r) * c;
+    }
+    host.assign(std::max<int64_t>(1, Mg.size), 0.0);
+    for (size_t il = 0; il < bl.q.size(); ++il)
+        for (int s = 0; s < 4; ++s) {
+            const QN qr = bl.q[il] + kSiteQN[s];
+            const int ir = br.find(qr);
+            if (ir < 0) continue;
+            const int ml = bl.dim[il], mr = br.dim[ir];
+            if (form == 1) {
+                const int iq = Mg.find(qr);
+                const Space sp = sys_space(bl, qr);
+                const Seg& sg = sp.segs[sp.seg_of[s]];
+                for (int a = 0; a < ml; ++a)
+                    for (int b = 0; b < mr; ++b)
+                        host[Mg.off[iq] + int64_t(sg.off + a) * Mg.cols[iq] + b] = vals[pos + int64_t(a) * mr + b];
+            } else {
+                const int iq = Mg.find(bl.q[il]);
+                const Space sp = env_space(br, bl.q[il]);
+                const Seg& sg = sp.segs[sp.seg_of[s]];
+                for (int a = 0; a < ml; ++a)
+                    for (int b = 0; b < mr; ++b)
+                        host[Mg.off[iq] + int64_t(a) * Mg.cols[iq] + sg.off + b] = vals[pos + int64_t(a) * mr + b];
+            }
+            pos += int64_t(ml) * mr;
+        }
+}
+
+static void upload(Merged& Mg, const std::vector<double>& host, hipStream_t s) {
+    Mg.buf.alloc(std::max<int64_t>(1, Mg.size) * sizeof(double), s);
+    DMRG_HIP(hipMemcpyAsync(Mg.buf.p, host.data(), std::max<int64_t>(1, Mg.size) * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+}
+
+// SVD of a row-major rows x cols matrix on the device (rocSOLVER, FP64):
+// returns Um (rows x r, row-major), S (r) and Vt (r x cols, row-major).
+struct SvdOut {
+    int rows, cols, r;
+    int64_t a_off, u_off, v_off, s_off, e_off;
+};
+
+static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::pair<int, int>>>& mats,
+                      std::vector<SvdOut>& outs, DevBuf& work, DevBuf& info) {
+    hipStream_t s = ctx->stream;
+    outs.clear();
+    int64_t tot = 0;
+    for (auto& [p, rc] : mats) {
+        SvdOut o;
+        o.rows = rc.first;
+        o.cols = rc.second;
+        o.r = std::min(o.rows, o.cols);
+        o.a_off = tot;
+        tot += int64_t(o.rows) * o.cols;
+        o.u_off = tot;
+        tot += int64_t(o.rows) * o.r;
+        o.v_off = tot;
+        tot += int64_t(o.r) * o.cols;
+        o.s_off = tot;
+        tot += o.r;
+        o.e_off = tot;
+        tot += std::max(1, o.r);
+        outs.push_back(o);
+    }
+    work.alloc(std::max<int64_t>(1, tot) * sizeof(double), s);
+    info.alloc(std::max<size_t>(1, mats.size()) * sizeof(rocblas_int), s);
+    double* w = work.as<double>();
+    for (size_t i = 0; i < mats.size(); ++i) {
+        const SvdOut& o = outs[i];
+        if (o.r == 0) continue;
+        launch_copy(w + o.a_off, mats[i].first, int64_t(o.rows) * o.cols, s);
+        // row-major (rows x cols) == column-major (cols x rows) = A^T = Ut S Vt^T
+        // so Um (row-major rows x r) is rocSOLVER's V output and Vt (row-major
+        // r x cols) is its U output.
+        rocblas_status st = rocsolver_dgesvd(
+            ctx->blas, rocblas_svect_singular, rocblas_svect_singular, o.cols, o.rows, w + o.a_off,
+            o.cols, w + o.s_off, w + o.v_off, o.cols, w + o.u_off, o.r, w + o.e_off,
+            rocblas_outofplace, info.as<rocblas_int>() + i);
+        if (st != rocblas_status_success)
+            throw Error(E_HIP, "rocsolver_dgesvd failed with status " + std::to_string(int(st)));
+    }
+    std::vector<rocblas_int> hinfo(mats.size());
+    if (!mats.empty())
+        DMRG_HIP(hipMemcpyAsync(hinfo.data(), info.p, mats.size() * sizeof(rocblas_int),
+                                hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < mats.size(); ++i)
+        if (outs[i].r > 0 && hinfo[i] != 0) throw Error(E_NUMERIC, "SVD did not converge");
+}
+
+void State::init_random(int M, const double* values, int64_t n_values) {
+    require(M >= 1, "M must be >= 1");
+    hipStream_t s = ctx->stream;
+    const int K = mpo->K;
+    auto dims = initial_dims(K, mpo->n_elec, mpo->two_sz, M);
+    bonds.clear();
+    bonds.resize(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        require(!dims[k].empty(), "no quantum-number sector survives at a bond: M too small");
+        std::vector<std::pair<QN, int>> v;
+        for (auto& [q, d] : dims[k]) v.push_back({q, int(d)});
+        set_bond(k, v);
+    }
+    require(n_values >= initial_value_count(*mpo, M), "value stream shorter than the MPS");
+    site.clear();
+    site.resize(K);
+    int64_t pos = 0;
+    std::vector<double> host;
+    for (int j = 0; j < K; ++j) {
+        merge_site(bonds[j], bonds[j + 1], 2, values, pos, site[j], host);
+        upload(site[j], host, s);
+    }
+    // right-canonical form by sector-wise SVD from the right: B = U S V^T,
+    // B <- V^T, U S absorbed into the left neighbour
+    DevBuf work, info, idx;
+    for (int k = K - 1; k >= 1; --k) {
+        Merged& B = site[k];
+        std::vector<std::pair<const double*, std::pair<int, int>>> mats;
+        for (size_t i = 0; i < B.q.size(); ++i)
+            mats.push_back({B.buf.as<double>() + B.off[i], {B.rows[i], B.cols[i]}});
+        std::vector<SvdOut> outs;
+        svd_batch(ctx, mats, outs, work, info);
+        double* w = work.as<double>();
+        GemmList Lg;
+        std::vector<UTerm> terms;
+        Merged& P = site[k - 1];
+        Merged Pn;
+        Pn.form = 2;
+        Pn.q = P.q;
+        Pn.rows = P.rows;
+        Pn.cols = P.cols;
+        Pn.off = P.off;
+        Pn.idx = P.idx;
+        Pn.size = P.size;
+        Pn.buf.alloc(std::max<int64_t>(1, P.size) * sizeof(double), s);
+        for (size_t i = 0; i < B.q.size(); ++i) {
+            const SvdOut& o = outs[i];
+            require(o.r == B.rows[i], "random MPS sector is rank deficient", E_NUMERIC);
+            // B(q) <- Vt
+            launch_copy(B.buf.as<double>() + B.off[i], w + o.v_off, int64_t(o.r) * o.cols, s);
+            // Um <- Um S (columns scaled)
+            std::vector<int> cols(o.r);
+            std::iota(cols.begin(), cols.end(), 0);
+            idx.alloc(sizeof(int) * o.r, s);
+            DMRG_HIP(hipMemcpyAsync(idx.p, cols.data(), sizeof(int) * o.r, hipMemcpyHostToDevice, s));
+            launch_gather_cols(w + o.u_off, o.r, w + o.u_off, o.r, idx.as<int>(), w + o.s_off,
+                               o.rows, o.r, s);
+            DMRG_HIP(hipStreamSynchronize(s));
+        }
+        // P'(q')[:, cols (t, q)] = P(q')[:, cols (t, q)] (U S)(q)
+        const BondL& bk = bonds[k];
+        for (size_t ip = 0; ip < P.q.size(); ++ip) {
+            const Space es = env_space(bk, P.q[ip]);
+            for (const Seg& sg : es.segs) {
+                const int iq = B.find(bk.q[sg.sec]);
+                const SvdOut& o = outs[iq];
+                terms.clear();
+                terms.push_back({0, P.off[ip] + sg.off, P.cols[ip], false, 1, o.u_off, o.r, false,
+                                 o.rows, 1.0, true});
+                add_unit(Lg, 2, Pn.off[ip] + sg.off, P.cols[ip], P.rows[ip], o.r, 0, terms);
+            }
+        }
+        Bases b{};
+        b.p[0] = P.buf.p;
+        b.p[1] = work.p;
+        b.p[2] = Pn.buf.p;
+        int64_t sz[kMaxBufs] = {elems(P.buf), elems(work), elems(Pn.buf)};
+        run_list(Lg, Prec::F64, b, s, sz);
+        DMRG_HIP(hipStreamSynchronize(s));
+        P.buf = std::move(Pn.buf);
+    }
+    // site 0 (one left sector) to left-merged form over bond 1, then psi = A0 B1
+    {
+        Merged& S0 = site[0];
+        std::vector<double> h0(std::max<int64_t>(1, S0.size));
+        DMRG_HIP(hipMemcpyAsync(h0.data(), S0.buf.p, h0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipStreamSynchronize(s));
+        Merged A0;
+        std::vector<double> ha;
+        // re-express as fine blocks, then merge in LEFT form
+        std::vector<double> fine;
+        const BondL &b0 = bonds[0], &b1 = bonds[1];
+        for (size_t il = 0; il < b0.q.size(); ++il) {
+            const Space es = env_space(b1, b0.q[il]);
+            for (int st = 0; st < 4; ++st) {
+                if (es.seg_of[st] < 0) continue;
+                const Seg& sg = es.segs[es.seg_of[st]];
+                for (int a = 0; a < b0.dim[il]; ++a)
+                    for (int c = 0; c < sg.dim; ++c)
+                        fine.push_back(h0[S0.off[il] + int64_t(a) * S0.cols[il] + sg.off + c]);
+            }
+        }
+        int64_t p0 = 0;
+        merge_site(b0, b1, 1, fine.data(), p0, A0, ha);
+        upload(A0, ha, s);
+        center = 0;
+        form_center_from_pair(A0, site[1]);
+        site[0] = std::move(A0);
+    }
+    L.clear();
+    R.clear();
+    L.resize(K + 1);
+    R.resize(K + 1);
+    L[0] = trivial_env(0);
+    R[K] = trivial_env(K);
+    for (int k = K - 1; k >= 2; --k) {
+        Blocked Zb = block_env(k, *R[k + 1]);
+        R[k] = decimate_right(Zb, k, site[k]);
+    }
+    prepared = false;
+}
+
+void State::import_tensors(const std::vector<std::vector<std::pair<QN, int>>>& bonds_in,
+                           const double* values, int cj) {
+    hipStream_t s = ctx->stream;
+    const int K = mpo->K;
+    require(int(bonds_in.size()) == K + 1, "need K+1 bonds");
+    require(cj >= 0 && cj <= K - 2, "center must be in [0, K-2]");
+    bonds.clear();
+    bonds.resize(K + 1);
+    for (int k = 0; k <= K; ++k) {
+        for (size_t i = 1; i < bonds_in[k].size(); ++i)
+            require(bonds_in[k][i - 1].first < bonds_in[k][i].first, "sectors must be sorted and unique");
+        set_bond(k, bonds_in[k]);
+    }
+    require(bonds[0].q.size() == 1 && bonds[0].q[0] == QN{0, 0} && bonds[0].dim[0] == 1,
+            "bond 0 must be the single sector (0,0) of dimension 1");
+    require(bonds[K].q.size() == 1 && bonds[K].q[0] == mpo->target() && bonds[K].dim[0] == 1,
+            "bond K must be the single target sector of dimension 1");
+    site.clear();
+    site.resize(K);
+    int64_t pos = 0;
+    std::vector<double> host;
+    for (int j = 0; j < K; ++j) {
+        const int form = (j <= cj) ? 1 : 2;
+        merge_site(bonds[j], bonds[j + 1], form, values, pos, site[j], host);
+        upload(site[j], host, s);
+    }
+    center = cj;
+    form_center_from_pair(site[cj], site[cj + 1]);
+    L.clear();
+    R.clear();
+    L.resize(K + 1);
+    R.resize(K + 1);
+    L[0] = trivial_env(0);
+    R[K] = trivial_env(K);
+    for (int k = 1; k <= cj; ++k) {
+        Blocked Yb = block_sys(k - 1, *L[k - 1]);
+        L[k] = decimate_left(Yb, k - 1, site[k - 1]);
+    }
+    for (int k = K - 1; k >= cj + 2; --k) {
+        Blocked Zb = block_env(k, *R[k + 1]);
+        R[k] = decimate_right(Zb, k, site[k]);
+    }
+    prepared = false;
+}
+
+// ---------------------------------------------------------------------------
+// sigma
+
+void State::release_workspace() {
+    DMRG_HIP(hipStreamSynchronize(ctx->stream));
+    Y = Blocked();
+    Z = Blocked();
+    pass1.clear();
+    pass2.clear();
+    pass1.dtasks.free();
+    pass1.dterms.free();
+    pass2.dtasks.free();
+    pass2.dterms.free();
+    t_off.clear();
+    tbuf.free();
+    part.free();
+    psi32.free();
+    sig32.free();
+    tbuf32.free();
+    part32.free();
+    diag.free();
+    diag_ok = false;
+    prepared = false;
+}
+
+void State::prepare() {
+    if (prepared) return;
+    const int j = center;
+    hipStream_t s = ctx->stream;
+    Y = block_sys(j, *L[j]);
+    Z = block_env(j + 1, *R[j + 2]);
+    const int nch = int(mpo->chans[j + 1].size());
+    const int nq = int(ts.q.size());
+    // T_y(q) = O^sys_y psi_q : rows sys(q + dq_y), cols env(q)
+    std::vector<char> hy(nch, 0), hz(nch, 0);
+    for (const BRow& r : Y.rows) hy[r.y] = 1;
+    for (const BRow& r : Z.rows) hz[r.y] = 1;
+    t_off.assign(size_t(nch) * nq, -1);
+    t_total = 0;
+    for (int y = 0; y < nch; ++y) {
+        if (!hy[y] || !hz[y]) continue;
+        const QN dq = mpo->chan_dq[j + 1][y];
+        for (int iq = 0; iq < nq; ++iq) {
+            const int iq2 = ts.find(ts.q[iq] + dq);
+            if (iq2 < 0) continue;
+            t_off[size_t(y) * nq + iq] = t_total;
+            t_total += int64_t(ts.sys[iq2].dim) * ts.env[iq].dim;
+        }
+    }
+    pass1.clear();
+    std::vector<UTerm> terms;
+    for (int y = 0; y < nch; ++y)
+        for (int iq = 0; iq < nq; ++iq) {
+            const int64_t to = t_off[size_t(y) * nq + iq];
+            if (to < 0) continue;
+            const int iq2 = ts.find(ts.q[iq] + mpo->chan_dq[j + 1][y]);
+            const int ncol = ts.env[iq].dim;
+            for (const Seg& so : ts.sys[iq2].segs) {
+                terms.clear();
+                for (int st = 0; st < 4; ++st) {
+                    const int ri = Y.row(y, so.st, st);
+                    if (ri < 0) continue;
+                    const int si = ts.sys[iq].seg_of[st];
+                    if (si < 0) continue;
+                    const Seg& sg = ts.sys[iq].segs[si];
+                    const BRow& r = Y.rows[ri];
+                    const int bi = r.lay->by_in[sg.sec];
+                    if (bi < 0) continue;
+                    const OpBlock& blk = r.lay->blocks[bi];
+                    if (blk.out != so.sec) continue;
+                    terms.push_back({0, r.off + blk.off, blk.cols, false, 1,
+                                     ts.off[iq] + int64_t(sg.off) * ncol, ncol, false, blk.cols, 1.0,
+                                     !r.identity});
+                }
+                add_unit(pass1, 2, to + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
+            }
+        }
+    // sigma_q' [:, (t', Q'_r)] = sum_y sum_t T_y(q)[:, (t, Q_r)] Z_(y,t',t)^T
+    pass2.clear();
+    int64_t tiles2 = 0;
+    for (int iq2 = 0; iq2 < nq; ++iq2)
+        for (const Seg& so : ts.env[iq2].segs)
+            tiles2 += int64_t((ts.sys[iq2].dim + kTile - 1) / kTile) * ((so.dim + kTile - 1) / kTile);
+    splits = int(std::max<int64_t>(1, std::min<int64_t>(16, (4096 + tiles2 - 1) / std::max<int64_t>(1, tiles2))));
+    const BondL& br = bonds[j + 2];
+    for (int iq2 = 0; iq2 < nq; ++iq2) {
+        const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
+        for (const Seg& so : ts.env[iq2].segs) {
+            terms.clear();
+            for (int y = 0; y < nch; ++y) {
+                if (!hy[y] || !hz[y]) continue;
+                const QN q = ts.q[iq2] - mpo->chan_dq[j + 1][y];
+                const int iq = ts.find(q);
+                if (iq < 0) continue;
+                const int64_t to = t_off[size_t(y) * nq + iq];
+                if (to < 0) continue;
+                for (int t = 0; t < 4; ++t) {
+                    const int ri = Z.row(y, so.st, t);
+                    if (ri < 0) continue;
+                    const int si = ts.env[iq].seg_of[t];
+                    if (si < 0) continue;
+                    const Seg& sg = ts.env[iq].segs[si];
+                    const BRow& r = Z.rows[ri];
+                    const int bi = r.lay->by_in[sg.sec];
+                    if (bi < 0) continue;
+                    const OpBlock& blk = r.lay->blocks[bi];
+                    if (blk.out != so.sec) continue;
+                    terms.push_back({0, to + sg.off, ts.env[iq].dim, false, 1, r.off + blk.off,
+                                     blk.cols, true, blk.cols, 1.0, !r.identity});
+                }
+            }
+            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, terms, splits, ts.n);
+        }
+    }
+    (void)br;
+    {
+        int64_t sz1[kMaxBufs] = {Y.total, ts.n, t_total};
+        validate_list(pass1, sz1);
+        int64_t sz2[kMaxBufs] = {t_total, Z.total, splits > 1 ? int64_t(splits) * ts.n : ts.n};
+        validate_list(pass2, sz2);
+    }
+    pass1.upload(s);
+    pass2.upload(s);
+    tbuf.alloc(std::max<int64_t>(1, t_total) * sizeof(double), s);
+    if (splits > 1) part.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(double), s);
+    DMRG_HIP(hipStreamSynchronize(s));
+    prepared = true;
+    diag_ok = false;
+}
+
+void State::sigma(const double* x, double* y, Prec p, double* flops, double* secs) {
+    prepare();
+    hipStream_t s = ctx->stream;
+    DMRG_HIP(hipEventRecord(ctx->ev0, s));
+    if (p == Prec::F64) {
+        Bases b1{};
+        b1.p[0] = Y.buf.p;
+        b1.p[1] = const_cast<double*>(x);
+        b1.p[2] = tbuf.p;
+        pass1.launch(Prec::F64, b1, s);
+        Bases b2{};
+        b2.p[0] = tbuf.p;
+        b2.p[1] = Z.buf.p;
+        b2.p[2] = splits > 1 ? part.p : static_cast<void*>(y);
+        pass2.launch(Prec::F64, b2, s);
+        if (splits > 1) launch_sum_slices(y, part.as<double>(), splits, ts.n, 0, s);
+    } else {
+        if (!Y.buf32.p) {
+            Y.buf32.alloc(std::max<int64_t>(1, Y.total) * sizeof(float), s);
+            launch_to_f32(Y.buf32.as<float>(), Y.buf.as<double>(), Y.total, s);
+            Z.buf32.alloc(std::max<int64_t>(1, Z.total) * sizeof(float), s);
+            launch_to_f32(Z.buf32.as<float>(), Z.buf.as<double>(), Z.total, s);
+            psi32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
+            sig32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
+            tbuf32.alloc(std::max<int64_t>(1, t_total) * sizeof(float), s);
+            if (splits > 1) part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
+        }
+        launch_to_f32(psi32.as<float>(), x, ts.n, s);
+        Bases b1{};
+        b1.p[0] = Y.buf32.p;
+        b1.p[1] = psi32.p;
+        b1.p[2] = tbuf32.p;
+        pass1.launch(p, b1, s);
+        Bases b2{};
+        b2.p[0] = tbuf32.p;
+        b2.p[1] = Z.buf32.p;
+        b2.p[2] = splits > 1 ? part32.p : sig32.p;
+        pass2.launch(p, b2, s);
+        if (splits > 1) launch_sum_slices_f32(sig32.as<float>(), part32.as<float>(), splits, ts.n, 0, s);
+        launch_f32_to_f64(y, sig32.as<float>(), ts.n, s);
+    }
+    DMRG_HIP(hipEventRecord(ctx->ev1, s));
+    DMRG_HIP(hipEventSynchronize(ctx->ev1));
+    float ms = 0;
+    DMRG_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (flops) *flops += pass1.model_flops + pass2.model_flops;
+    if (secs) *secs += ms * 1e-3;
+}
+
+void State::build_diag() {
+    prepare();
+    if (diag_ok) return;
+    hipStream_t s = ctx->stream;
+    const int j = center;
+    const int nch = int(mpo->chans[j + 1].size());
+    const int nq = int(ts.q.size());
+    std::vector<int> y0;
+    for (int y = 0; y < nch; ++y)
+        if (mpo->chan_dq[j + 1][y] == QN{0, 0}) y0.push_back(y);
+    std::vector<int64_t> sb(nq), eb(nq);
+    int64_t ns = 0, ne = 0;
+    for (int iq = 0; iq < nq; ++iq) {
+        sb[iq] = ns;
+        eb[iq] = ne;
+        ns += ts.sys[iq].dim;
+        ne += ts.env[iq].dim;
+    }
+    const int ny = int(y0.size());
+    DevBuf Ds(std::max<int64_t>(1, ny * ns) * sizeof(double), s);
+    DevBuf De(std::max<int64_t>(1, ny * ne) * sizeof(double), s);
+    launch_fill(Ds.as<double>(), 0.0, ny * ns, s);
+    launch_fill(De.as<double>(), 0.0, ny * ne, s);
+    std::vector<DiagItem> items;
+    for (int a = 0; a < ny; ++a) {
+        const int y = y0[a];
+        for (int iq = 0; iq < nq; ++iq) {
+            for (const Seg& sg : ts.sys[iq].segs) {
+                const int ri = Y.row(y, sg.st, sg.st);
+                if (ri < 0) continue;
+                const BRow& r = Y.rows[ri];
+                const int bi = r.lay->by_in[sg.sec];
+                if (bi < 0) continue;
+                const OpBlock& blk = r.lay->blocks[bi];
+                items.push_back({Y.buf.as<double>() + r.off + blk.off, blk.cols, sg.dim,
+                                 Ds.as<double>() + a * ns + sb[iq] + sg.off});
+            }
+            for (const Seg& sg : ts.env[iq].segs) {
+                const int ri = Z.row(y, sg.st, sg.st);
+                if (ri < 0) continue;
+                const BRow& r = Z.rows[ri];
+                const int bi = r.lay->by_in[sg.sec];
+                if (bi < 0) continue;
+                const OpBlock& blk = r.lay->blocks[bi];
+                items.push_back({Z.buf.as<double>() + r.off + blk.off, blk.cols, sg.dim,
+                                 De.as<double>() + a * ne + eb[iq] + sg.off});
+            }
+        }
+    }
+    DevBuf di(std::max<size_t>(1, items.size()) * sizeof(DiagItem), s);
+    if (!items.empty()) {
+        DMRG_HIP(hipMemcpyAsync(di.p, items.data(), items.size() * sizeof(DiagItem), hipMemcpyHostToDevice, s));
+        launch_diag_gather(di.as<DiagItem>(), int(items.size()), s);
+    }
+    diag.alloc(std::max<int64_t>(1, ts.n) * sizeof(double), s);
+    GemmList Lg;
+    std::vector<UTerm> terms;
+    for (int iq = 0; iq < nq; ++iq) {
+        terms.clear();
+        if (ny > 0)
+            terms.push_back({0, sb[iq], int(ns), true, 1, eb[iq], int(ne), false, ny, 1.0, false});
+        add_unit(Lg, 2, ts.off[iq], ts.env[iq].dim, ts.sys[iq].dim, ts.env[iq].dim, 0, terms);
+    }
+    Bases b{};
+    b.p[0] = Ds.p;
+    b.p[1] = De.p;
+    b.p[2] = diag.p;
+    int64_t sz[kMaxBufs] = {elems(Ds), elems(De), elems(diag)};
+    run_list(Lg, Prec::F64, b, s, sz);
+    DMRG_HIP(hipStreamSynchronize(s));
+    diag_ok = true;
+}
+
+// ---------------------------------------------------------------------------
+// Davidson + truncation + decimation: one two-site step
+
+namespace {
+
+struct DavOut {
+    double theta, rnorm;
+    int iters;
+};
+
+DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& stats) {
+    hipStream_t s = st.ctx->stream;
+    const int ms = std::max(2, std::min(o.dav_max_space, 40));
+    const int keep = std::max(1, std::min(o.dav_keep, ms - 1));
+    DevBuf V(sizeof(double) * n * ms, s), W(sizeof(double) * n * ms, s);
+    DevBuf r(sizeof(double) * n, s), t(sizeof(double) * n, s), xr(sizeof(double) * n, s),
+        wr(sizeof(double) * n, s), scr(sizeof(double) * n * keep, s);
+    Dots dots;
+    dots.init(s);
+    double* Vp = V.as<double>();
+    double* Wp = W.as<double>();
+    Prec prec = o.prec;
+    auto apply = [&](const double* in, double* out) {
+        st.sigma(in, out, prec, &stats.sigma_flops, &stats.sigma_seconds);
+        stats.sigma_calls++;
+    };
+    // normalized start
+    double nx = std::sqrt(dots.run(x, 0, 1, x, n, s)[0]);
+    check_finite(nx, "Davidson start vector");
+    require(nx > 0, "Davidson start vector is zero", E_NUMERIC);
+    launch_copy(Vp, x, n, s);
+    launch_scale(Vp, 1.0 / nx, n, s);
+    apply(Vp, Wp);
+    int k = 1, napply = 1;
+    std::vector<double> G(size_t(ms) * ms, 0.0);
+    G[0] = dots.run(Vp, 0, 1, Wp, n, s)[0];
+    std::vector<double> w, U;
+    DavOut out{0, 0, 0};
+    bool refined = (prec == Prec::F64);
+    while (true) {
+        std::vector<double> Gk(size_t(k) * k);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) Gk[a * k + b] = 0.5 * (G[a * ms + b] + G[b * ms + a]);
+        sym_eig(k, Gk, w, U);
+        const double theta = w[0];
+        check_finite(theta, "Rayleigh quotient");
+        Coefs cu{};
+        for (int a = 0; a < k; ++a) cu.c[a] = U[a * k + 0];
+        launch_lincomb(xr.as<double>(), Vp, n, k, cu, n, s);
+        launch_lincomb(wr.as<double>(), Wp, n, k, cu, n, s);
+        launch_residual(r.as<double>(), wr.as<double>(), xr.as<double>(), theta, n, s);
+        const double rn = std::sqrt(dots.run(r.as<double>(), 0, 1, r.as<double>(), n, s)[0]);
+        check_finite(rn, "Davidson residual");
+        out = {theta, rn, napply};
+        if (!refined && o.refine_tol > 0 && rn <= o.refine_tol) {
+            // low-precision phase done: restart from the Ritz vector in FP64
+            prec = Prec::F64;
+            refined = true;
+            launch_copy(Vp, xr.as<double>(), n, s);
+            apply(Vp, Wp);
+            ++napply;
+            k = 1;
+            G[0] = dots.run(Vp, 0, 1, Wp, n, s)[0];
+            continue;
+        }
+        const bool low = !refined && o.refine_tol > 0;
+        if ((rn <= o.dav_tol && !low) || napply >= o.dav_max_iter) break;
+        if (k >= ms) {
+            // thick restart from the `keep` lowest Ritz vectors
+            for (int i = 0; i < keep; ++i) {
+                Coefs c{};
+                for (int a = 0; a < k; ++a) c.c[a] = U[a * k + i];
+                launch_lincomb(scr.as<double>() + int64_t(i) * n, Vp, n, k, c, n, s);
+            }
+            for (int i = 0; i < keep; ++i) launch_copy(Vp + int64_t(i) * n, scr.as<double>() + int64_t(i) * n, n, s);
+            for (int i = 0; i < keep; ++i) {
+                Coefs c{};
+                for (int a = 0; a < k; ++a) c.c[a] = U[a * k + i];
+                launch_lincomb(scr.as<double>() + int64_t(i) * n, Wp, n, k, c, n, s);
+            }
+            for (int i = 0; i < keep; ++i) launch_copy(Wp + int64_t(i) * n, scr.as<double>() + int64_t(i) * n, n, s);
+            std::fill(G.begin(), G.end(), 0.0);
+            for (int i = 0; i < keep; ++i) G[i * ms + i] = w[i];
+            k = keep;
+        }
+        launch_precond(t.as<double>(), r.as<double>(), st.diag.as<double>(), theta, n, s);
+        for (int pass = 0; pass < 2; ++pass) {
+            const auto& c = dots.run(Vp, n, k, t.as<double>(), n, s);
+            Coefs cc{};
+            for (int a = 0; a < k; ++a) cc.c[a] = c[a];
+            launch_axpy_many(t.as<double>(), Vp, n, k, cc, n, s);
+        }
+        const double nt = std::sqrt(dots.run(t.as<double>(), 0, 1, t.as<double>(), n, s)[0]);
+        check_finite(nt, "Davidson correction");
+        if (nt < 1e-14) break;
+        launch_copy(Vp + int64_t(k) * n, t.as<double>(), n, s);
+        launch_scale(Vp + int64_t(k) * n, 1.0 / nt, n, s);
+        apply(Vp + int64_t(k) * n, Wp + int64_t(k) * n);
+        ++napply;
+        const auto& g = dots.run(Vp, n, k + 1, Wp + int64_t(k) * n, n, s);
+        for (int a = 0; a <= k; ++a) {
+            G[a * ms + k] = g[a];
+            G[k * ms + a] = g[a];
+        }
+        ++k;
+    }
+    launch_copy(x, xr.as<double>(), n, s);
+    DMRG_HIP(hipStreamSynchronize(s));
+    out.iters = napply;
+    return out;
+}
+
+}  // namespace
+
+double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt) {
+    const int K = mpo->K;
+    const int j = center;
+    hipStream_t s = ctx->stream;
+    prepare();
+    build_diag();
+    DavOut dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
+    stt.theta = dv.theta;
+    stt.dav_iters += dv.iters;
+
+    // sector-wise SVD of psi_q (rows sys, cols env)
+    const int nq = int(ts.q.size());
+    std::vector<std::pair<const double*, std::pair<int, int>>> mats;
+    for (int iq = 0; iq < nq; ++iq)
+        mats.push_back({psi.as<double>() + ts.off[iq], {ts.sys[iq].dim, ts.env[iq].dim}});
+    std::vector<SvdOut> outs;
+    DevBuf work, info;
+    svd_batch(ctx, mats, outs, work, info);
+    std::vector<std::vector<double>> sv(nq);
+    for (int iq = 0; iq < nq; ++iq) {
+        sv[iq].resize(outs[iq].r);
+        if (outs[iq].r > 0)
+            DMRG_HIP(hipMemcpyAsync(sv[iq].data(), work.as<double>() + outs[iq].s_off,
+                                    sizeof(double) * outs[iq].r, hipMemcpyDeviceToHost, s));
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+    struct Ent {
+        double v;
+        int iq, i;
+    };
+    std::vector<Ent> pool;
+    for (int iq = 0; iq < nq; ++iq)
+        for (int i = 0; i < outs[iq].r; ++i) pool.push_back({sv[iq][i], iq, i});
+    require(!pool.empty(), "two-site vector has no sector", E_STATE);
+    std::stable_sort(pool.begin(), pool.end(), [](const Ent& a, const Ent& b) {
+        if (a.v != b.v) return a.v > b.v;
+        if (a.iq != b.iq) return a.iq < b.iq;
+        return a.i < b.i;
+    });
+    const double smax = pool[0].v;
+    size_t nkeep = 0;
+    while (nkeep < pool.size() && nkeep < size_t(M) && pool[nkeep].v > o.svd_cutoff * smax) ++nkeep;
+    double disc = 0;
+    for (size_t i = nkeep; i < pool.size(); ++i) disc += pool[i].v * pool[i].v;
+    stt.discarded = std::max(stt.discarded, disc);
+    std::vector<int> kept(nq, 0);
+    for (size_t i = 0; i < nkeep; ++i) kept[pool[i].iq]++;
+    std::vector<std::pair<QN, int>> nb;
+    for (int iq = 0; iq < nq; ++iq)
+        if (kept[iq] > 0) nb.push_back({ts.q[iq], kept[iq]});
+    set_bond(j + 1, nb);
+    stt.max_bond = std::max(stt.max_bond, bonds[j + 1].total);
+
+    // new site tensors: U_kept (LEFT form over bond j+1), S V^T_kept (RIGHT form)
+    int maxr = 1;
+    for (auto& o2 : outs) maxr = std::max(maxr, o2.r);
+    std::vector<int> iota_h(maxr);
+    std::iota(iota_h.begin(), iota_h.end(), 0);
+    DevBuf iota_d(sizeof(int) * maxr, s);
+    DMRG_HIP(hipMemcpyAsync(iota_d.p, iota_h.data(), sizeof(int) * maxr, hipMemcpyHostToDevice, s));
+    Merged Lf, Rf;
+    Lf.form = 1;
+    Rf.form = 2;
+    for (int iq = 0; iq < nq; ++iq) {
+        if (kept[iq] == 0) continue;
+        Lf.idx[ts.q[iq]] = int(Lf.q.size());
+        Lf.q.push_back(ts.q[iq]);
+        Lf.rows.push_back(ts.sys[iq].dim);
+        Lf.cols.push_back(kept[iq]);
+        Lf.off.push_back(Lf.size);
+        Lf.size += int64_t(ts.sys[iq].dim) * kept[iq];
+        Rf.idx[ts.q[iq]] = int(Rf.q.size());
+        Rf.q.push_back(ts.q[iq]);
+        Rf.rows.push_back(kept[iq]);
+        Rf.cols.push_back(ts.env[iq].dim);
+        Rf.off.push_back(Rf.size);
+        Rf.size += int64_t(kept[iq]) * ts.env[iq].dim;
+    }
+    Lf.buf.alloc(std::max<int64_t>(1, Lf.size) * sizeof(double), s);
+    Rf.buf.alloc(std::max<int64_t>(1, Rf.size) * sizeof(double), s);
+    double* w = work.as<double>();
+    for (int iq = 0; iq < nq; ++iq) {
+        if (kept[iq] == 0) continue;
+        const SvdOut& so = outs[iq];
+        const int li = Lf.find(ts.q[iq]);
+        const double* sc = w + so.s_off;
+        // U part (rows x kept) from Um (rows x r); V^T part (kept x cols) from Vt
+        launch_gather_cols(Lf.buf.as<double>() + Lf.off[li], kept[iq], w + so.u_off, so.r,
+                           iota_d.as<int>(), forward ? nullptr : sc, so.rows, kept[iq], s);
+        launch_gather_rows(Rf.buf.as<double>() + Rf.off[li], so.cols, w + so.v_off, so.cols,
+                           iota_d.as<int>(), forward ? sc : nullptr, kept[iq], so.cols, s);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+
+    const bool last = forward ? (j == K - 2) : (j == 0);
+    if (forward) {
+        if (!last) {
+            L[j + 1] = decimate_left(Y, j, Lf);
+        }
+        site[j] = std::move(Lf);
+        site[j + 1] = std::move(Rf);
+        release_workspace();
+        if (!last) {
+            center = j + 1;
+            // psi' = C (x) B_{j+2}: rows (q, t), cols env of bond j+3
+            ts = make_two_site(bonds[j + 1], bonds[j + 3]);
+            psi.alloc(std::max<int64_t>(1, ts.n) * sizeof(double), s);
+            launch_fill(psi.as<double>(), 0.0, ts.n, s);
+            const Merged& C = site[j + 1];
+            const Merged& B = site[j + 2];
+            GemmList Lg;
+            std::vector<UTerm> terms;
+            for (int iq = 0; iq < int(ts.q.size()); ++iq) {
+                const int ib = B.find(ts.q[iq]);
+                if (ib < 0) continue;
+                for (const Seg& sg : ts.sys[iq].segs) {
+                    const QN qc = bonds[j + 1].q[sg.sec];
+                    const int ic = C.find(qc);
+                    const Space es = env_space(bonds[j + 2], qc);
+                    const Seg& cs = es.segs[es.seg_of[sg.st]];
+                    terms.clear();
+                    terms.push_back({0, C.off[ic] + cs.off, C.cols[ic], false, 1, B.off[ib],
+                                     B.cols[ib], false, cs.dim, 1.0, true});
+                    add_unit(Lg, 2, ts.off[iq] + int64_t(sg.off) * ts.env[iq].dim, ts.env[iq].dim,
+                             sg.dim, ts.env[iq].dim, 0, terms);
+                }
+            }
+            Bases b{};
+            b.p[0] = C.buf.p;
+            b.p[1] = B.buf.p;
+            b.p[2] = psi.p;
+            int64_t sz[kMaxBufs] = {elems(C.buf), elems(B.buf), elems(psi)};
+            run_list(Lg, Prec::F64, b, s, sz);
+            DMRG_HIP(hipStreamSynchronize(s));
+        } else {
+            form_center_from_pair(site[j], site[j + 1]);
+        }
+    } else {
+        // Rf = V^T (right-canonical B_{j+1}), Lf = U S (center on site j)
+        if (!last) {
+            R[j + 1] = decimate_right(Z, j + 1, Rf);
+        }
+        site[j] = std::move(Lf);
+        site[j + 1] = std::move(Rf);
+        release_workspace();
+        if (!last) {
+            center = j - 1;
+            // psi' = A_{j-1} (x) C: rows sys of bond j-1, cols (s, q)
+            ts = make_two_site(bonds[j - 1], bonds[j + 1]);
+            psi.alloc(std::max<int64_t>(1, ts.n) * sizeof(double), s);
+            launch_fill(psi.as<double>(), 0.0, ts.n, s);
+            const Merged& A = site[j - 1];
+            const Merged& C = site[j];
+            GemmList Lg;
+            std::vector<UTerm> terms;
+            for (int iq = 0; iq < int(ts.q.size()); ++iq) {
+                const int ia = A.find(ts.q[iq]);
+                if (ia < 0) continue;
+                for (const Seg& sg : ts.env[iq].segs) {
+                    const QN qc = bonds[j + 1].q[sg.sec];
+                    const int ic = C.find(qc);
+                    const Space ss = sys_space(bonds[j], qc);
+                    const Seg& cs = ss.segs[ss.seg_of[sg.st]];
+                    terms.clear();
+                    terms.push_back({0, A.off[ia], A.cols[ia], false, 1,
+                                     C.off[ic] + int64_t(cs.off) * C.cols[ic], C.cols[ic], false,
+                                     cs.dim, 1.0, true});
+                    add_unit(Lg, 2, ts.off[iq] + sg.off, ts.env[iq].dim, ts.sys[iq].dim, sg.dim, 0,
+                             terms);
+                }
+            }
+            Bases b{};
+            b.p[0] = A.buf.p;
+            b.p[1] = C.buf.p;
+            b.p[2] = psi.p;
+            int64_t sz[kMaxBufs] = {elems(A.buf), elems(C.buf), elems(psi)};
+            run_list(Lg, Prec::F64, b, s, sz);
+            DMRG_HIP(hipStreamSynchronize(s));
+        } else {
+            form_center_from_pair(site[j], site[j + 1]);
+        }
+    }
+    return dv.theta;
+}
+
+double State::energy() {
+    hipStream_t s = ctx->stream;
+    prepare();
+    const int64_t n = ts.n;
+    DevBuf y(sizeof(double) * std::max<int64_t>(1, n), s);
+    sigma(psi.as<double>(), y.as<double>(), Prec::F64, nullptr, nullptr);
+    Dots d;
+    d.init(s);
+    const double num = d.run(psi.as<double>(), 0, 1, y.as<double>(), n, s)[0];
+    const double den = d.run(psi.as<double>(), 0, 1, psi.as<double>(), n, s)[0];
+    check_finite(num, "energy");
+    require(den > 0, "zero state", E_NUMERIC);
+    return num / den;
+}
+
+void State::env_dense(int side, int bond, std::vector<double>& out) {
+    hipStream_t s = ctx->stream;
+    require(bond >= 0 && bond <= mpo->K, "bond out of range");
+    const Env* e = side == 0 ? L[bond].get() : R[bond].get();
+    require(e != nullptr, "environment not stored at that bond", E_STATE);
+    const BondL& b = bonds[bond];
+    std::vector<double> h(std::max<int64_t>(1, e->total));
+    DMRG_HIP(hipMemcpyAsync(h.data(), e->buf.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    const int m = b.total;
+    const size_t nch = mpo->chans[bond].size();
+    out.assign(nch * m * m, 0.0);
+    for (size_t x = 0; x < nch; ++x) {
+        const OpLayout& lay = b.layout(mpo->chan_dq[bond][x]);
+        for (const OpBlock& blk : lay.blocks)
+            for (int r = 0; r < blk.rows; ++r)
+                for (int c = 0; c < blk.cols; ++c)
+                    out[(x * m + b.off[blk.out] + r) * m + b.off[blk.in] + c] =
+                        h[e->off[x] + blk.off + int64_t(r) * blk.cols + c];
+    }
+}
+
+}  // namespace dmrg

@@ -1,0 +1,219 @@
+// DMRG engine: block-sparse MPS state on the GPU, renormalized operators,
+// the two-site sigma vector and the sweep (Chan et al., Secs. 2.1-2.5).
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include <chrono>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "core.h"
+
+namespace dmrg {
+
+// Cached operator layouts of a bond.
+struct BondL : Bond {
+    mutable std::map<QN, std::unique_ptr<OpLayout>> lay;
+    const OpLayout& layout(QN dq) const {
+        auto it = lay.find(dq);
+        if (it != lay.end()) return *it->second;
+        auto p = std::make_unique<OpLayout>(make_layout(*this, dq));
+        const OpLayout& r = *p;
+        lay[dq] = std::move(p);
+        return r;
+    }
+};
+
+// One fine segment of a merged two-site index: (local state, neighbour sector)
+struct Seg {
+    int st;   // local state 0..3
+    int sec;  // sector index in the neighbouring bond
+    int off;  // offset inside the merged dimension
+    int dim;
+};
+// Merged space of sector q: sys rows (Q_l = q - q_s, s) or env cols (t, Q_r = q + q_t)
+struct Space {
+    QN q;
+    int dim = 0;
+    std::vector<Seg> segs;
+    int seg_of[4] = {-1, -1, -1, -1};
+};
+Space sys_space(const Bond& left, QN q);
+Space env_space(const Bond& right, QN q);
+
+// Two-site vector layout at the pair (j, j+1).
+struct TwoSite {
+    std::vector<QN> q;
+    std::vector<Space> sys, env;
+    std::vector<int64_t> off;
+    std::map<QN, int> idx;
+    int64_t n = 0;
+    int find(QN x) const {
+        auto it = idx.find(x);
+        return it == idx.end() ? -1 : it->second;
+    }
+};
+TwoSite make_two_site(const Bond& left, const Bond& right);
+
+// Site tensor merged by the sector of one of its bonds.
+//   LEFT  (left-canonical A_j): sectors of bond j+1, rows = sys space, cols = m_{j+1}(q)
+//   RIGHT (right-canonical B_j): sectors of bond j, rows = m_j(q), cols = env space
+struct Merged {
+    int form = 0;  // 1 LEFT, 2 RIGHT
+    std::vector<QN> q;
+    std::vector<int> rows, cols;
+    std::vector<int64_t> off;
+    std::map<QN, int> idx;
+    int64_t size = 0;
+    DevBuf buf;
+    int find(QN x) const {
+        auto it = idx.find(x);
+        return it == idx.end() ? -1 : it->second;
+    }
+};
+
+// Renormalized operators of a block at one bond: one block-sparse operator
+// per MPO channel, laid out by the channel's quantum-number shift.
+struct Env {
+    int bond = -1;
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    DevBuf buf;
+};
+
+// Blocked operators (Eq. prenormmatrix): for each (channel y, local sp <- s)
+// the bond operator sum_x c_x O_x, all with the same shift.
+struct BRow {
+    int y, sp, s;
+    QN dq;
+    int64_t off;
+    const OpLayout* lay;
+    int t_begin, t_end;  // terms in Blocked::terms
+    bool identity;       // a pure identity (costs no model flops)
+};
+struct Blocked {
+    int bond = -1;
+    int n_chan = 0;
+    std::vector<BRow> rows;
+    std::vector<std::pair<int, double>> terms;  // (source channel, coefficient)
+    std::vector<int> find;                      // [y*16 + sp*4 + s] -> row or -1
+    int64_t total = 0;
+    DevBuf buf;     // FP64
+    DevBuf buf32;   // FP32 copy for low-precision contractions
+    int row(int y, int sp, int s) const { return find[size_t(y) * 16 + sp * 4 + s]; }
+};
+
+// Host-built task list of the grouped GEMM kernel.
+struct GemmList {
+    std::vector<GemmTask> tasks;
+    std::vector<GemmTerm> terms;
+    DevBuf dtasks, dterms;
+    double flops = 0;        // all multiply-adds x2
+    double model_flops = 0;  // flops the model counts (identity terms excluded)
+    void clear() {
+        tasks.clear();
+        terms.clear();
+        flops = model_flops = 0;
+    }
+    void upload(hipStream_t s);
+    void launch(Prec p, const Bases& b, hipStream_t s) const;
+};
+// Check every access of a task list against the element counts of the
+// buffers it addresses (throws instead of letting a kernel fault).
+void validate_list(const GemmList& L, const int64_t* sizes);
+
+struct UTerm {
+    int a_buf;
+    int64_t a_off;
+    int lda;
+    bool ta;
+    int b_buf;
+    int64_t b_off;
+    int ldb;
+    bool tb;
+    int k;
+    double alpha;
+    bool model;  // counted by the flop model
+};
+// Add the output block C[m x n] (buffer c_buf, offset c_off, ldc) with the
+// given terms, tiled into kTile x kTile tasks.  With splits > 1 the term list
+// of every tile is cut into `splits` parts writing to slices c_off + i*slice.
+void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
+              const std::vector<UTerm>& terms, int splits = 1, int64_t slice = 0);
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    rocblas_handle blas = nullptr;
+    std::string err;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct SweepOpts {
+    Prec prec = Prec::F64;
+    double dav_tol = 1e-9;
+    int dav_max_iter = 200;
+    int dav_max_space = 24;
+    int dav_keep = 4;
+    double svd_cutoff = 1e-12;
+    double refine_tol = 0.0;
+};
+
+struct StepStats {
+    double theta = 0, discarded = 0, sigma_flops = 0, sigma_seconds = 0;
+    int64_t sigma_calls = 0, dav_iters = 0;
+    int max_bond = 0;
+};
+
+// The MPS with its environments and the current two-site center.
+class State {
+  public:
+    State(Ctx* c, const MPO* m) : ctx(c), mpo(m) {}
+    Ctx* ctx;
+    const MPO* mpo;
+    std::vector<BondL> bonds;  // 0..K
+    std::vector<Merged> site;  // 0..K-1
+    std::vector<std::unique_ptr<Env>> L, R;
+    int center = 0;
+    TwoSite ts;
+    DevBuf psi;
+
+    // step workspace, valid for the current center
+    bool prepared = false;
+    Blocked Y, Z;
+    GemmList pass1, pass2;
+    std::vector<int64_t> t_off;  // T_y(q) offsets, [y * nq + iq], -1 if absent
+    int64_t t_total = 0;
+    int splits = 1;
+    DevBuf tbuf, part, psi32, sig32, tbuf32, part32;
+    DevBuf diag;
+    bool diag_ok = false;
+
+    // setup
+    void init_random(int M, const double* values, int64_t n_values);
+    void import_tensors(const std::vector<std::vector<std::pair<QN, int>>>& bonds_in,
+                        const double* values, int center_j);
+    // operations
+    void prepare();                      // blocking + task lists at the center
+    void sigma(const double* x, double* y, Prec p, double* flops, double* secs);
+    void build_diag();
+    double step(int M, bool forward, const SweepOpts& o, StepStats& st);
+    double energy();
+    void env_dense(int side, int bond, std::vector<double>& out);
+
+  private:
+    void set_bond(int k, const std::vector<std::pair<QN, int>>& secs);
+    std::unique_ptr<Env> trivial_env(int bond);
+    Blocked block_sys(int j, const Env& Lj);
+    Blocked block_env(int k, const Env& Rk1);
+    std::unique_ptr<Env> decimate_left(const Blocked& Yb, int j, const Merged& A);
+    std::unique_ptr<Env> decimate_right(const Blocked& Zb, int k, const Merged& B);
+    void form_center_from_pair(const Merged& A, const Merged& B);
+    void release_workspace();
+};
+
+}  // namespace dmrg

@@ -1,0 +1,487 @@
+// HIP kernels of the DMRG library (gfx950 / CDNA4).
+//
+//  * grouped_gemm: one workgroup per 64x64 output tile of a list of
+//    independent block GEMMs; each tile accumulates a list of terms
+//    alpha * op(A) op(B) (the K-concatenation over quantum-number blocks and
+//    MPO channels) in MFMA accumulators and writes once, so results are
+//    deterministic.  A and B slices are staged through LDS in K-steps of 16.
+//  * wsum: weighted sums of equally shaped operator buffers (blocking of
+//    renormalized operators with MPO coefficients).
+//  * FP64 vector kernels for Davidson (multi-dot with fixed-order partial
+//    sums, linear combinations, preconditioner) and small gathers.
+#include <hip/hip_runtime.h>
+
+#include "core.h"
+
+namespace dmrg {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short shrt4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS = 16;  // K-step staged in LDS
+
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+// Element load helpers for term operands, zero outside the slice.
+template <class T>
+__device__ inline T ld(const T* base, int64_t idx) {
+    return base[idx];
+}
+
+// LDS tile holder per compute type.
+template <int MODE>
+struct Cfg;
+// MODE 0: FP64 storage, FP64 MFMA
+template <>
+struct Cfg<0> {
+    using T = double;
+    using Acc = dbl4;
+};
+// MODE 1: FP32 storage, FP32 MFMA
+template <>
+struct Cfg<1> {
+    using T = float;
+    using Acc = flt4;
+};
+// MODE 2: FP32 storage, operands rounded to BF16, BF16 MFMA, FP32 accumulation
+template <>
+struct Cfg<2> {
+    using T = float;
+    using Acc = flt4;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__ tasks,
+                                                    const GemmTerm* __restrict__ terms,
+                                                    Bases bases) {
+    using T = typename Cfg<MODE>::T;
+    using Acc = typename Cfg<MODE>::Acc;
+    __shared__ T As[KS][kTile + 4];
+    __shared__ T Bs[KS][kTile + 4];
+
+    const GemmTask task = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wm = (wave >> 1) * 32;
+    const int wn = (wave & 1) * 32;
+    const int lr = lane & 15;   // row / column inside a 16x16 MFMA tile
+    const int lk = lane >> 4;   // k-group of the lane
+
+    Acc acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    for (int l = task.l_begin; l < task.l_end; ++l) {
+        const GemmTerm g = terms[l];
+        const T* A = static_cast<const T*>(bases.p[g.a_buf]) + g.a_off;
+        const T* B = static_cast<const T*>(bases.p[g.b_buf]) + g.b_off;
+        const T alpha = T(g.alpha);
+        const bool ta = g.flags & GT_TA;
+        const bool tb = g.flags & GT_TB;
+        for (int k0 = 0; k0 < g.k; k0 += KS) {
+            // stage A (m x KS) as As[kk][r] and B (KS x n) as Bs[kk][c]
+            for (int idx = tid; idx < kTile * KS; idx += 256) {
+                int r, kk;
+                if (!ta) {
+                    r = idx / KS;
+                    kk = idx % KS;
+                } else {
+                    kk = idx / kTile;
+                    r = idx % kTile;
+                }
+                T v = T(0);
+                if (r < task.m && k0 + kk < g.k)
+                    v = ta ? A[int64_t(k0 + kk) * g.lda + r] : A[int64_t(r) * g.lda + k0 + kk];
+                As[kk][r] = v * alpha;
+                int c, kb;
+                if (!tb) {
+                    kb = idx / kTile;
+                    c = idx % kTile;
+                } else {
+                    c = idx / KS;
+                    kb = idx % KS;
+                }
+                T u = T(0);
+                if (c < task.n && k0 + kb < g.k)
+                    u = tb ? B[int64_t(c) * g.ldb + k0 + kb] : B[int64_t(k0 + kb) * g.ldb + c];
+                Bs[kb][c] = u;
+            }
+            __syncthreads();
+            if constexpr (MODE == 0) {
+                for (int ks = 0; ks < KS; ks += 4) {
+                    double a0 = As[ks + lk][wm + lr];
+                    double a1 = As[ks + lk][wm + 16 + lr];
+                    double b0 = Bs[ks + lk][wn + lr];
+                    double b1 = Bs[ks + lk][wn + 16 + lr];
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                }
+            } else if constexpr (MODE == 1) {
+                for (int ks = 0; ks < KS; ks += 4) {
+                    float a0 = As[ks + lk][wm + lr];
+                    float a1 = As[ks + lk][wm + 16 + lr];
+                    float b0 = Bs[ks + lk][wn + lr];
+                    float b1 = Bs[ks + lk][wn + 16 + lr];
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+                }
+            } else {
+                // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
+                shrt4 a[2], b[2];
+                for (int i = 0; i < 2; ++i)
+                    for (int e = 0; e < 4; ++e) {
+                        a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
+                        b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
+                    }
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] =
+                            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+    // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds
+    // row 4 lk + e for the FP32 MFMAs but row 4 e + lk for the FP64 MFMA
+    // (checked on gfx950 with a probe of known products).
+    T* C = static_cast<T*>(bases.p[task.c_buf]) + task.c_off;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int r = wm + 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
+                const int c = wn + 16 * j + lr;
+                if (r < task.m && c < task.n) {
+                    T* p = C + int64_t(r) * task.ldc + c;
+                    T v = T(acc[i][j][e]);
+                    *p = task.accumulate ? *p + v : v;
+                }
+            }
+}
+
+__global__ void wsum_kernel(const SumItem* __restrict__ items, const SumTerm* __restrict__ terms) {
+    const SumItem it = items[blockIdx.x];
+    for (int64_t e = it.begin + threadIdx.x; e < it.end; e += blockDim.x) {
+        double acc = 0.0;
+        for (int t = it.t_begin; t < it.t_end; ++t) acc += terms[t].coef * terms[t].src[e];
+        it.out[e] = acc;
+    }
+}
+
+__global__ void multidot_kernel(const double* __restrict__ V, int64_t stride, int k,
+                                const double* __restrict__ w, int64_t n,
+                                double* __restrict__ partial) {
+    __shared__ double red[40][8];
+    double acc[40];
+    for (int i = 0; i < k; ++i) acc[i] = 0.0;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const double x = w[e];
+        for (int i = 0; i < k; ++i) acc[i] += V[i * stride + e] * x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < k; ++i) {
+        double v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[i][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+        for (int wv = 0; wv < int(blockDim.x >> 6); ++wv) s += red[threadIdx.x][wv];
+        partial[int64_t(blockIdx.x) * k + threadIdx.x] = s;
+    }
+}
+
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, int k,
+                                       double* __restrict__ out) {
+    // one thread per output; fixed order over blocks
+    const int i = threadIdx.x;
+    if (i < k) {
+        double s = 0.0;
+        for (int b = 0; b < kDotBlocks; ++b) s += partial[int64_t(b) * k + i];
+        out[i] = s;
+    }
+}
+
+__global__ void lincomb_kernel(double* __restrict__ out, const double* __restrict__ V,
+                               int64_t stride, int k, Coefs c, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += c.c[i] * V[i * stride + e];
+        out[e] = s;
+    }
+}
+
+__global__ void axpy_many_kernel(double* __restrict__ t, const double* __restrict__ V,
+                                 int64_t stride, int k, Coefs c, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        double s = t[e];
+        for (int i = 0; i < k; ++i) s -= c.c[i] * V[i * stride + e];
+        t[e] = s;
+    }
+}
+
+__global__ void precond_kernel(double* __restrict__ t, const double* __restrict__ r,
+                               const double* __restrict__ d, double theta, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        double den = theta - d[e];
+        if (fabs(den) < 1e-12) den = den < 0 ? -1e-12 : 1e-12;
+        t[e] = r[e] / den;
+    }
+}
+
+__global__ void residual_kernel(double* __restrict__ r, const double* __restrict__ wx,
+                                const double* __restrict__ x, double theta, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        r[e] = wx[e] - theta * x[e];
+}
+
+__global__ void scale_kernel(double* x, double a, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        x[e] *= a;
+}
+
+__global__ void copy_kernel(double* __restrict__ d, const double* __restrict__ s, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        d[e] = s[e];
+}
+
+__global__ void fill_kernel(double* d, double v, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        d[e] = v;
+}
+
+__global__ void to_f32_kernel(float* __restrict__ d, const double* __restrict__ s, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        d[e] = float(s[e]);
+}
+
+__global__ void to_bf16_kernel(uint16_t* __restrict__ d, const double* __restrict__ s, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        d[e] = f32_to_bf16_rne(float(s[e]));
+}
+
+__global__ void f32_to_f64_kernel(double* __restrict__ d, const float* __restrict__ s, int64_t n) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x)
+        d[e] = double(s[e]);
+}
+
+template <class T>
+__global__ void sum_slices_kernel(T* __restrict__ out, const T* __restrict__ part, int ns,
+                                  int64_t n, int accumulate) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        T s = accumulate ? out[e] : T(0);
+        for (int i = 0; i < ns; ++i) s += part[int64_t(i) * n + e];
+        out[e] = s;
+    }
+}
+
+__global__ void diag_gather_kernel(const DiagItem* __restrict__ items) {
+    const DiagItem it = items[blockIdx.x];
+    for (int i = threadIdx.x; i < it.len; i += blockDim.x)
+        it.dst[i] = it.src[int64_t(i) * (it.ld + 1)];
+}
+
+__global__ void gather_cols_kernel(double* __restrict__ dst, int dld, const double* __restrict__ src,
+                                   int sld, const int* __restrict__ cols,
+                                   const double* __restrict__ scale, int nrow, int ncol) {
+    const int64_t total = int64_t(nrow) * ncol;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e / ncol), c = int(e % ncol);
+        double v = src[int64_t(r) * sld + cols[c]];
+        if (scale) v *= scale[c];
+        dst[int64_t(r) * dld + c] = v;
+    }
+}
+
+__global__ void gather_rows_kernel(double* __restrict__ dst, int dld, const double* __restrict__ src,
+                                   int sld, const int* __restrict__ rows,
+                                   const double* __restrict__ scale, int nrow, int ncol) {
+    const int64_t total = int64_t(nrow) * ncol;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int r = int(e / ncol), c = int(e % ncol);
+        double v = src[int64_t(rows[r]) * sld + c];
+        if (scale) v *= scale[r];
+        dst[int64_t(r) * dld + c] = v;
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return unsigned(g);
+}
+
+}  // namespace
+
+void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                 const Bases& b, hipStream_t s) {
+    if (n_tasks <= 0) return;
+    const int64_t kMaxGrid = 1 << 30;
+    for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
+        const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
+        switch (p) {
+            case Prec::F64:
+                hipLaunchKernelGGL(grouped_gemm<0>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                break;
+            case Prec::F32:
+                hipLaunchKernelGGL(grouped_gemm<1>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                break;
+            case Prec::BF16:
+                hipLaunchKernelGGL(grouped_gemm<2>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                break;
+        }
+    }
+    DMRG_HIP(hipGetLastError());
+}
+
+void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(wsum_kernel, dim3(unsigned(n_items)), dim3(256), 0, s, items, terms);
+    DMRG_HIP(hipGetLastError());
+}
+
+void launch_multidot(const double* V, int64_t stride, int k, const double* w, int64_t n,
+                     double* partial, hipStream_t s) {
+    require(k >= 1 && k <= 40, "multidot: k out of range");
+    hipLaunchKernelGGL(multidot_kernel, dim3(kDotBlocks), dim3(256), 0, s, V, stride, k, w, n,
+                       partial);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_reduce_partials(const double* partial, int k, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, k, out);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_lincomb(double* out, const double* V, int64_t stride, int k, Coefs c, int64_t n,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, V, stride, k, c, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_axpy_many(double* t, const double* V, int64_t stride, int k, Coefs c, int64_t n,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(axpy_many_kernel, dim3(grid_for(n)), dim3(256), 0, s, t, V, stride, k, c, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_precond(double* t, const double* r, const double* diag, double theta, int64_t n,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(precond_kernel, dim3(grid_for(n)), dim3(256), 0, s, t, r, diag, theta, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_residual(double* r, const double* wx, const double* x, double theta, int64_t n,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, s, r, wx, x, theta, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_scale(double* x, double a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, a, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_copy(double* d, const double* src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, d, src, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_fill(double* d, double v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, d, v, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_to_f32(float* d, const double* src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, d, src, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_to_bf16(uint16_t* d, const double* src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, d, src, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_f32_to_f64(double* d, const float* src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(f32_to_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, d, src, n);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_sum_slices(double* out, const double* part, int ns, int64_t n, int accumulate,
+                       hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(sum_slices_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, out, part, ns,
+                       n, accumulate);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_sum_slices_f32(float* out, const float* part, int ns, int64_t n, int accumulate,
+                           hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(sum_slices_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, out, part, ns,
+                       n, accumulate);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_diag_gather(const DiagItem* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return;
+    hipLaunchKernelGGL(diag_gather_kernel, dim3(n_items), dim3(64), 0, s, items);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_gather_cols(double* dst, int dld, const double* src, int sld, const int* cols,
+                        const double* scale, int nrow, int ncol, hipStream_t s) {
+    const int64_t n = int64_t(nrow) * ncol;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, dld, src, sld,
+                       cols, scale, nrow, ncol);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_gather_rows(double* dst, int dld, const double* src, int sld, const int* rows,
+                        const double* scale, int nrow, int ncol, hipStream_t s) {
+    const int64_t n = int64_t(nrow) * ncol;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, dld, src, sld,
+                       rows, scale, nrow, ncol);
+    DMRG_HIP(hipGetLastError());
+}
+
+void DevBuf::alloc(size_t b, hipStream_t st) {
+    free();
+    s = st;
+    bytes = b;
+    if (b == 0) return;
+    hipError_t e = hipMallocAsync(&p, b, st);
+    if (e != hipSuccess) {
+        p = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        throw Error(e == hipErrorOutOfMemory ? E_NOMEM : E_HIP,
+                    "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+}
+void DevBuf::free() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    bytes = 0;
+}
+
+}  // namespace dmrg

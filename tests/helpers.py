@@ -1,0 +1,88 @@
+"""Conversions between the oracle's dense tensors and the library's layouts.
+
+Test infrastructure only.  The oracle keeps dense arrays with a (N, 2Sz)
+label per bond state (sorted by label); the library uses the layouts
+documented in include/dmrg.h (fine blocks for site tensors, merged sectors
+for two-site vectors).  Nothing here does any of the method's arithmetic.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+SITE_QN = [(0, 0), (1, 1), (1, -1), (2, 0)]
+SYS_ORDER = [3, 1, 2, 0]
+
+
+def sectors(labels):
+    """Sorted [(N, 2Sz, dim)] of a label array (m, 2)."""
+    out = {}
+    for n, s in np.asarray(labels).reshape(-1, 2):
+        out[(int(n), int(s))] = out.get((int(n), int(s)), 0) + 1
+    return [(q[0], q[1], d) for q, d in sorted(out.items())]
+
+
+def _rows_of(labels, q):
+    return np.nonzero(np.all(np.asarray(labels) == q, axis=1))[0]
+
+
+def site_fine_blocks(T, lab_l, lab_r):
+    """Dense site tensor (m_l, 4, m_r) -> flat fine-block values."""
+    out = []
+    for n, s2, _ in sectors(lab_l):
+        rows = _rows_of(lab_l, (n, s2))
+        for s in range(4):
+            qr = (n + SITE_QN[s][0], s2 + SITE_QN[s][1])
+            cols = _rows_of(lab_r, qr)
+            if len(cols) == 0:
+                continue
+            out.append(T[np.ix_(rows, [s], cols)][:, 0, :].ravel())
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def two_site_sectors(lab_l, lab_r):
+    """Middle sectors q with nonempty sys and env spaces, sorted."""
+    ql = {tuple(x) for x in np.asarray(lab_l).reshape(-1, 2)}
+    qr = {tuple(x) for x in np.asarray(lab_r).reshape(-1, 2)}
+    cand = sorted({(a + SITE_QN[s][0], b + SITE_QN[s][1]) for a, b in ql for s in range(4)})
+    out = []
+    for q in cand:
+        sys_ok = any((q[0] - SITE_QN[s][0], q[1] - SITE_QN[s][1]) in ql for s in range(4))
+        env_ok = any((q[0] + SITE_QN[t][0], q[1] + SITE_QN[t][1]) in qr for t in range(4))
+        if sys_ok and env_ok:
+            out.append(q)
+    return out
+
+
+def merged_index(lab_l, lab_r):
+    """Flat positions of the merged layout inside the dense (m_l,4,4,m_r) array."""
+    lab_l, lab_r = np.asarray(lab_l), np.asarray(lab_r)
+    ml, mr = len(lab_l), len(lab_r)
+    idx = []
+    for q in two_site_sectors(lab_l, lab_r):
+        rows = []  # (a, s) in order of Q_l ascending (a ascending)
+        for a in range(ml):
+            for s in range(4):
+                if (lab_l[a][0] + SITE_QN[s][0], lab_l[a][1] + SITE_QN[s][1]) == q:
+                    rows.append((a, s))
+        cols = []  # (t, b), t-major
+        for t in range(4):
+            for b in range(mr):
+                if (lab_r[b][0] - SITE_QN[t][0], lab_r[b][1] - SITE_QN[t][1]) == q:
+                    cols.append((t, b))
+        for a, s in rows:
+            for t, b in cols:
+                idx.append(((a * 4 + s) * 4 + t) * mr + b)
+    return np.array(idx, dtype=np.int64), (ml, 4, 4, mr)
+
+
+def dense_to_merged(psi, lab_l, lab_r):
+    idx, shape = merged_index(lab_l, lab_r)
+    return np.asarray(psi).reshape(-1)[idx]
+
+
+def merged_to_dense(vec, lab_l, lab_r):
+    idx, shape = merged_index(lab_l, lab_r)
+    out = np.zeros(int(np.prod(shape)))
+    out[idx] = vec
+    return out.reshape(shape)
