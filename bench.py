@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Benchmark of the two-site DMRG hot path on one MI355X.
+
+Workload (default): the K=36, N=36, M=1024 chain molecule (integral seed
+1003).  Setup, untimed: build the MPO, draw the random initial MPS, move the
+center to the middle pair (17, 18) by exact SVD splits, run the warm-up
+steps.  A timed step is one complete two-site DMRG step at the middle bond:
+blocking of the renormalized operators, Davidson with the sigma vector,
+sector-wise SVD truncation to M, environment update and the next guess.
+Steps alternate between the pairs (17, 18) forward and (18, 19) backward, so
+every step works at the middle of the chain.
+
+The metric value is the sigma-vector rate: model flops of all sigma calls in
+the timed steps divided by their GPU time (HIP events on the library stream).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA, TFLOP/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(P, ctx, m_sample, seed):
+    """Oracle sigma at the same Hamiltonian and middle pair, bond dimension
+    m_sample; rate = library model flops of that shape / oracle time."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import dmrg as od
+    from oracle import mpo as omp
+    from oracle.fermions import spin_orbital_integrals
+    from workloads import CONFIGS, config_integrals, mps_values
+
+    c = CONFIGS[3]
+    K = c["K"]
+    j = K // 2 - 1
+    I = config_integrals(3)
+    # model flops of this shape from the library
+    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
+    n = mpo.n_values(m_sample)
+    mps = P.Mps.random(ctx, mpo, m_sample, mps_values(seed, n))
+    for _ in range(j):
+        mps.move(True)
+    import torch
+    x = torch.randn(mps.psi_size(), device="cuda", dtype=torch.float64)
+    y = torch.zeros_like(x)
+    flops = mps.sigma(x, y)
+    bl, br = mps.bond(j), mps.bond(j + 2)
+    del mps
+    # the oracle on the same shape
+    t0 = time.time()
+    ts, vs = spin_orbital_integrals(I.h, I.v)
+    w = vs - vs.transpose(0, 1, 3, 2)
+    D = omp.bond_dims(K)
+    W1 = omp.dense_site(omp._build_site(K, j, ts, w, vs), D[j], D[j + 1])
+    W2 = omp.dense_site(omp._build_site(K, j + 1, ts, w, vs), D[j + 1], D[j + 2])
+    t_build = time.time() - t0
+    lab_l = od.labels_from_dims({(a, b): d for a, b, d in bl})
+    lab_r = od.labels_from_dims({(a, b): d for a, b, d in br})
+    rng = np.random.default_rng(0)
+    o = object.__new__(od.DMRG)
+    o.Lenv = {j: rng.standard_normal((D[j], len(lab_l), len(lab_l)))}
+    o.Renv = {j + 2: rng.standard_normal((D[j + 2], len(lab_r), len(lab_r)))}
+    o.Wd = {j: W1, j + 1: W2}
+    o.labels = {j: lab_l, j + 2: lab_r}
+    psi = rng.standard_normal((len(lab_l), 4, 4, len(lab_r))) * o.mask(j)
+    reps, t1 = 0, time.time()
+    while reps < 1 or time.time() - t1 < 8.0:
+        o.sigma(j, psi)
+        reps += 1
+    dt = time.time() - t1
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    return {
+        "value": flops * reps / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": ("oracle sigma (dense FP64 tensordot over MPO channels) at the middle pair of the "
+                   "K=36 workload with bond dimension %d instead of 1024 (%d psi elements), %d call(s) "
+                   "in %.1f s; rate = library model flops of the same shape / oracle time; MPO tensors "
+                   "of the two sites built in %.1f s (not timed)" % (m_sample, int(o.mask(j).sum()), reps,
+                                                                      dt, t_build)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--dav-tol", type=float, default=1e-7)
+    ap.add_argument("--dav-iter", type=int, default=24)
+    ap.add_argument("--sweep", action="store_true", help="also time one full sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-m", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1605_02611_amd as P
+    from workloads import CONFIGS, config_integrals, mps_values
+
+    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
+    c = CONFIGS[3]
+    K, M = c["K"], c["M"]
+    ctx = P.Context(0)
+    t0 = time.time()
+    I = config_integrals(3)
+    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
+    n = mpo.n_values(M)
+    mps = P.Mps.random(ctx, mpo, M, mps_values(c["seed"], n))
+    j = K // 2 - 1
+    for _ in range(j):
+        mps.move(True)
+    log("setup %.1fs: center %d, psi %d, D_mid %d" % (time.time() - t0, mps.center(), mps.psi_size(),
+                                                      mpo.bond_dims()[j + 1]))
+    opts = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
+                          refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    fwd = True
+    for w in range(args.warmup):
+        th, st = mps.step(M, fwd, opts)
+        log("warmup %d theta %.10f" % (w, th))
+        fwd = not fwd
+    torch.cuda.synchronize()
+    tot = dict(flops=0.0, sig=0.0, gemm=0.0, launches=0, calls=0, iters=0)
+    thetas = []
+    t1 = time.time()
+    for s in range(args.steps):
+        th, st = mps.step(M, fwd, opts)
+        fwd = not fwd
+        thetas.append(th)
+        tot["flops"] += st["sigma_flops"]
+        tot["sig"] += st["sigma_seconds"]
+        tot["gemm"] += st["gemm_seconds"]
+        tot["launches"] += st["gemm_launches"]
+        tot["calls"] += st["sigma_calls"]
+        tot["iters"] += st["dav_iters"]
+        log("step %d %s theta %.10f %.2fs sigma %d calls %.3fs" % (s, "fwd" if not fwd else "bwd", th,
+                                                                  st["seconds"], st["sigma_calls"],
+                                                                  st["sigma_seconds"]))
+    torch.cuda.synchronize()
+    wall = time.time() - t1
+    sigma_tflops = tot["flops"] / tot["sig"] / 1e12
+    gemm_tflops = tot["flops"] / tot["gemm"] / 1e12
+    out = {
+        "metric": "sigma-vector TFLOP/s + sweep seconds (K=36,M=1024); mixed vs FP64 at 1e-5 Eh",
+        "value": sigma_tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "chain molecule K=36 N=36 2Sz=0 M=1024 (integral seed 1003), "
+                               "two-site steps at the middle bond",
+                   "K": K, "M": M, "D_mid": int(mpo.bond_dims()[j + 1]), "psi_elements": mps.psi_size(),
+                   "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
+                   "precision": args.prec},
+        "sigma_calls": tot["calls"],
+        "sigma_model_flops": tot["flops"],
+        "step_tflops_wall": tot["flops"] / wall / 1e12,
+        "thetas": thetas,
+        "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK[args.prec],
+                     "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec], "traffic": None,
+                     "kernel": "grouped_gemm<%d,1>" % prec,
+                     "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
+                     "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},
+        "sweep_seconds": None,
+    }
+    if args.sweep:
+        # one full sweep from the middle: move to the left end, then sweep
+        while mps.center() > 0:
+            mps.move(False)
+        t2 = time.time()
+        stats, _ = mps.sweep(M, 1, opts)
+        out["sweep_seconds"] = time.time() - t2
+        out["sweep_energy"] = stats[0]["energy"]
+    else:
+        # projection: middle-step time x number of steps x mean(D)/D_mid
+        D = mpo.bond_dims()
+        frac = float(sum(D[1:K])) / (K - 1) / D[j + 1]
+        out["sweep_seconds_projected"] = wall / args.steps * 2 * (K - 1) * frac
+    if not args.no_cpu:
+        try:
+            out["cpu_baseline"] = cpu_baseline(P, ctx, args.cpu_m, c["seed"])
+        except Exception as e:  # report, do not hide
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

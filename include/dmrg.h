@@ -81,7 +81,8 @@ typedef struct dmrg_mps dmrg_mps;
  * needs the GPU then fails with DMRG_E_STATE. */
 dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out);
 void dmrg_ctx_destroy(dmrg_ctx* ctx);
-/* Text of the last error on ctx (never NULL; "" after success). */
+/* Text of the last error on ctx (never NULL; "" after success).  With
+ * ctx == NULL: why the last dmrg_ctx_create of this thread failed. */
 const char* dmrg_last_error(const dmrg_ctx* ctx);
 
 /* ---- MPO (Sec. 2.4, Eqs. Hdecomp, Sm, norm_complementary, prenormrule) --- */
@@ -118,8 +119,9 @@ void dmrg_mpo_free(dmrg_mpo* mpo);
 /* Number of FP64 values a random initial MPS of bond dimension M consumes. */
 dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n);
 /* Random initial MPS: sector dimensions from the fixed integer rule (full
- * dimension min(left count, right count, M), apportioned to M by largest
- * remainders, then made consistent between neighbouring bonds), blocks
+ * dimension min(left count, right count); M apportioned in proportion to it
+ * by largest remainders when the total exceeds M; then made consistent
+ * between neighbouring bonds; K <= 60), blocks
  * filled from `values` in fine-block order site by site, then made
  * right-canonical on the GPU.  The center is left at the pair (0, 1) with
  * its environments built. */
@@ -192,6 +194,8 @@ typedef struct {
     double sigma_flops;     /* model flops of all sigma calls */
     double sigma_seconds;   /* GPU time of all sigma calls */
     int64_t sigma_calls;
+    double gemm_seconds;    /* GPU time of the grouped-GEMM launches of sigma */
+    int64_t gemm_launches;  /* number of those launches (two per sigma) */
     int64_t dav_iters;      /* Davidson iterations summed over steps */
     int32_t max_bond;       /* largest bond dimension after the sweep */
     int32_t n_steps;
@@ -208,6 +212,10 @@ dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
 /* One two-site step at the current center (forward = 1 moves right). */
 dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
                       const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat);
+/* Move the center one pair right (forward = 1) or left without solving: the
+ * two-site vector is split exactly by SVD (singular values <= 1e-14 sigma_max
+ * dropped) and the environment on the side left behind is updated. */
+dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward);
 /* <Psi|H|Psi>/<Psi|Psi> of the current state, accumulated in FP64
  * (Eqs. transferop, energy_expect, at the center bond). */
 dmrg_status dmrg_energy(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* E);

@@ -48,8 +48,10 @@ def initial_bond_dims(K, n_elec, two_sz, M):
     """Sector dimensions of the random initial MPS (integer rule).
 
     full(Q) = min(#states of the left block with Q, #states of the right
-    block completing Q to the target, M); if the total exceeds M it is
-    apportioned by largest remainders: floor(M full(Q) / total) each, then
+    block completing Q to the target) (the largest Schmidt rank the sector
+    can have); if the total exceeds M, M is apportioned to the sectors in
+    proportion to full(Q) by largest remainders: floor(M full(Q) / total)
+    each, then
     one more state to the sectors with the largest remainders (ties by Q)
     until the total is M; empty sectors are dropped; then
     d_k(Q) <= sum_s d_{k-1}(Q - q_s) and d_k(Q) <= sum_s d_{k+1}(Q + q_s)
@@ -68,7 +70,7 @@ def initial_bond_dims(K, n_elec, two_sz, M):
                     continue
                 fl = comb(k, nu) * comb(k, nd)
                 fr = comb(K - k, ru) * comb(K - k, rd)
-                d[(nu + nd, nu - nd)] = min(fl, fr, M)
+                d[(nu + nd, nu - nd)] = min(fl, fr)
         tot = sum(d.values())
         if tot > M:
             # largest-remainder apportionment of M over the sectors

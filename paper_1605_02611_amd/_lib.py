@@ -35,7 +35,8 @@ class SweepOpts(C.Structure):
 class SweepStat(C.Structure):
     _fields_ = [("energy", c_double), ("discarded", c_double), ("seconds", c_double),
                 ("sigma_flops", c_double), ("sigma_seconds", c_double),
-                ("sigma_calls", c_int64), ("dav_iters", c_int64), ("max_bond", c_int32),
+                ("sigma_calls", c_int64), ("gemm_seconds", c_double), ("gemm_launches", c_int64),
+                ("dav_iters", c_int64), ("max_bond", c_int32),
                 ("n_steps", c_int32)]
 
 
@@ -70,6 +71,7 @@ SIGNATURES = {
     "dmrg_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, P(SweepOpts),
                           P(c_double), P(SweepStat)]),
     "dmrg_energy": (c_int, [c_void_p, c_void_p, c_void_p, P(c_double)]),
+    "dmrg_mps_move": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
 }
 
 _lib = None
@@ -80,6 +82,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that same runtime instead of a second copy from the ROCm install
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libdmrg.so is not built (run __graft_entry__.build() or "
                            "python -m paper_1605_02611_amd.build); there is no fallback")

@@ -52,7 +52,7 @@ class Context:
         h = C.c_void_p()
         st = self.lib.dmrg_ctx_create(device, stream, C.byref(h))
         if st != 0:
-            raise DmrgError(st, "dmrg_ctx_create failed")
+            raise DmrgError(st, "dmrg_ctx_create: " + self.lib.dmrg_last_error(None).decode())
         self.h = h
 
     def gemm(self, A, B, C, m, n, k, ta=False, tb=False, alpha=1.0, accumulate=False,
@@ -231,6 +231,9 @@ class Mps:
         self.ctx.check(self.lib.dmrg_step(self.ctx.h, self.h, self.mpo.h, M, int(bool(forward)),
                                           C.byref(opts), C.byref(th), C.byref(st)))
         return th.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
+
+    def move(self, forward=True):
+        self.ctx.check(self.lib.dmrg_mps_move(self.ctx.h, self.h, self.mpo.h, int(bool(forward))))
 
     def energy(self):
         e = C.c_double()

@@ -68,6 +68,8 @@ void use_device(const Ctx& c) {
 
 }  // namespace
 
+static thread_local std::string g_create_err;
+
 extern "C" {
 
 dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
@@ -98,12 +100,15 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
         }
         DMRG_HIP(hipEventCreate(&ctx->c.ev0));
         DMRG_HIP(hipEventCreate(&ctx->c.ev1));
+        DMRG_HIP(hipEventCreate(&ctx->c.ev2));
+        DMRG_HIP(hipEventCreate(&ctx->c.ev3));
         if (rocblas_create_handle(&ctx->c.blas) != rocblas_status_success)
             throw Error(E_HIP, "rocblas_create_handle failed");
         if (rocblas_set_stream(ctx->c.blas, ctx->c.stream) != rocblas_status_success)
             throw Error(E_HIP, "rocblas_set_stream failed");
     });
     if (st != DMRG_OK) {
+        g_create_err = ctx->c.err;
         dmrg_ctx_destroy(ctx);
         return st;
     }
@@ -122,11 +127,15 @@ void dmrg_ctx_destroy(dmrg_ctx* ctx) {
     if (ctx->c.blas) rocblas_destroy_handle(ctx->c.blas);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);
+    if (ctx->c.ev2) (void)hipEventDestroy(ctx->c.ev2);
+    if (ctx->c.ev3) (void)hipEventDestroy(ctx->c.ev3);
     if (ctx->c.own_stream && ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
     delete ctx;
 }
 
-const char* dmrg_last_error(const dmrg_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+const char* dmrg_last_error(const dmrg_ctx* ctx) {
+    return ctx ? ctx->c.err.c_str() : g_create_err.c_str();
+}
 
 dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K, int n_elec,
                            int two_sz, const dmrg_mpo_opts* opts, dmrg_mpo** out) {
@@ -296,9 +305,9 @@ dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const 
         const int64_t n = mps->st->ts.n;
         require(psi + n <= out || out + n <= psi, "psi and out overlap");
         use_device(ctx->c);
-        double f = 0, sec = 0;
-        mps->st->sigma(psi, out, Prec(prec), &f, &sec);
-        if (flops) *flops += f;
+        StepStats st;
+        mps->st->sigma(psi, out, Prec(prec), &st);
+        if (flops) *flops += st.sigma_flops;
     });
 }
 
@@ -400,6 +409,8 @@ dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, 
             stat->sigma_flops = s.sigma_flops;
             stat->sigma_seconds = s.sigma_seconds;
             stat->sigma_calls = s.sigma_calls;
+            stat->gemm_seconds = s.gemm_seconds;
+            stat->gemm_launches = s.gemm_launches;
             stat->dav_iters = s.dav_iters;
             stat->max_bond = s.max_bond;
             stat->n_steps = 1;
@@ -440,11 +451,29 @@ dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
                 stats[sw].sigma_flops = s.sigma_flops;
                 stats[sw].sigma_seconds = s.sigma_seconds;
                 stats[sw].sigma_calls = s.sigma_calls;
+                stats[sw].gemm_seconds = s.gemm_seconds;
+                stats[sw].gemm_launches = s.gemm_launches;
                 stats[sw].dav_iters = s.dav_iters;
                 stats[sw].max_bond = s.max_bond;
                 stats[sw].n_steps = step;
             }
         }
+    });
+}
+
+dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        use_device(ctx->c);
+        const int K = mpo->m->K;
+        const int j = mps->st->center;
+        require(forward ? j < K - 2 : j > 0, "center cannot move further that way", E_STATE);
+        SweepOpts o;
+        o.svd_cutoff = 1e-14;
+        StepStats s;
+        mps->st->step(1, forward != 0, o, s, false);
     });
 }
 

@@ -164,6 +164,9 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                  const Bases& bases, hipStream_t s);
+// same kernel, separate symbol for the two passes of the sigma vector
+void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                       const Bases& bases, hipStream_t s);
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]
 struct SumItem {
@@ -217,6 +220,22 @@ void launch_gather_cols(double* dst, int dld, const double* src, int sld, const 
                         const double* scale, int nrow, int ncol, hipStream_t s);
 void launch_gather_rows(double* dst, int dld, const double* src, int sld, const int* rows,
                         const double* scale, int nrow, int ncol, hipStream_t s);
+
+// batched one-sided Jacobi SVD of small row-major matrices (one workgroup each)
+struct SvdJob {
+    const double* src;
+    int rows, cols;
+    double* work;  // (m*n + n*n + n) doubles + n ints, m = max, n = min(rows, cols)
+    double* U;     // rows x r
+    double* S;     // r
+    double* Vt;    // r x cols
+    int* info;
+};
+inline int64_t svd_work_elems(int rows, int cols) {
+    const int64_t m = rows > cols ? rows : cols, n = rows > cols ? cols : rows;
+    return m * n + n * n + n + (n + 1) / 2 + 1;
+}
+void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // device memory: stream-ordered allocations

@@ -8,8 +8,12 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <set>
 
@@ -131,7 +135,10 @@ void GemmList::upload(hipStream_t s) {
 }
 
 void GemmList::launch(Prec p, const Bases& b, hipStream_t s) const {
-    launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
+    if (sigma_role)
+        launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
+    else
+        launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
@@ -638,6 +645,8 @@ std::vector<std::vector<U128>> binomials(int n) {
 
 // Integer rule for the sector dimensions of the random initial MPS.
 static std::vector<std::map<QN, int64_t>> initial_dims(int K, int N, int tsz, int M) {
+    // counts are exact up to K = 60 (products of binomials stay below 2^100)
+    require(K <= 60, "the initial-state rule is exact only for K <= 60");
     const int nu_t = (N + tsz) / 2, nd_t = (N - tsz) / 2;
     auto C = binomials(K);
     auto comb = [&](int n, int k) -> U128 { return (k < 0 || k > n) ? 0 : C[n][k]; };
@@ -650,30 +659,31 @@ static std::vector<std::map<QN, int64_t>> initial_dims(int K, int N, int tsz, in
                 if (ru < 0 || rd < 0 || ru > K - k || rd > K - k) continue;
                 U128 fl = sat_mul(comb(k, nu), comb(k, nd));
                 U128 fr = sat_mul(comb(K - k, ru), comb(K - k, rd));
-                U128 f = std::min(std::min(fl, fr), U128(M));
-                d[{nu + nd, nu - nd}] = int64_t(f);
+                d[{nu + nd, nu - nd}] = std::min(fl, fr);
             }
-        int64_t tot = 0;
+        U128 tot = 0;
         for (auto& kv : d) tot += kv.second;
-        if (tot > M) {
-            std::vector<std::pair<QN, int64_t>> num;  // M * full
-            std::map<QN, int64_t> nd;
+        std::map<QN, int64_t> nd;
+        if (tot > U128(M)) {
+            // largest-remainder apportionment of M in proportion to the counts
+            std::vector<std::pair<QN, U128>> num;  // M * full
             for (auto& [q, x] : d) {
-                num.push_back({q, int64_t(M) * x});
-                nd[q] = int64_t(M) * x / tot;
+                num.push_back({q, U128(M) * x});
+                nd[q] = int64_t(U128(M) * x / tot);
             }
             int64_t extra = M;
             for (auto& kv : nd) extra -= kv.second;
             std::stable_sort(num.begin(), num.end(), [&](const auto& a, const auto& b) {
-                const int64_t ra = a.second % tot, rb = b.second % tot;
+                const U128 ra = a.second % tot, rb = b.second % tot;
                 if (ra != rb) return ra > rb;
                 return a.first < b.first;
             });
             for (int64_t i = 0; i < extra && i < int64_t(num.size()); ++i) nd[num[i].first] += 1;
-            d = nd;
+        } else {
+            for (auto& [q, x] : d) nd[q] = int64_t(x);
         }
         std::map<QN, int64_t> pos;
-        for (auto& [q, x] : d)
+        for (auto& [q, x] : nd)
             if (x > 0) pos[q] = x;
         dims[k] = pos;
     }
@@ -817,9 +827,34 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
     work.alloc(std::max<int64_t>(1, tot) * sizeof(double), s);
     info.alloc(std::max<size_t>(1, mats.size()) * sizeof(rocblas_int), s);
     double* w = work.as<double>();
+    // small sectors: batched one-sided Jacobi kernel; large ones: rocSOLVER
+    static const int jmax = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 256;
+    std::vector<char> jac(mats.size(), 0);
+    std::vector<SvdJob> jobs;
+    int64_t jtot = 0;
+    for (size_t i = 0; i < mats.size(); ++i)
+        if (outs[i].r > 0 && outs[i].r <= jmax) {
+            jac[i] = 1;
+            jtot += svd_work_elems(outs[i].rows, outs[i].cols);
+        }
+    DevBuf jscr, djobs;
+    if (jtot > 0) {
+        jscr.alloc(jtot * sizeof(double), s);
+        int64_t pos = 0;
+        for (size_t i = 0; i < mats.size(); ++i) {
+            if (!jac[i]) continue;
+            const SvdOut& o = outs[i];
+            jobs.push_back({mats[i].first, o.rows, o.cols, jscr.as<double>() + pos, w + o.u_off,
+                            w + o.s_off, w + o.v_off, info.as<rocblas_int>() + i});
+            pos += svd_work_elems(o.rows, o.cols);
+        }
+        djobs.alloc(jobs.size() * sizeof(SvdJob), s);
+        DMRG_HIP(hipMemcpyAsync(djobs.p, jobs.data(), jobs.size() * sizeof(SvdJob), hipMemcpyHostToDevice, s));
+        launch_jacobi_svd(djobs.as<SvdJob>(), int(jobs.size()), s);
+    }
     for (size_t i = 0; i < mats.size(); ++i) {
         const SvdOut& o = outs[i];
-        if (o.r == 0) continue;
+        if (o.r == 0 || jac[i]) continue;
         launch_copy(w + o.a_off, mats[i].first, int64_t(o.rows) * o.cols, s);
         // row-major (rows x cols) == column-major (cols x rows) = A^T = Ut S Vt^T
         // so Um (row-major rows x r) is rocSOLVER's V output and Vt (row-major
@@ -837,7 +872,8 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
                                 hipMemcpyDeviceToHost, s));
     DMRG_HIP(hipStreamSynchronize(s));
     for (size_t i = 0; i < mats.size(); ++i)
-        if (outs[i].r > 0 && hinfo[i] != 0) throw Error(E_NUMERIC, "SVD did not converge");
+        if (outs[i].r > 0 && (jac[i] ? hinfo[i] < 0 : hinfo[i] != 0))
+            throw Error(E_NUMERIC, "SVD did not converge");
 }
 
 void State::init_random(int M, const double* values, int64_t n_values) {
@@ -1128,6 +1164,7 @@ void State::prepare() {
         int64_t sz2[kMaxBufs] = {t_total, Z.total, splits > 1 ? int64_t(splits) * ts.n : ts.n};
         validate_list(pass2, sz2);
     }
+    pass1.sigma_role = pass2.sigma_role = true;
     pass1.upload(s);
     pass2.upload(s);
     tbuf.alloc(std::max<int64_t>(1, t_total) * sizeof(double), s);
@@ -1137,11 +1174,11 @@ void State::prepare() {
     diag_ok = false;
 }
 
-void State::sigma(const double* x, double* y, Prec p, double* flops, double* secs) {
+void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
     prepare();
     hipStream_t s = ctx->stream;
-    DMRG_HIP(hipEventRecord(ctx->ev0, s));
     if (p == Prec::F64) {
+        DMRG_HIP(hipEventRecord(ctx->ev0, s));
         Bases b1{};
         b1.p[0] = Y.buf.p;
         b1.p[1] = const_cast<double*>(x);
@@ -1152,6 +1189,7 @@ void State::sigma(const double* x, double* y, Prec p, double* flops, double* sec
         b2.p[1] = Z.buf.p;
         b2.p[2] = splits > 1 ? part.p : static_cast<void*>(y);
         pass2.launch(Prec::F64, b2, s);
+        DMRG_HIP(hipEventRecord(ctx->ev2, s));
         if (splits > 1) launch_sum_slices(y, part.as<double>(), splits, ts.n, 0, s);
     } else {
         if (!Y.buf32.p) {
@@ -1164,6 +1202,7 @@ void State::sigma(const double* x, double* y, Prec p, double* flops, double* sec
             tbuf32.alloc(std::max<int64_t>(1, t_total) * sizeof(float), s);
             if (splits > 1) part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
         }
+        DMRG_HIP(hipEventRecord(ctx->ev0, s));
         launch_to_f32(psi32.as<float>(), x, ts.n, s);
         Bases b1{};
         b1.p[0] = Y.buf32.p;
@@ -1175,15 +1214,22 @@ void State::sigma(const double* x, double* y, Prec p, double* flops, double* sec
         b2.p[1] = Z.buf32.p;
         b2.p[2] = splits > 1 ? part32.p : sig32.p;
         pass2.launch(p, b2, s);
+        DMRG_HIP(hipEventRecord(ctx->ev2, s));
         if (splits > 1) launch_sum_slices_f32(sig32.as<float>(), part32.as<float>(), splits, ts.n, 0, s);
         launch_f32_to_f64(y, sig32.as<float>(), ts.n, s);
     }
     DMRG_HIP(hipEventRecord(ctx->ev1, s));
     DMRG_HIP(hipEventSynchronize(ctx->ev1));
-    float ms = 0;
-    DMRG_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (flops) *flops += pass1.model_flops + pass2.model_flops;
-    if (secs) *secs += ms * 1e-3;
+    if (st) {
+        float ms = 0, mg = 0;
+        DMRG_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        DMRG_HIP(hipEventElapsedTime(&mg, ctx->ev0, ctx->ev2));
+        st->sigma_flops += pass1.model_flops + pass2.model_flops;
+        st->sigma_seconds += ms * 1e-3;
+        st->gemm_seconds += mg * 1e-3;
+        st->gemm_launches += 2;
+        st->sigma_calls += 1;
+    }
 }
 
 void State::build_diag() {
@@ -1281,10 +1327,7 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
     double* Vp = V.as<double>();
     double* Wp = W.as<double>();
     Prec prec = o.prec;
-    auto apply = [&](const double* in, double* out) {
-        st.sigma(in, out, prec, &stats.sigma_flops, &stats.sigma_seconds);
-        stats.sigma_calls++;
-    };
+    auto apply = [&](const double* in, double* out) { st.sigma(in, out, prec, &stats); };
     // normalized start
     double nx = std::sqrt(dots.run(x, 0, 1, x, n, s)[0]);
     check_finite(nx, "Davidson start vector");
@@ -1298,6 +1341,7 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
     std::vector<double> w, U;
     DavOut out{0, 0, 0};
     bool refined = (prec == Prec::F64);
+    std::vector<double> rn_hist;
     while (true) {
         std::vector<double> Gk(size_t(k) * k);
         for (int a = 0; a < k; ++a)
@@ -1313,7 +1357,18 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
         const double rn = std::sqrt(dots.run(r.as<double>(), 0, 1, r.as<double>(), n, s)[0]);
         check_finite(rn, "Davidson residual");
         out = {theta, rn, napply};
-        if (!refined && o.refine_tol > 0 && rn <= o.refine_tol) {
+        // the low-precision residual cannot fall below ~u |theta| (u = unit
+        // roundoff of the contraction precision): refine once it reaches
+        // that floor, the requested tolerance, or stops decreasing
+        bool stalled = false;
+        if (!refined) {
+            rn_hist.push_back(rn);
+            const size_t h = rn_hist.size();
+            if (h >= 4) stalled = rn > 0.9 * std::min(rn_hist[h - 4], rn_hist[h - 3]);
+        }
+        const double u = prec == Prec::BF16 ? 0x1p-8 : 0x1p-24;
+        if (!refined && o.refine_tol > 0 &&
+            (rn <= std::max(o.refine_tol, 10.0 * u * std::fabs(theta)) || stalled)) {
             // low-precision phase done: restart from the Ritz vector in FP64
             prec = Prec::F64;
             refined = true;
@@ -1373,18 +1428,35 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
 
 }  // namespace
 
-double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt) {
+double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool solve) {
     const int K = mpo->K;
     const int j = center;
     hipStream_t s = ctx->stream;
-    prepare();
-    build_diag();
-    DavOut dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
-    stt.theta = dv.theta;
-    stt.dav_iters += dv.iters;
+    using clk = std::chrono::steady_clock;
+    auto sec = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+    const auto t0 = clk::now();
+    DavOut dv{0, 0, 0};
+    double sig0 = stt.sigma_seconds;
+    auto t1 = t0, t2 = t0;
+    if (solve) {
+        prepare();
+        t1 = clk::now();
+        build_diag();
+        t2 = clk::now();
+        dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
+        stt.theta = dv.theta;
+        stt.dav_iters += dv.iters;
+    } else {
+        // gauge move: split the current vector exactly
+        M = std::numeric_limits<int>::max();
+        t1 = t2 = t0;
+    }
+    const auto t3 = clk::now();
 
     // sector-wise SVD of psi_q (rows sys, cols env)
     const int nq = int(ts.q.size());
+    const int64_t ts_n_at_solve = ts.n;
+    const size_t ts_nq_at_solve = ts.q.size();
     std::vector<std::pair<const double*, std::pair<int, int>>> mats;
     for (int iq = 0; iq < nq; ++iq)
         mats.push_back({psi.as<double>() + ts.off[iq], {ts.sys[iq].dim, ts.env[iq].dim}});
@@ -1467,7 +1539,13 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt) {
     }
     DMRG_HIP(hipStreamSynchronize(s));
 
+    const auto t4 = clk::now();
     const bool last = forward ? (j == K - 2) : (j == 0);
+    if (!last && !solve) {
+        // the environment update needs only the blocked operators of one side
+        if (forward) Y = block_sys(j, *L[j]);
+        else Z = block_env(j + 1, *R[j + 2]);
+    }
     if (forward) {
         if (!last) {
             L[j + 1] = decimate_left(Y, j, Lf);
@@ -1555,6 +1633,17 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt) {
             form_center_from_pair(site[j], site[j + 1]);
         }
     }
+    if (std::getenv("DMRG_TRACE")) {
+        const auto t5 = clk::now();
+        fprintf(stderr,
+                "[dmrg] pair %d %s n=%lld sectors=%zu iters=%d theta=%.12f |r|=%.2e kept=%d disc=%.2e "
+                "block+lists %.3fs diag %.3fs davidson %.3fs (sigma %.3fs) svd %.3fs "
+                "update+next %.3fs total %.3fs\n",
+                j, forward ? "fwd" : "bwd", (long long)ts_n_at_solve, ts_nq_at_solve, dv.iters,
+                dv.theta, dv.rnorm, bonds[forward ? j + 1 : j + 1].total, stt.discarded, sec(t0, t1),
+                sec(t1, t2), sec(t2, t3), stt.sigma_seconds - sig0, sec(t3, t4), sec(t4, t5),
+                sec(t0, t5));
+    }
     return dv.theta;
 }
 
@@ -1563,7 +1652,7 @@ double State::energy() {
     prepare();
     const int64_t n = ts.n;
     DevBuf y(sizeof(double) * std::max<int64_t>(1, n), s);
-    sigma(psi.as<double>(), y.as<double>(), Prec::F64, nullptr, nullptr);
+    sigma(psi.as<double>(), y.as<double>(), Prec::F64, nullptr);
     Dots d;
     d.init(s);
     const double num = d.run(psi.as<double>(), 0, 1, y.as<double>(), n, s)[0];

@@ -118,6 +118,7 @@ struct GemmList {
         terms.clear();
         flops = model_flops = 0;
     }
+    bool sigma_role = false;  // launch under the sigma-vector kernel symbol
     void upload(hipStream_t s);
     void launch(Prec p, const Bases& b, hipStream_t s) const;
 };
@@ -150,7 +151,7 @@ struct Ctx {
     bool own_stream = false;
     rocblas_handle blas = nullptr;
     std::string err;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 
 struct SweepOpts {
@@ -165,7 +166,8 @@ struct SweepOpts {
 
 struct StepStats {
     double theta = 0, discarded = 0, sigma_flops = 0, sigma_seconds = 0;
-    int64_t sigma_calls = 0, dav_iters = 0;
+    double gemm_seconds = 0;  // the two grouped-GEMM launches of each sigma
+    int64_t sigma_calls = 0, dav_iters = 0, gemm_launches = 0;
     int max_bond = 0;
 };
 
@@ -199,9 +201,9 @@ class State {
                         const double* values, int center_j);
     // operations
     void prepare();                      // blocking + task lists at the center
-    void sigma(const double* x, double* y, Prec p, double* flops, double* secs);
+    void sigma(const double* x, double* y, Prec p, StepStats* st);
     void build_diag();
-    double step(int M, bool forward, const SweepOpts& o, StepStats& st);
+    double step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve = true);
     double energy();
     void env_dense(int side, int bond, std::vector<double>& out);
 

@@ -58,7 +58,9 @@ struct Cfg<2> {
     using Acc = flt4;
 };
 
-template <int MODE>
+// ROLE only separates the symbol of the sigma-vector launches (1) from every
+// other use (0) so that profiles report them apart; the code is identical.
+template <int MODE, int ROLE>
 __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                     const GemmTerm* __restrict__ terms,
                                                     Bases bases) {
@@ -332,6 +334,128 @@ __global__ void gather_rows_kernel(double* __restrict__ dst, int dld, const doub
     }
 }
 
+// One-sided (Hestenes) Jacobi SVD of one row-major R x C matrix per
+// workgroup.  The columns of A = M (R >= C) or A = M^T (R < C) are
+// orthogonalised by plane rotations in round-robin order; each wave owns a
+// set of column pairs of a round and reduces their dot products with
+// cross-lane shuffles.  Singular values are the final column norms, sorted
+// descending (ties by index).  Outputs: Um (R x r), S (r), Vt (r x C),
+// row-major, r = min(R, C); info = sweeps used, or -1 if not converged.
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs) {
+    const SvdJob job = jobs[blockIdx.x];
+    const int R = job.rows, C = job.cols;
+    const bool tr = R < C;
+    const int m = tr ? C : R;  // column length
+    const int n = tr ? R : C;  // number of columns (= r)
+    double* A = job.work;               // column j at A + j * m
+    double* V = job.work + int64_t(m) * n;  // column j at V + j * n
+    double* nrm = V + int64_t(n) * n;
+    int* perm = reinterpret_cast<int*>(nrm + n);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t e = tid; e < int64_t(m) * n; e += blockDim.x) {
+        const int j = int(e / m), i = int(e % m);
+        A[e] = tr ? job.src[int64_t(j) * C + i] : job.src[int64_t(i) * C + j];
+    }
+    for (int64_t e = tid; e < int64_t(n) * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    __shared__ int rotated;
+    __syncthreads();
+    const int nn = n + (n & 1);
+    int sweep = 0;
+    bool converged = (n < 2);
+    for (; sweep < 60 && !converged; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int rd = 0; rd < nn - 1; ++rd) {
+            for (int pi = wave; pi < nn / 2; pi += 4) {
+                int p, q;
+                if (pi == 0) {
+                    p = nn - 1;
+                    q = rd;
+                } else {
+                    p = (rd + pi) % (nn - 1);
+                    q = (rd - pi + nn - 1) % (nn - 1);
+                }
+                if (p >= n || q >= n) continue;
+                double* a = A + int64_t(p) * m;
+                double* b = A + int64_t(q) * m;
+                double al = 0, be = 0, ga = 0;
+                for (int i = lane; i < m; i += 64) {
+                    const double x = a[i], y = b[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int i = lane; i < m; i += 64) {
+                    const double x = a[i], y = b[i];
+                    a[i] = c * x - s * y;
+                    b[i] = s * x + c * y;
+                }
+                double* vp = V + int64_t(p) * n;
+                double* vq = V + int64_t(q) * n;
+                for (int i = lane; i < n; i += 64) {
+                    const double x = vp[i], y = vq[i];
+                    vp[i] = c * x - s * y;
+                    vq[i] = s * x + c * y;
+                }
+                if (lane == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+        converged = (rotated == 0);
+        __syncthreads();
+    }
+    for (int j = wave; j < n; j += 4) {
+        double ss = 0;
+        for (int i = lane; i < m; i += 64) ss += A[int64_t(j) * m + i] * A[int64_t(j) * m + i];
+        ss = wave_sum(ss);
+        if (lane == 0) nrm[j] = sqrt(ss);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        int rank = 0;
+        const double sj = nrm[j];
+        for (int k = 0; k < n; ++k) rank += (nrm[k] > sj) || (nrm[k] == sj && k < j);
+        perm[rank] = j;
+    }
+    __syncthreads();
+    const int r = n;
+    for (int k = tid; k < r; k += blockDim.x) job.S[k] = nrm[perm[k]];
+    if (!tr) {
+        for (int64_t e = tid; e < int64_t(R) * r; e += blockDim.x) {
+            const int i = int(e / r), k = int(e % r);
+            const double sg = nrm[perm[k]];
+            job.U[e] = sg > 0 ? A[int64_t(perm[k]) * m + i] / sg : 0.0;
+        }
+        for (int64_t e = tid; e < int64_t(r) * C; e += blockDim.x) {
+            const int k = int(e / C), j = int(e % C);
+            job.Vt[e] = V[int64_t(perm[k]) * n + j];
+        }
+    } else {
+        for (int64_t e = tid; e < int64_t(R) * r; e += blockDim.x) {
+            const int i = int(e / r), k = int(e % r);
+            job.U[e] = V[int64_t(perm[k]) * n + i];
+        }
+        for (int64_t e = tid; e < int64_t(r) * C; e += blockDim.x) {
+            const int k = int(e / C), j = int(e % C);
+            const double sg = nrm[perm[k]];
+            job.Vt[e] = sg > 0 ? A[int64_t(perm[k]) * m + j] / sg : 0.0;
+        }
+    }
+    if (tid == 0) *job.info = converged ? sweep : -1;
+}
+
 inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -341,25 +465,35 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 }  // namespace
 
-void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 const Bases& b, hipStream_t s) {
+template <int ROLE>
+static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                             const Bases& b, hipStream_t s) {
     if (n_tasks <= 0) return;
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
         const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL(grouped_gemm<0>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL(grouped_gemm<1>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL(grouped_gemm<2>, dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
                 break;
         }
     }
     DMRG_HIP(hipGetLastError());
+}
+
+void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                 const Bases& b, hipStream_t s) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, s);
+}
+void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                       const Bases& b, hipStream_t s) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, s);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {
@@ -461,6 +595,12 @@ void launch_gather_rows(double* dst, int dld, const double* src, int sld, const 
     if (n <= 0) return;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, dld, src, sld,
                        rows, scale, nrow, ncol);
+    DMRG_HIP(hipGetLastError());
+}
+
+void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return;
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(n_jobs), dim3(256), 0, s, jobs);
     DMRG_HIP(hipGetLastError());
 }
 

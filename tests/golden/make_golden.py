@@ -1,0 +1,64 @@
+"""Write the oracle's reference energies used by the GPU parity tests.
+
+Calls only ``oracle/`` and the seeded input generators.  Run from the
+repository root:  python tests/golden/make_golden.py
+"""
+
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import dmrg as od  # noqa: E402
+from oracle import fermions as fm  # noqa: E402
+from workloads import CONFIGS, chain_integrals, config_integrals, mps_values  # noqa: E402
+
+CASES = {
+    # first workload: random molecule K=8, N=8, M=64, 6 sweeps
+    "config1": dict(kind="config", cfg=1, M=64, sweeps=6),
+    # the same molecule at M=256, where the two-site space is exact
+    "config1_exact": dict(kind="config", cfg=1, M=256, sweeps=2),
+    # chain K=8, N=8, M=16 (truncating), 3 sweeps
+    "chain8": dict(kind="chain", K=8, N=8, seed=77, M=16, sweeps=3),
+    # odd electron count: K=7, N=7, 2Sz=1
+    "chain7_odd": dict(kind="chain", K=7, N=7, seed=78, M=16, sweeps=3),
+}
+
+
+def run(name, c):
+    if c["kind"] == "config":
+        I = config_integrals(c["cfg"])
+        seed = CONFIGS[c["cfg"]]["seed"]
+    else:
+        I = chain_integrals(c["K"], n_elec=c["N"], seed=c["seed"])
+        seed = c["seed"]
+    K, N, tsz, M = I.K, I.n_elec, I.two_sz, c["M"]
+    n = od.n_mps_values(K, N, tsz, M)
+    t0 = time.time()
+    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n))
+    sweeps = []
+    for _ in range(c["sweeps"]):
+        d.sweep()
+        sweeps.append(d.log[-2]["theta"])
+    thetas = [l["theta"] for l in d.log if "theta" in l][-2 * (K - 1):]
+    out = dict(K=K, N=N, two_sz=tsz, M=M, seed=seed, kind=I.kind, sweeps=c["sweeps"],
+               sweep_energies=sweeps, last_sweep_thetas=thetas, energy=d.energy(),
+               bonds=[[list(q) + [dd] for q, dd in d.bond_sectors(k)] for k in range(K + 1)],
+               seconds=time.time() - t0)
+    if K <= 10:
+        out["fci"] = fm.fci_energy(I.h, I.v, N, tsz)
+    return out
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(CASES)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_dmrg.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    for nm in names:
+        data[nm] = run(nm, CASES[nm])
+        data[nm]["source"] = "oracle/dmrg.py via tests/golden/make_golden.py"
+        json.dump(data, open(path, "w"), indent=1)
+        print(nm, data[nm]["energy"], "%.1fs" % data[nm]["seconds"], flush=True)

@@ -1,0 +1,124 @@
+"""CPU checks of the C ABI: symbols, host-side MPO builder, validation.
+
+The library is loaded but nothing here launches GPU work: the MPO builder
+and the integer block-index rule run on the host with a host-only context.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1605_02611_amd as P
+from paper_1605_02611_amd import _lib
+from oracle import dmrg as od, fermions as fm, mpo as omp
+from workloads import chain_integrals, random_integrals_cfg1
+
+NAMES = ["I", "H", "Cd", "C", "SL", "SLd", "A", "Ad", "B", "P", "Pd", "Q"]
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    return P.Context(device=-1)
+
+
+def _header_functions(root):
+    txt = open(os.path.join(root, "include", "dmrg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmrg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function(repo_root):
+    lib = _lib.load()
+    names = _header_functions(repo_root)
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+@pytest.mark.parametrize("K", [2, 3, 4, 5, 6])
+def test_host_mpo_equals_oracle_mpo(hctx, K):
+    I = random_integrals_cfg1(K=K, n_elec=K, seed=40 + K, rank=4)
+    m = P.Mpo(hctx, I.h, I.v, K, K % 2)
+    Ws, ch = omp.build_mpo(I.h, I.v)
+    assert list(m.bond_dims()) == omp.bond_dims(K)
+    for k in range(K + 1):
+        assert [(NAMES[a], b, c) for a, b, c in m.channels(k)] == ch[k]
+    for j in range(K):
+        xy, mats = m.site_entries(j)
+        Wc = {(int(x), int(y)): mat for (x, y), mat in zip(xy, mats)}
+        assert set(Wc) == set(Ws[j])
+        for key, mat in Wc.items():
+            assert np.abs(mat - Ws[j][key]).max() < 1e-13
+
+
+@pytest.mark.parametrize("K", [3, 5])
+def test_host_mpo_contracts_to_fock_hamiltonian(hctx, K):
+    I = chain_integrals(K, seed=60 + K)
+    m = P.Mpo(hctx, I.h, I.v, K, K % 2)
+    ch = [omp.channels(K, k) for k in range(K + 1)]
+    Wc = []
+    for j in range(K):
+        xy, mats = m.site_entries(j)
+        Wc.append({(int(x), int(y)): mat for (x, y), mat in zip(xy, mats)})
+    H = omp.contract_full(Wc, ch)
+    Hf = fm.fock_hamiltonian(I.h, I.v)
+    assert np.abs(H - Hf).max() < 1e-12 * np.abs(Hf).max()
+
+
+def test_switch_bond_option_changes_only_the_recursion(hctx):
+    K = 4
+    I = random_integrals_cfg1(K=K, n_elec=K, seed=3, rank=3)
+    Hf = fm.fock_hamiltonian(I.h, I.v)
+    for sw in (0, 1, 3, 4):
+        m = P.Mpo(hctx, I.h, I.v, K, 0, switch_bond=sw)
+        labs = [[(NAMES[a], b, c) for a, b, c in m.channels(k)] for k in range(K + 1)]
+        Wc = []
+        for j in range(K):
+            xy, mats = m.site_entries(j)
+            Wc.append({(int(x), int(y)): mat for (x, y), mat in zip(xy, mats)})
+        H = omp.contract_full(Wc, labs)
+        assert np.abs(H - Hf).max() < 1e-12 * np.abs(Hf).max()
+
+
+@pytest.mark.parametrize("K,N,tsz,M", [(8, 8, 0, 64), (8, 8, 0, 256), (13, 13, 1, 128),
+                                       (24, 24, 0, 512), (36, 36, 0, 1024)])
+def test_initial_value_count_matches_oracle_rule(hctx, K, N, tsz, M):
+    h = np.eye(K)
+    v = np.zeros((K,) * 4)
+    m = P.Mpo(hctx, h, v, N, tsz)
+    assert m.n_values(M) == od.n_mps_values(K, N, tsz, M)
+
+
+def test_invalid_inputs_are_rejected(hctx):
+    K = 3
+    I = random_integrals_cfg1(K=K, n_elec=K, seed=1, rank=2)
+    h = I.h.copy()
+    h[0, 1] += 1e-6
+    with pytest.raises(P.DmrgError) as e:
+        P.Mpo(hctx, h, I.v, 3, 1)
+    assert e.value.status == 1 and "symmetric" in str(e.value)
+    v = I.v.copy()
+    v[0, 1, 2, 2] += 1e-6
+    with pytest.raises(P.DmrgError) as e:
+        P.Mpo(hctx, I.h, v, 3, 1)
+    assert e.value.status == 1
+    with pytest.raises(P.DmrgError):
+        P.Mpo(hctx, I.h, I.v, 3, 0)  # parity of 2Sz differs from N
+    with pytest.raises(P.DmrgError):
+        P.Mpo(hctx, I.h, I.v, 7, 1)  # N > 2K
+    h2 = I.h.copy()
+    h2[1, 1] = np.nan
+    with pytest.raises(P.DmrgError):
+        P.Mpo(hctx, h2, I.v, 3, 1)
+
+
+def test_gpu_calls_on_host_context_fail_cleanly(hctx):
+    I = random_integrals_cfg1(K=4, n_elec=4, seed=1, rank=2)
+    m = P.Mpo(hctx, I.h, I.v, 4, 0)
+    n = m.n_values(8)
+    with pytest.raises(P.DmrgError) as e:
+        P.Mps.random(hctx, m, 8, np.zeros(n))
+    assert e.value.status == 6

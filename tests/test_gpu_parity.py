@@ -1,0 +1,240 @@
+"""GPU parity of the HIP library against the CPU oracle (through the C ABI).
+
+Small cases compare element by element with the oracle on the same seeded
+inputs and the same MPS tensors; the full-size workload (K=36, M=1024) is
+checked through properties that hold at any size (hermiticity, gauge
+invariance of the energy, sampled diagonal elements, precision agreement).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1605_02611_amd as P  # noqa: E402
+from oracle import dmrg as od  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from workloads import (CONFIGS, chain_integrals, config_integrals, mps_values,  # noqa: E402
+                       random_integrals_cfg1)
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_dmrg.json")
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a), device="cuda", dtype=torch.float64)
+
+
+# --- the grouped GEMM kernel ------------------------------------------------------
+
+SHAPES = [(1, 1, 1), (5, 7, 3), (16, 16, 4), (17, 33, 19), (64, 64, 16), (65, 63, 17),
+          (70, 130, 50), (130, 65, 200), (3, 300, 2)]
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_kernel(ctx, m, n, k, ta, tb):
+    _log("gemm", m, n, k, ta, tb)
+    rng = np.random.default_rng(m * 1000 + n * 10 + k + 7 * ta + 3 * tb)
+    Ah = rng.standard_normal((k, m + 3) if ta else (m, k + 3))
+    Bh = rng.standard_normal((n, k + 2) if tb else (k, n + 2))
+    Ch = rng.standard_normal((m, n + 1))
+    opA = Ah[:, :m].T if ta else Ah[:, :k]
+    opB = Bh[:, :k].T if tb else Bh[:, :n]
+    for prec, tol in [(P.DMRG_FP64, 1e-13), (P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2)]:
+        for acc in (False, True):
+            ref = 0.7 * opA @ opB + (Ch[:, :n] if acc else 0)
+            Cd = _dev(Ch)
+            ctx.gemm(_dev(Ah), _dev(Bh), Cd, m, n, k, ta=bool(ta), tb=bool(tb), alpha=0.7,
+                     accumulate=acc, prec=prec)
+            out = Cd.cpu().numpy()
+            err = np.abs(out[:, :n] - ref).max() / max(1.0, np.abs(ref).max())
+            assert err <= tol, (prec, acc, err)
+            if prec == P.DMRG_FP64:  # nothing written past column n
+                assert np.array_equal(out[:, n:], Ch[:, n:])
+
+
+# --- environments, sigma and diagonal on imported tensors -----------------------------
+
+def _oracle_case(K, N, tsz, M, seed, kind="random"):
+    I = (random_integrals_cfg1(K=K, n_elec=N, seed=seed, rank=4) if kind == "random"
+         else chain_integrals(K, n_elec=N, seed=seed))
+    n = od.n_mps_values(K, N, tsz, M)
+    return I, od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n))
+
+
+@pytest.mark.parametrize("K,N,tsz,M,centers,kind", [
+    (5, 5, 1, 6, (0, 2), "random"),
+    (6, 6, 0, 12, (0, 1, 3), "chain"),
+    (7, 8, 2, 20, (0, 2, 5), "random"),
+])
+def test_environments_sigma_diag_match_oracle(ctx, K, N, tsz, M, centers, kind):
+    I, d = _oracle_case(K, N, tsz, M, 100 + K, kind)
+    mpo = P.Mpo(ctx, I.h, I.v, N, tsz)
+    done = 0
+    for c in centers:
+        while done < c:
+            d.step(done, True, False)
+            done += 1
+        _log("import K=%d center %d" % (K, c))
+        bonds = [H.sectors(l) for l in d.labels]
+        fine = np.concatenate([H.site_fine_blocks(d.A[j], d.labels[j], d.labels[j + 1])
+                               for j in range(K)])
+        mps = P.Mps.from_tensors(ctx, mpo, bonds, fine, c)
+        lab_l, lab_r = d.labels[c], d.labels[c + 2]
+        assert np.abs(mps.psi() - H.dense_to_merged(d.psi, lab_l, lab_r)).max() < 1e-12
+        for k in range(c + 2, K + 1):
+            assert np.abs(mps.env(1, k) - d.Renv[k]).max() < 1e-11
+        for k in range(0, c + 1):
+            assert np.abs(mps.env(0, k) - d.Lenv[k]).max() < 1e-11
+        rng = np.random.default_rng(c)
+        msk = d.mask(c)
+        x = rng.standard_normal(msk.shape) * msk
+        ref = H.dense_to_merged(d.sigma(c, x), lab_l, lab_r)
+        xd = _dev(H.dense_to_merged(x, lab_l, lab_r))
+        yd = torch.zeros_like(xd)
+        mps.sigma(xd, yd)
+        y = yd.cpu().numpy()
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+        for prec, tol in [(P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2)]:
+            yd.zero_()
+            mps.sigma(xd, yd, prec)
+            assert np.linalg.norm(yd.cpu().numpy() - ref) <= tol * np.linalg.norm(ref)
+        dg = torch.zeros_like(xd)
+        mps.diag(dg)
+        refd = H.dense_to_merged(d.diag(c) * msk, lab_l, lab_r)
+        assert np.abs(dg.cpu().numpy() - refd).max() <= 1e-11 * max(1, np.abs(refd).max())
+        del mps
+
+
+def test_sigma_is_deterministic_and_linear(ctx):
+    I, d = _oracle_case(6, 6, 0, 12, 5, "chain")
+    mpo = P.Mpo(ctx, I.h, I.v, 6, 0)
+    n = mpo.n_values(12)
+    mps = P.Mps.random(ctx, mpo, 12, mps_values(5, n))
+    rng = np.random.default_rng(0)
+    x1 = _dev(rng.standard_normal(mps.psi_size()))
+    x2 = _dev(rng.standard_normal(mps.psi_size()))
+    y1, y1b, y2, y3 = (torch.zeros_like(x1) for _ in range(4))
+    mps.sigma(x1, y1)
+    mps.sigma(x1, y1b)
+    assert torch.equal(y1, y1b)
+    mps.sigma(x2, y2)
+    mps.sigma(2.0 * x1 - 3.0 * x2, y3)
+    assert torch.allclose(y3, 2.0 * y1 - 3.0 * y2, rtol=0, atol=1e-12 * float(y3.abs().max()))
+
+
+# --- whole sweeps -----------------------------------------------------------------------
+
+def _golden():
+    return json.load(open(GOLD))
+
+
+@pytest.mark.parametrize("name", ["chain7_odd", "chain8", "config1_exact", "config1"])
+def test_sweeps_match_oracle_energies(ctx, name):
+    g = _golden()[name]
+    _log("sweeps", name)
+    if g["kind"] == "random":
+        I = config_integrals(1)
+    else:
+        I = chain_integrals(g["K"], n_elec=g["N"], seed=g["seed"])
+    mpo = P.Mpo(ctx, I.h, I.v, g["N"], g["two_sz"])
+    n = mpo.n_values(g["M"])
+    mps = P.Mps.random(ctx, mpo, g["M"], mps_values(g["seed"], n))
+    stats, thetas = mps.sweep(g["M"], g["sweeps"])
+    es = [s["energy"] for s in stats]
+    assert np.abs(np.array(es) - np.array(g["sweep_energies"])).max() < 1e-8
+    assert np.abs(thetas - np.array(g["last_sweep_thetas"])).max() < 1e-8
+    assert abs(mps.energy() - g["energy"]) < 1e-8
+    assert [list(t) for t in mps.bond(g["K"] // 2)] == g["bonds"][g["K"] // 2]
+    for k in range(g["K"] + 1):
+        assert [list(t) for t in mps.bond(k)] == g["bonds"][k]
+    if "fci" in g:
+        assert mps.energy() >= g["fci"] - 1e-10
+        if name == "config1_exact":
+            assert abs(mps.energy() - g["fci"]) < 1e-10
+
+
+def test_mixed_precision_refinement_reaches_fp64_energy(ctx):
+    I = chain_integrals(10, seed=77)
+    mpo = P.Mpo(ctx, I.h, I.v, 10, 0)
+    n = mpo.n_values(24)
+    res = {}
+    for prec in (P.DMRG_FP64, P.DMRG_FP32, P.DMRG_BF16):
+        mps = P.Mps.random(ctx, mpo, 24, mps_values(77, n))
+        o = P.default_opts(prec=prec, refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+        st, _ = mps.sweep(24, 3, o)
+        res[prec] = mps.energy()
+    assert abs(res[P.DMRG_FP32] - res[P.DMRG_FP64]) < 1e-5
+    assert abs(res[P.DMRG_BF16] - res[P.DMRG_FP64]) < 1e-5
+
+
+# --- full-size workload: properties at K=36, M=1024 ----------------------------------------
+
+@pytest.fixture(scope="module")
+def big(ctx):
+    c = CONFIGS[3]
+    I = config_integrals(3)
+    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
+    n = mpo.n_values(c["M"])
+    mps = P.Mps.random(ctx, mpo, c["M"], mps_values(c["seed"], n))
+    for _ in range(c["K"] // 2 - 1):
+        mps.move(True)
+    return mpo, mps
+
+
+def test_full_size_sigma_hermitian_and_precisions(big):
+    mpo, mps = big
+    _log("full size: center", mps.center(), "n", mps.psi_size())
+    rng = np.random.default_rng(3)
+    n = mps.psi_size()
+    x = _dev(rng.standard_normal(n))
+    z = _dev(rng.standard_normal(n))
+    hx, hz = torch.zeros_like(x), torch.zeros_like(x)
+    mps.sigma(x, hx)
+    mps.sigma(z, hz)
+    a, b = float(torch.dot(z, hx)), float(torch.dot(hz, x))
+    assert abs(a - b) <= 1e-12 * float(hx.norm() * z.norm())
+    for prec, tol in [(P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2)]:
+        y = torch.zeros_like(x)
+        mps.sigma(x, y, prec)
+        assert float((y - hx).norm()) <= tol * float(hx.norm())
+
+
+def test_full_size_sampled_diagonal(big):
+    mpo, mps = big
+    n = mps.psi_size()
+    dg = torch.zeros(n, device="cuda", dtype=torch.float64)
+    mps.diag(dg)
+    rng = np.random.default_rng(9)
+    for i in rng.choice(n, 4, replace=False):
+        e = torch.zeros(n, device="cuda", dtype=torch.float64)
+        e[int(i)] = 1.0
+        y = torch.zeros_like(e)
+        mps.sigma(e, y)
+        assert abs(float(y[int(i)]) - float(dg[int(i)])) <= 1e-11 * max(1.0, abs(float(dg[int(i)])))
+
+
+def test_full_size_energy_is_gauge_invariant(big):
+    mpo, mps = big
+    e0 = mps.energy()
+    mps.move(True)
+    e1 = mps.energy()
+    mps.move(False)
+    e2 = mps.energy()
+    assert abs(e1 - e0) <= 1e-10 * abs(e0)
+    assert abs(e2 - e0) <= 1e-10 * abs(e0)
