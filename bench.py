@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time one full sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
+    ap.add_argument("--calib", action="store_true",
+                    help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -116,6 +118,13 @@ def main():
     from workloads import CONFIGS, config_integrals, mps_values
 
     prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
+    if args.calib:
+        src = torch.ones(32 << 20, device="cuda", dtype=torch.float64)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     c = CONFIGS[3]
     K, M = c["K"], c["M"]
     ctx = P.Context(0)

@@ -212,6 +212,19 @@ dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
 /* One two-site step at the current center (forward = 1 moves right). */
 dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
                       const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat);
+/* Sweep n independent instances in lockstep (same options, own M each):
+ * at every global step the sigma-vector task lists of all active instances
+ * are merged into one grouped GEMM launch per pass, captured in a hipGraph
+ * and replayed at each Davidson iteration; converged instances are masked.
+ * Instance b's step sequence, and hence its energies, are those of
+ * dmrg_sweep on it alone.  Every center must be at the pair (0, 1).
+ * stats: caller-owned n * n_sweeps entries, instance-major (seconds is the
+ * wall time of the whole batched sweep).  batch_sigma_seconds, if not
+ * NULL, receives the wall time spent in batched sigma launches. */
+dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps,
+                               const dmrg_mpo* const* mpo, const int* M, int n_sweeps,
+                               const dmrg_sweep_opts* opts, dmrg_sweep_stat* stats,
+                               double* batch_sigma_seconds);
 /* Move the center one pair right (forward = 1) or left without solving: the
  * two-site vector is split exactly by SVD (singular values <= 1e-14 sigma_max
  * dropped) and the environment on the side left behind is updated. */

@@ -5,4 +5,4 @@ include/dmrg.h); this package only marshals arguments to it.
 """
 
 from ._lib import DMRG_BF16, DMRG_FP32, DMRG_FP64, LIB_PATH, load  # noqa: F401
-from .api import Context, DmrgError, Mpo, Mps, default_opts  # noqa: F401
+from .api import Context, DmrgError, Mpo, Mps, default_opts, sweep_batched  # noqa: F401

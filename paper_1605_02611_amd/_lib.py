@@ -72,6 +72,8 @@ SIGNATURES = {
                           P(c_double), P(SweepStat)]),
     "dmrg_energy": (c_int, [c_void_p, c_void_p, c_void_p, P(c_double)]),
     "dmrg_mps_move": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    "dmrg_sweep_batched": (c_int, [c_void_p, c_int, P(c_void_p), P(c_void_p), P(c_int), c_int,
+                                   P(SweepOpts), P(SweepStat), P(c_double)]),
 }
 
 _lib = None

@@ -244,3 +244,19 @@ class Mps:
         if getattr(self, "h", None):
             self.lib.dmrg_mps_free(self.h)
             self.h = None
+
+
+def sweep_batched(ctx, states, Ms, n_sweeps, opts=None):
+    """Lockstep sweeps of several Mps instances with batched sigma launches."""
+    opts = opts or default_opts()
+    n = len(states)
+    hm = (C.c_void_p * n)(*[s.h.value for s in states])
+    hp = (C.c_void_p * n)(*[s.mpo.h.value for s in states])
+    Mv = (C.c_int * n)(*Ms)
+    st = (L.SweepStat * max(1, n * n_sweeps))()
+    bs = C.c_double()
+    ctx.check(ctx.lib.dmrg_sweep_batched(ctx.h, n, hm, hp, Mv, n_sweeps, C.byref(opts), st,
+                                         C.byref(bs)))
+    out = [[{f: getattr(st[b * n_sweeps + i], f) for f, _ in L.SweepStat._fields_}
+            for i in range(n_sweeps)] for b in range(n)]
+    return out, bs.value

@@ -1,0 +1,249 @@
+// Batched two-site DMRG over many independent instances (molecules).
+//
+// All instances advance in lockstep through their sweep schedules.  At each
+// global step every active instance builds its blocking and task lists; the
+// sigma-vector task lists of all instances are merged into one grouped GEMM
+// launch per pass (tasks carry their instance id and address a device table
+// of per-instance buffers), and the launch sequence of one batched sigma is
+// captured once per step in a hipGraph that every Davidson iteration
+// replays.  Instances whose Davidson has converged are masked out through a
+// device flag array.  This is the parallelism over quantum-number blocks of
+// Sec. 4.3 (ii), extended across molecules, on one GPU.
+#include <algorithm>
+#include <chrono>
+
+#include "engine.h"
+
+namespace dmrg {
+
+namespace {
+
+struct BatchSigma {
+    hipStream_t s = nullptr;
+    std::vector<State*> st;
+    GemmList p1, p2;
+    DevBuf tab[2], act;
+    std::vector<DevBuf> xin, yout;
+    std::vector<double> flops;  // model flops of one sigma per instance
+    hipGraph_t gr[2] = {nullptr, nullptr};
+    hipGraphExec_t ex[2] = {nullptr, nullptr};
+    std::vector<int> hact;
+    std::vector<void*> htab[2];
+
+    ~BatchSigma() {
+        for (int i = 0; i < 2; ++i) {
+            if (ex[i]) (void)hipGraphExecDestroy(ex[i]);
+            if (gr[i]) (void)hipGraphDestroy(gr[i]);
+        }
+    }
+
+    static void merge(GemmList& dst, const GemmList& src, int inst, const int remap[3]) {
+        const int tb = int(dst.terms.size());
+        for (GemmTask t : src.tasks) {
+            t.c_buf = 8 * inst + remap[t.c_buf];
+            t.l_begin += tb;
+            t.l_end += tb;
+            t.inst = inst;
+            dst.tasks.push_back(t);
+        }
+        for (GemmTerm g : src.terms) {
+            g.a_buf = 8 * inst + remap[g.a_buf];
+            g.b_buf = 8 * inst + remap[g.b_buf];
+            dst.terms.push_back(g);
+        }
+        dst.flops += src.flops;
+        dst.model_flops += src.model_flops;
+    }
+
+    void build(const std::vector<State*>& states, hipStream_t stream) {
+        s = stream;
+        st = states;
+        const int nb = int(st.size());
+        const int r1[3] = {0, 1, 2};  // pass 1: Y, x, T
+        const int r2[3] = {2, 3, 4};  // pass 2: T, Z, out
+        xin.resize(nb);
+        yout.resize(nb);
+        flops.resize(nb);
+        htab[0].assign(size_t(8) * nb, nullptr);
+        for (int b = 0; b < nb; ++b) {
+            State& S = *st[b];
+            merge(p1, S.pass1, b, r1);
+            merge(p2, S.pass2, b, r2);
+            flops[b] = S.pass1.model_flops + S.pass2.model_flops;
+            xin[b].alloc(std::max<int64_t>(1, S.ts.n) * sizeof(double), s);
+            yout[b].alloc(std::max<int64_t>(1, S.ts.n) * sizeof(double), s);
+            void** t = &htab[0][size_t(8) * b];
+            t[0] = S.Y.buf.p;
+            t[1] = xin[b].p;
+            t[2] = S.tbuf.p;
+            t[3] = S.Z.buf.p;
+            t[4] = S.splits > 1 ? S.part.p : yout[b].p;
+        }
+        p1.sigma_role = p2.sigma_role = true;
+        p1.upload(s);
+        p2.upload(s);
+        tab[0].alloc(htab[0].size() * sizeof(void*), s);
+        DMRG_HIP(hipMemcpyAsync(tab[0].p, htab[0].data(), htab[0].size() * sizeof(void*),
+                                hipMemcpyHostToDevice, s));
+        act.alloc(std::max<size_t>(1, st.size()) * sizeof(int), s);
+        hact.assign(st.size(), 1);
+        DMRG_HIP(hipStreamSynchronize(s));
+    }
+
+    void ensure_graph(Prec p) {
+        const int g = p == Prec::F64 ? 0 : 1;
+        const int nb = int(st.size());
+        if (g == 1 && !tab[1].p) {
+            htab[1].assign(size_t(8) * nb, nullptr);
+            for (int b = 0; b < nb; ++b) {
+                State& S = *st[b];
+                S.ensure_f32();
+                void** t = &htab[1][size_t(8) * b];
+                t[0] = S.Y.buf32.p;
+                t[1] = S.psi32.p;
+                t[2] = S.tbuf32.p;
+                t[3] = S.Z.buf32.p;
+                t[4] = S.splits > 1 ? S.part32.p : S.sig32.p;
+            }
+            tab[1].alloc(htab[1].size() * sizeof(void*), s);
+            DMRG_HIP(hipMemcpyAsync(tab[1].p, htab[1].data(), htab[1].size() * sizeof(void*),
+                                    hipMemcpyHostToDevice, s));
+            DMRG_HIP(hipStreamSynchronize(s));
+        }
+        if (ex[g]) return;
+        DMRG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        void* const* tb = reinterpret_cast<void* const*>(tab[g].p);
+        const int* ac = act.as<int>();
+        if (g == 1)
+            for (int b = 0; b < nb; ++b)
+                launch_to_f32(st[b]->psi32.as<float>(), xin[b].as<double>(), st[b]->ts.n, s);
+        p1.launch_dev(p, tb, ac, s);
+        p2.launch_dev(p, tb, ac, s);
+        for (int b = 0; b < nb; ++b) {
+            State& S = *st[b];
+            if (g == 0) {
+                if (S.splits > 1) launch_sum_slices(yout[b].as<double>(), S.part.as<double>(), S.splits, S.ts.n, 0, s);
+            } else {
+                if (S.splits > 1)
+                    launch_sum_slices_f32(S.sig32.as<float>(), S.part32.as<float>(), S.splits, S.ts.n, 0, s);
+                launch_f32_to_f64(yout[b].as<double>(), S.sig32.as<float>(), S.ts.n, s);
+            }
+        }
+        DMRG_HIP(hipStreamEndCapture(s, &gr[g]));
+        DMRG_HIP(hipGraphInstantiate(&ex[g], gr[g], nullptr, nullptr, 0));
+    }
+
+    // one batched sigma for the instances with on[b] != 0
+    void run(Prec p, const std::vector<char>& on, const std::vector<DavSolver*>& ds, Ctx* ctx) {
+        ensure_graph(p);
+        const int nb = int(st.size());
+        double ftot = 0;
+        for (int b = 0; b < nb; ++b) {
+            hact[b] = on[b] ? 1 : 0;
+            if (on[b]) {
+                launch_copy(xin[b].as<double>(), ds[b]->in(), st[b]->ts.n, s);
+                ftot += flops[b];
+            }
+        }
+        DMRG_HIP(hipMemcpyAsync(act.p, hact.data(), hact.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        DMRG_HIP(hipEventRecord(ctx->ev0, s));
+        DMRG_HIP(hipGraphLaunch(ex[p == Prec::F64 ? 0 : 1], s));
+        DMRG_HIP(hipEventRecord(ctx->ev1, s));
+        for (int b = 0; b < nb; ++b)
+            if (on[b]) launch_copy(ds[b]->out(), yout[b].as<double>(), st[b]->ts.n, s);
+        DMRG_HIP(hipStreamSynchronize(s));
+        float ms = 0;
+        DMRG_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        for (int b = 0; b < nb; ++b) {
+            if (!on[b]) continue;
+            StepStats& S = ds[b]->stats();
+            S.sigma_flops += flops[b];
+            S.sigma_seconds += ms * 1e-3 * (ftot > 0 ? flops[b] / ftot : 0.0);
+            S.gemm_seconds += ms * 1e-3 * (ftot > 0 ? flops[b] / ftot : 0.0);
+            S.gemm_launches += 2;
+            S.sigma_calls += 1;
+        }
+    }
+};
+
+}  // namespace
+
+void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M, int n_sweeps,
+                   const SweepOpts& o, std::vector<std::vector<StepStats>>& stats,
+                   std::vector<std::vector<double>>& seconds, double* batch_sigma_seconds) {
+    const int nb = int(st.size());
+    hipStream_t s = ctx->stream;
+    std::vector<int> nsteps(nb);
+    int tmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        require(st[b]->center == 0, "every instance must start with its center at the pair (0, 1)",
+                E_STATE);
+        nsteps[b] = 2 * (st[b]->mpo->K - 1);
+        tmax = std::max(tmax, nsteps[b]);
+    }
+    stats.assign(nb, std::vector<StepStats>(n_sweeps));
+    seconds.assign(nb, std::vector<double>(n_sweeps, 0.0));
+    using clk = std::chrono::steady_clock;
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        const auto t0 = clk::now();
+        for (int t = 0; t < tmax; ++t) {
+            std::vector<State*> act;
+            std::vector<int> idx;
+            for (int b = 0; b < nb; ++b)
+                if (t < nsteps[b]) {
+                    act.push_back(st[b]);
+                    idx.push_back(b);
+                }
+            const int na = int(act.size());
+            for (State* S : act) {
+                S->prepare();
+                S->build_diag();
+            }
+            std::vector<std::unique_ptr<DavSolver>> ds(na);
+            std::vector<DavSolver*> dp(na);
+            for (int a = 0; a < na; ++a) {
+                ds[a] = std::make_unique<DavSolver>(*act[a], act[a]->psi.as<double>(), act[a]->ts.n, o,
+                                                    stats[idx[a]][sw]);
+                dp[a] = ds[a].get();
+            }
+            {
+                BatchSigma B;
+                B.build(act, s);
+                std::vector<char> live(na, 1);
+                int nlive = na;
+                while (nlive > 0) {
+                    for (Prec p : {Prec::F64, Prec::F32, Prec::BF16}) {
+                        std::vector<char> on(na, 0);
+                        bool any = false;
+                        for (int a = 0; a < na; ++a)
+                            if (live[a] && dp[a]->prec() == p) on[a] = 1, any = true;
+                        if (!any) continue;
+                        const auto tb = clk::now();
+                        B.run(p, on, dp, ctx);
+                        if (batch_sigma_seconds)
+                            *batch_sigma_seconds += std::chrono::duration<double>(clk::now() - tb).count();
+                    }
+                    for (int a = 0; a < na; ++a)
+                        if (live[a] && !dp[a]->advance()) {
+                            live[a] = 0;
+                            --nlive;
+                        }
+                }
+            }
+            for (int a = 0; a < na; ++a) {
+                const int b = idx[a];
+                StepStats& S = stats[b][sw];
+                const DavOut dv = dp[a]->result();
+                ds[a].reset();
+                S.theta = dv.theta;
+                S.dav_iters += dv.iters;
+                const bool forward = t < nsteps[b] / 2;
+                act[a]->finish_step(M[b], forward, o, S, true, dv, 0, 0, 0, S.sigma_seconds);
+            }
+        }
+        const double dt = std::chrono::duration<double>(clk::now() - t0).count();
+        for (int b = 0; b < nb; ++b) seconds[b][sw] = dt;
+    }
+}
+
+}  // namespace dmrg

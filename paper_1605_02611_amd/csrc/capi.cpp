@@ -102,6 +102,7 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
         DMRG_HIP(hipEventCreate(&ctx->c.ev1));
         DMRG_HIP(hipEventCreate(&ctx->c.ev2));
         DMRG_HIP(hipEventCreate(&ctx->c.ev3));
+        DMRG_HIP(hipDeviceGetAttribute(&ctx->c.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
         if (rocblas_create_handle(&ctx->c.blas) != rocblas_status_success)
             throw Error(E_HIP, "rocblas_create_handle failed");
         if (rocblas_set_stream(ctx->c.blas, ctx->c.stream) != rocblas_status_success)
@@ -474,6 +475,49 @@ dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int
         o.svd_cutoff = 1e-14;
         StepStats s;
         mps->st->step(1, forward != 0, o, s, false);
+    });
+}
+
+dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps, const dmrg_mpo* const* mpo,
+                               const int* M, int n_sweeps, const dmrg_sweep_opts* opts,
+                               dmrg_sweep_stat* stats, double* batch_sigma_seconds) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(n >= 1 && mps && mpo && M && n_sweeps >= 0, "bad batched arguments");
+        use_device(ctx->c);
+        std::vector<State*> st(n);
+        std::vector<int> Mv(n);
+        for (int b = 0; b < n; ++b) {
+            require(mps[b] && mpo[b], "null instance");
+            require(mps[b]->st->mpo == mpo[b]->m.get(), "state was built with another MPO", E_STATE);
+            require(M[b] >= 1, "M must be >= 1");
+            for (int c = 0; c < b; ++c) require(mps[c] != mps[b], "an instance appears twice");
+            st[b] = mps[b]->st.get();
+            Mv[b] = M[b];
+        }
+        SweepOpts o = to_opts(opts);
+        std::vector<std::vector<StepStats>> S;
+        std::vector<std::vector<double>> secs;
+        double bs = 0;
+        sweep_batched(&ctx->c, st, Mv, n_sweeps, o, S, secs, &bs);
+        if (batch_sigma_seconds) *batch_sigma_seconds = bs;
+        if (stats)
+            for (int b = 0; b < n; ++b)
+                for (int sw = 0; sw < n_sweeps; ++sw) {
+                    dmrg_sweep_stat& d = stats[size_t(b) * n_sweeps + sw];
+                    const StepStats& x = S[b][sw];
+                    d.energy = x.theta;
+                    d.discarded = x.discarded;
+                    d.seconds = secs[b][sw];
+                    d.sigma_flops = x.sigma_flops;
+                    d.sigma_seconds = x.sigma_seconds;
+                    d.sigma_calls = x.sigma_calls;
+                    d.gemm_seconds = x.gemm_seconds;
+                    d.gemm_launches = x.gemm_launches;
+                    d.dav_iters = x.dav_iters;
+                    d.max_bond = x.max_bond;
+                    d.n_steps = 2 * (mpo[b]->m->K - 1);
+                }
     });
 }
 

@@ -122,8 +122,21 @@ struct FineW {
     double c;
 };
 
+// W[site] grouped for blocking: one group per (channel of the middle bond,
+// local sp, local s) with the list of (channel of the outer bond, coefficient)
+struct WGroup {
+    int ch, sp, s;
+    int begin, end;  // into terms
+};
+struct WGroups {
+    std::vector<WGroup> groups;
+    std::vector<std::pair<int, double>> terms;
+};
+
 struct MPO {
     int K = 0, n_elec = 0, two_sz = 0, switch_bond = 0;
+    std::vector<WGroups> sys_groups;  // per site: grouped by right channel (left blocking)
+    std::vector<WGroups> env_groups;  // per site: grouped by left channel (right blocking)
     std::vector<std::vector<Chan>> chans;        // bonds 0..K
     std::vector<std::vector<QN>> chan_dq;        // per bond
     std::vector<std::vector<std::pair<std::pair<int, int>, Mat4>>> W;  // per site
@@ -144,6 +157,7 @@ struct GemmTask {
     int c_buf, ldc, m, n;  // m, n <= kTile
     int accumulate;
     int l_begin, l_end;
+    int inst;  // instance of a batched launch (skipped when inactive)
 };
 struct GemmTerm {
     int64_t a_off, b_off;  // origin of the m x k slice of A and k x n slice of B
@@ -155,18 +169,20 @@ struct GemmTerm {
 };
 enum { GT_TA = 1, GT_TB = 2 };
 constexpr int kTile = 64;
-constexpr int kMaxBufs = 8;
+constexpr int kMaxBufs = 8;  // buffers of one single-instance task list
 struct Bases {
     void* p[kMaxBufs];
 };
 
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
+// bases: DEVICE array of buffer base pointers indexed by the buffer ids of
+// the tasks and terms; active: DEVICE flags per instance or nullptr
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 const Bases& bases, hipStream_t s);
+                 void* const* bases, const int* active, hipStream_t s);
 // same kernel, separate symbol for the two passes of the sigma vector
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       const Bases& bases, hipStream_t s);
+                       void* const* bases, const int* active, hipStream_t s);
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]
 struct SumItem {
@@ -235,7 +251,9 @@ inline int64_t svd_work_elems(int rows, int cols) {
     const int64_t m = rows > cols ? rows : cols, n = rows > cols ? cols : rows;
     return m * n + n * n + n + (n + 1) / 2 + 1;
 }
-void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, hipStream_t s);
+// lds_elems: doubles of dynamic LDS per workgroup (0 = all in global memory)
+void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, int lds_elems, hipStream_t s);
+constexpr int kJacobiLds = 20000;  // 160 000 bytes of the 160 KiB LDS
 
 // ---------------------------------------------------------------------------
 // device memory: stream-ordered allocations

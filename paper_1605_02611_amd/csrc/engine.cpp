@@ -118,6 +118,7 @@ void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int 
                     L.terms.push_back(g);
                 }
                 tk.l_end = int(L.terms.size());
+                tk.inst = 0;
                 L.tasks.push_back(tk);
             }
         }
@@ -134,11 +135,20 @@ void GemmList::upload(hipStream_t s) {
                                 hipMemcpyHostToDevice, s));
 }
 
-void GemmList::launch(Prec p, const Bases& b, hipStream_t s) const {
+void GemmList::launch(Prec p, const Bases& b, hipStream_t s) {
+    if (!dbases.p) dbases.alloc(sizeof(Bases), s);
+    hbases = b;
+    DMRG_HIP(hipMemcpyAsync(dbases.p, &hbases, sizeof(Bases), hipMemcpyHostToDevice, s));
+    launch_dev(p, reinterpret_cast<void* const*>(dbases.p), nullptr, s);
+}
+
+void GemmList::launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const {
     if (sigma_role)
-        launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
+        launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
+                          dev_bases, active, s);
     else
-        launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(), b, s);
+        launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
+                    dev_bases, active, s);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
@@ -299,99 +309,54 @@ static void run_wsum(Blocked& B, const double* src_base, const std::vector<int64
     DMRG_HIP(hipStreamSynchronize(s));
 }
 
-Blocked State::block_sys(int j, const Env& Lj) {
-    const auto& f = mpo->fine[j];
+// side 0: Y rows from L_j and the groups of W[j] by right channel
+// side 1: Z rows from R_{k+1} and the groups of W[k] by left channel
+static Blocked make_blocked(const MPO& mpo, const BondL& bond, const WGroups& G,
+                            const std::vector<QN>& src_dq, int n_chan, int id_kind,
+                            const std::vector<Chan>& row_chans) {
     Blocked B;
-    B.bond = j;
-    B.n_chan = int(mpo->chans[j + 1].size());
-    B.find.assign(size_t(B.n_chan) * 16, -1);
-    std::vector<int> idx(f.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-        const FineW &p = f[a], &q = f[b];
-        if (p.y != q.y) return p.y < q.y;
-        if (p.sp != q.sp) return p.sp < q.sp;
-        if (p.s != q.s) return p.s < q.s;
-        return p.x < q.x;
-    });
-    const BondL& bond = bonds[j];
-    for (size_t i = 0; i < idx.size();) {
-        const FineW& h = f[idx[i]];
-        size_t e = i;
-        while (e < idx.size() && f[idx[e]].y == h.y && f[idx[e]].sp == h.sp && f[idx[e]].s == h.s) ++e;
-        const QN dq = mpo->chan_dq[j][h.x];
+    B.n_chan = n_chan;
+    B.find.assign(size_t(n_chan) * 16, -1);
+    for (const WGroup& g : G.groups) {
+        const QN dq = src_dq[G.terms[g.begin].first];
         const OpLayout& lay = bond.layout(dq);
-        if (lay.size > 0) {
-            BRow r;
-            r.y = h.y;
-            r.sp = h.sp;
-            r.s = h.s;
-            r.dq = dq;
-            r.off = B.total;
-            r.lay = &lay;
-            r.t_begin = int(B.terms.size());
-            for (size_t k = i; k < e; ++k) {
-                require(bond.layout(mpo->chan_dq[j][f[idx[k]].x]).size == lay.size,
-                        "internal: blocking terms with different layouts", E_STATE);
-                B.terms.push_back({f[idx[k]].x, f[idx[k]].c});
-            }
-            r.t_end = int(B.terms.size());
-            r.identity = mpo->chans[j + 1][h.y].kind == CK_I;
-            B.find[size_t(h.y) * 16 + h.sp * 4 + h.s] = int(B.rows.size());
-            B.rows.push_back(r);
-            B.total += lay.size;
+        if (lay.size == 0) continue;
+        BRow r;
+        r.y = g.ch;
+        r.sp = g.sp;
+        r.s = g.s;
+        r.dq = dq;
+        r.off = B.total;
+        r.lay = &lay;
+        r.t_begin = int(B.terms.size());
+        for (int k = g.begin; k < g.end; ++k) {
+            require(bond.layout(src_dq[G.terms[k].first]).size == lay.size,
+                    "internal: blocking terms with different layouts", E_STATE);
+            B.terms.push_back(G.terms[k]);
         }
-        i = e;
+        r.t_end = int(B.terms.size());
+        r.identity = row_chans[g.ch].kind == id_kind;
+        B.find[size_t(g.ch) * 16 + g.sp * 4 + g.s] = int(B.rows.size());
+        B.rows.push_back(r);
+        B.total += lay.size;
     }
+    (void)mpo;
+    return B;
+}
+
+Blocked State::block_sys(int j, const Env& Lj) {
+    Blocked B = make_blocked(*mpo, bonds[j], mpo->sys_groups[j], mpo->chan_dq[j],
+                             int(mpo->chans[j + 1].size()), CK_I, mpo->chans[j + 1]);
+    B.bond = j;
     B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
     run_wsum(B, Lj.buf.as<double>(), Lj.off, ctx->stream);
     return B;
 }
 
 Blocked State::block_env(int k, const Env& Rk1) {
-    const auto& f = mpo->fine[k];
-    Blocked B;
+    Blocked B = make_blocked(*mpo, bonds[k + 1], mpo->env_groups[k], mpo->chan_dq[k + 1],
+                             int(mpo->chans[k].size()), CK_H, mpo->chans[k]);
     B.bond = k + 1;
-    B.n_chan = int(mpo->chans[k].size());
-    B.find.assign(size_t(B.n_chan) * 16, -1);
-    std::vector<int> idx(f.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-        const FineW &p = f[a], &q = f[b];
-        if (p.x != q.x) return p.x < q.x;
-        if (p.sp != q.sp) return p.sp < q.sp;
-        if (p.s != q.s) return p.s < q.s;
-        return p.y < q.y;
-    });
-    const BondL& bond = bonds[k + 1];
-    for (size_t i = 0; i < idx.size();) {
-        const FineW& h = f[idx[i]];
-        size_t e = i;
-        while (e < idx.size() && f[idx[e]].x == h.x && f[idx[e]].sp == h.sp && f[idx[e]].s == h.s) ++e;
-        const QN dq = mpo->chan_dq[k + 1][h.y];
-        const OpLayout& lay = bond.layout(dq);
-        if (lay.size > 0) {
-            BRow r;
-            r.y = h.x;
-            r.sp = h.sp;
-            r.s = h.s;
-            r.dq = dq;
-            r.off = B.total;
-            r.lay = &lay;
-            r.t_begin = int(B.terms.size());
-            for (size_t q = i; q < e; ++q) {
-                require(bond.layout(mpo->chan_dq[k + 1][f[idx[q]].y]).size == lay.size,
-                        "internal: blocking terms with different layouts", E_STATE);
-                B.terms.push_back({f[idx[q]].y, f[idx[q]].c});
-            }
-            r.t_end = int(B.terms.size());
-            r.identity = mpo->chans[k][h.x].kind == CK_H;
-            B.find[size_t(h.x) * 16 + h.sp * 4 + h.s] = int(B.rows.size());
-            B.rows.push_back(r);
-            B.total += lay.size;
-        }
-        i = e;
-    }
     B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
     run_wsum(B, Rk1.buf.as<double>(), Rk1.off, ctx->stream);
     return B;
@@ -850,7 +815,14 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
         }
         djobs.alloc(jobs.size() * sizeof(SvdJob), s);
         DMRG_HIP(hipMemcpyAsync(djobs.p, jobs.data(), jobs.size() * sizeof(SvdJob), hipMemcpyHostToDevice, s));
-        launch_jacobi_svd(djobs.as<SvdJob>(), int(jobs.size()), s);
+        // the largest working set decides whether the launch asks for LDS
+        int64_t need = 0;
+        for (const SvdJob& jb : jobs) {
+            const int64_t mm = std::max(jb.rows, jb.cols), nn = std::min(jb.rows, jb.cols);
+            need = std::max(need, mm * nn + nn * nn);
+        }
+        const int64_t cap = std::min<int64_t>(kJacobiLds, (ctx->max_lds - 64) / int64_t(sizeof(double)));
+        launch_jacobi_svd(djobs.as<SvdJob>(), int(jobs.size()), int(std::max<int64_t>(0, std::min(need, cap))), s);
     }
     for (size_t i = 0; i < mats.size(); ++i) {
         const SvdOut& o = outs[i];
@@ -1072,10 +1044,21 @@ void State::prepare() {
     if (prepared) return;
     const int j = center;
     hipStream_t s = ctx->stream;
+    const auto tp0 = std::chrono::steady_clock::now();
     Y = block_sys(j, *L[j]);
     Z = block_env(j + 1, *R[j + 2]);
+    const auto tp1 = std::chrono::steady_clock::now();
     const int nch = int(mpo->chans[j + 1].size());
     const int nq = int(ts.q.size());
+    // destination sector of every sector for each distinct shift
+    std::map<QN, std::vector<int>> dest;
+    auto dest_of = [&](QN dq) -> const std::vector<int>& {
+        auto it = dest.find(dq);
+        if (it != dest.end()) return it->second;
+        std::vector<int> v(nq);
+        for (int iq = 0; iq < nq; ++iq) v[iq] = ts.find(ts.q[iq] + dq);
+        return dest.emplace(dq, std::move(v)).first->second;
+    };
     // T_y(q) = O^sys_y psi_q : rows sys(q + dq_y), cols env(q)
     std::vector<char> hy(nch, 0), hz(nch, 0);
     for (const BRow& r : Y.rows) hy[r.y] = 1;
@@ -1084,9 +1067,9 @@ void State::prepare() {
     t_total = 0;
     for (int y = 0; y < nch; ++y) {
         if (!hy[y] || !hz[y]) continue;
-        const QN dq = mpo->chan_dq[j + 1][y];
+        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
         for (int iq = 0; iq < nq; ++iq) {
-            const int iq2 = ts.find(ts.q[iq] + dq);
+            const int iq2 = dv[iq];
             if (iq2 < 0) continue;
             t_off[size_t(y) * nq + iq] = t_total;
             t_total += int64_t(ts.sys[iq2].dim) * ts.env[iq].dim;
@@ -1094,11 +1077,12 @@ void State::prepare() {
     }
     pass1.clear();
     std::vector<UTerm> terms;
-    for (int y = 0; y < nch; ++y)
+    for (int y = 0; y < nch; ++y) {
+        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
         for (int iq = 0; iq < nq; ++iq) {
             const int64_t to = t_off[size_t(y) * nq + iq];
             if (to < 0) continue;
-            const int iq2 = ts.find(ts.q[iq] + mpo->chan_dq[j + 1][y]);
+            const int iq2 = dv[iq];
             const int ncol = ts.env[iq].dim;
             for (const Seg& so : ts.sys[iq2].segs) {
                 terms.clear();
@@ -1120,25 +1104,28 @@ void State::prepare() {
                 add_unit(pass1, 2, to + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
             }
         }
+    }
     // sigma_q' [:, (t', Q'_r)] = sum_y sum_t T_y(q)[:, (t, Q_r)] Z_(y,t',t)^T
     pass2.clear();
     int64_t tiles2 = 0;
-    for (int iq2 = 0; iq2 < nq; ++iq2)
+    std::vector<int> unit_base(nq + 1, 0);
+    for (int iq2 = 0; iq2 < nq; ++iq2) {
+        unit_base[iq2 + 1] = unit_base[iq2] + int(ts.env[iq2].segs.size());
         for (const Seg& so : ts.env[iq2].segs)
             tiles2 += int64_t((ts.sys[iq2].dim + kTile - 1) / kTile) * ((so.dim + kTile - 1) / kTile);
+    }
     splits = int(std::max<int64_t>(1, std::min<int64_t>(16, (4096 + tiles2 - 1) / std::max<int64_t>(1, tiles2))));
-    const BondL& br = bonds[j + 2];
-    for (int iq2 = 0; iq2 < nq; ++iq2) {
-        const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
-        for (const Seg& so : ts.env[iq2].segs) {
-            terms.clear();
-            for (int y = 0; y < nch; ++y) {
-                if (!hy[y] || !hz[y]) continue;
-                const QN q = ts.q[iq2] - mpo->chan_dq[j + 1][y];
-                const int iq = ts.find(q);
-                if (iq < 0) continue;
-                const int64_t to = t_off[size_t(y) * nq + iq];
-                if (to < 0) continue;
+    std::vector<std::vector<UTerm>> uterms(unit_base[nq]);
+    for (int y = 0; y < nch; ++y) {
+        if (!hy[y] || !hz[y]) continue;
+        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
+        for (int iq = 0; iq < nq; ++iq) {
+            const int64_t to = t_off[size_t(y) * nq + iq];
+            if (to < 0) continue;
+            const int iq2 = dv[iq];
+            const Space& es2 = ts.env[iq2];
+            for (size_t ui = 0; ui < es2.segs.size(); ++ui) {
+                const Seg& so = es2.segs[ui];
                 for (int t = 0; t < 4; ++t) {
                     const int ri = Z.row(y, so.st, t);
                     if (ri < 0) continue;
@@ -1150,13 +1137,22 @@ void State::prepare() {
                     if (bi < 0) continue;
                     const OpBlock& blk = r.lay->blocks[bi];
                     if (blk.out != so.sec) continue;
-                    terms.push_back({0, to + sg.off, ts.env[iq].dim, false, 1, r.off + blk.off,
-                                     blk.cols, true, blk.cols, 1.0, !r.identity});
+                    uterms[unit_base[iq2] + ui].push_back({0, to + sg.off, ts.env[iq].dim, false, 1,
+                                                           r.off + blk.off, blk.cols, true, blk.cols,
+                                                           1.0, !r.identity});
                 }
             }
-            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, terms, splits, ts.n);
         }
     }
+    for (int iq2 = 0; iq2 < nq; ++iq2) {
+        const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
+        for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
+            const Seg& so = ts.env[iq2].segs[ui];
+            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[unit_base[iq2] + ui],
+                     splits, ts.n);
+        }
+    }
+    const BondL& br = bonds[j + 2];
     (void)br;
     {
         int64_t sz1[kMaxBufs] = {Y.total, ts.n, t_total};
@@ -1165,6 +1161,7 @@ void State::prepare() {
         validate_list(pass2, sz2);
     }
     pass1.sigma_role = pass2.sigma_role = true;
+    const auto tp2 = std::chrono::steady_clock::now();
     pass1.upload(s);
     pass2.upload(s);
     tbuf.alloc(std::max<int64_t>(1, t_total) * sizeof(double), s);
@@ -1172,6 +1169,26 @@ void State::prepare() {
     DMRG_HIP(hipStreamSynchronize(s));
     prepared = true;
     diag_ok = false;
+    if (std::getenv("DMRG_TRACE")) {
+        const auto tp3 = std::chrono::steady_clock::now();
+        auto d = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+        fprintf(stderr, "[dmrg] prepare pair %d: blocking %.3fs lists %.3fs upload %.3fs tasks %zu+%zu terms %zu+%zu T %.2f GB splits %d\n",
+                j, d(tp0, tp1), d(tp1, tp2), d(tp2, tp3), pass1.tasks.size(), pass2.tasks.size(),
+                pass1.terms.size(), pass2.terms.size(), t_total * 8e-9, splits);
+    }
+}
+
+void State::ensure_f32() {
+    if (Y.buf32.p) return;
+    hipStream_t s = ctx->stream;
+    Y.buf32.alloc(std::max<int64_t>(1, Y.total) * sizeof(float), s);
+    launch_to_f32(Y.buf32.as<float>(), Y.buf.as<double>(), Y.total, s);
+    Z.buf32.alloc(std::max<int64_t>(1, Z.total) * sizeof(float), s);
+    launch_to_f32(Z.buf32.as<float>(), Z.buf.as<double>(), Z.total, s);
+    psi32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
+    sig32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
+    tbuf32.alloc(std::max<int64_t>(1, t_total) * sizeof(float), s);
+    if (splits > 1) part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
 }
 
 void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
@@ -1192,16 +1209,7 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
         DMRG_HIP(hipEventRecord(ctx->ev2, s));
         if (splits > 1) launch_sum_slices(y, part.as<double>(), splits, ts.n, 0, s);
     } else {
-        if (!Y.buf32.p) {
-            Y.buf32.alloc(std::max<int64_t>(1, Y.total) * sizeof(float), s);
-            launch_to_f32(Y.buf32.as<float>(), Y.buf.as<double>(), Y.total, s);
-            Z.buf32.alloc(std::max<int64_t>(1, Z.total) * sizeof(float), s);
-            launch_to_f32(Z.buf32.as<float>(), Z.buf.as<double>(), Z.total, s);
-            psi32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
-            sig32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
-            tbuf32.alloc(std::max<int64_t>(1, t_total) * sizeof(float), s);
-            if (splits > 1) part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
-        }
+        ensure_f32();
         DMRG_HIP(hipEventRecord(ctx->ev0, s));
         launch_to_f32(psi32.as<float>(), x, ts.n, s);
         Bases b1{};
@@ -1308,122 +1316,148 @@ void State::build_diag() {
 // ---------------------------------------------------------------------------
 // Davidson + truncation + decimation: one two-site step
 
-namespace {
-
-struct DavOut {
-    double theta, rnorm;
-    int iters;
-};
-
-DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& stats) {
-    hipStream_t s = st.ctx->stream;
-    const int ms = std::max(2, std::min(o.dav_max_space, 40));
-    const int keep = std::max(1, std::min(o.dav_keep, ms - 1));
-    DevBuf V(sizeof(double) * n * ms, s), W(sizeof(double) * n * ms, s);
-    DevBuf r(sizeof(double) * n, s), t(sizeof(double) * n, s), xr(sizeof(double) * n, s),
-        wr(sizeof(double) * n, s), scr(sizeof(double) * n * keep, s);
-    Dots dots;
-    dots.init(s);
-    double* Vp = V.as<double>();
-    double* Wp = W.as<double>();
-    Prec prec = o.prec;
-    auto apply = [&](const double* in, double* out) { st.sigma(in, out, prec, &stats); };
-    // normalized start
-    double nx = std::sqrt(dots.run(x, 0, 1, x, n, s)[0]);
+DavSolver::DavSolver(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& stats)
+    : st_(st), x_(x), n_(n), o_(o), stats_(stats), s_(st.ctx->stream) {
+    ms_ = std::max(2, std::min(o.dav_max_space, 40));
+    keep_ = std::max(1, std::min(o.dav_keep, ms_ - 1));
+    V_.alloc(sizeof(double) * n * ms_, s_);
+    W_.alloc(sizeof(double) * n * ms_, s_);
+    r_.alloc(sizeof(double) * n, s_);
+    t_.alloc(sizeof(double) * n, s_);
+    xr_.alloc(sizeof(double) * n, s_);
+    wr_.alloc(sizeof(double) * n, s_);
+    scr_.alloc(sizeof(double) * n * keep_, s_);
+    part_.alloc(sizeof(double) * kDotBlocks * 40, s_);
+    dout_.alloc(sizeof(double) * 40, s_);
+    hdot_.resize(40);
+    G_.assign(size_t(ms_) * ms_, 0.0);
+    prec_ = o.prec;
+    refined_ = (prec_ == Prec::F64);
+    const double nx = std::sqrt(dots(x, 0, 1, x)[0]);
     check_finite(nx, "Davidson start vector");
     require(nx > 0, "Davidson start vector is zero", E_NUMERIC);
-    launch_copy(Vp, x, n, s);
-    launch_scale(Vp, 1.0 / nx, n, s);
-    apply(Vp, Wp);
-    int k = 1, napply = 1;
-    std::vector<double> G(size_t(ms) * ms, 0.0);
-    G[0] = dots.run(Vp, 0, 1, Wp, n, s)[0];
-    std::vector<double> w, U;
-    DavOut out{0, 0, 0};
-    bool refined = (prec == Prec::F64);
-    std::vector<double> rn_hist;
-    while (true) {
-        std::vector<double> Gk(size_t(k) * k);
-        for (int a = 0; a < k; ++a)
-            for (int b = 0; b < k; ++b) Gk[a * k + b] = 0.5 * (G[a * ms + b] + G[b * ms + a]);
-        sym_eig(k, Gk, w, U);
-        const double theta = w[0];
-        check_finite(theta, "Rayleigh quotient");
-        Coefs cu{};
-        for (int a = 0; a < k; ++a) cu.c[a] = U[a * k + 0];
-        launch_lincomb(xr.as<double>(), Vp, n, k, cu, n, s);
-        launch_lincomb(wr.as<double>(), Wp, n, k, cu, n, s);
-        launch_residual(r.as<double>(), wr.as<double>(), xr.as<double>(), theta, n, s);
-        const double rn = std::sqrt(dots.run(r.as<double>(), 0, 1, r.as<double>(), n, s)[0]);
-        check_finite(rn, "Davidson residual");
-        out = {theta, rn, napply};
-        // the low-precision residual cannot fall below ~u |theta| (u = unit
-        // roundoff of the contraction precision): refine once it reaches
-        // that floor, the requested tolerance, or stops decreasing
-        bool stalled = false;
-        if (!refined) {
-            rn_hist.push_back(rn);
-            const size_t h = rn_hist.size();
-            if (h >= 4) stalled = rn > 0.9 * std::min(rn_hist[h - 4], rn_hist[h - 3]);
+    launch_copy(V(), x, n, s_);
+    launch_scale(V(), 1.0 / nx, n, s_);
+    req_ = 0;
+    first_ = true;
+}
+
+const std::vector<double>& DavSolver::dots(const double* Vb, int64_t stride, int k, const double* w) {
+    launch_multidot(Vb, stride, k, w, n_, part_.as<double>(), s_);
+    launch_reduce_partials(part_.as<double>(), k, dout_.as<double>(), s_);
+    DMRG_HIP(hipMemcpyAsync(hdot_.data(), dout_.p, sizeof(double) * k, hipMemcpyDeviceToHost, s_));
+    DMRG_HIP(hipStreamSynchronize(s_));
+    return hdot_;
+}
+
+void DavSolver::finish() {
+    launch_copy(x_, xr_.as<double>(), n_, s_);
+    DMRG_HIP(hipStreamSynchronize(s_));
+    res_.iters = napply_;
+    done_ = true;
+}
+
+bool DavSolver::advance() {
+    const int64_t n = n_;
+    double* Vp = V();
+    double* Wp = W();
+    ++napply_;
+    if (first_) {
+        k_ = 1;
+        std::fill(G_.begin(), G_.end(), 0.0);
+        G_[0] = dots(Vp, 0, 1, Wp)[0];
+        first_ = false;
+    } else {
+        const auto& g = dots(Vp, n, k_ + 1, Wp + int64_t(k_) * n);
+        for (int a = 0; a <= k_; ++a) {
+            G_[a * ms_ + k_] = g[a];
+            G_[k_ * ms_ + a] = g[a];
         }
-        const double u = prec == Prec::BF16 ? 0x1p-8 : 0x1p-24;
-        if (!refined && o.refine_tol > 0 &&
-            (rn <= std::max(o.refine_tol, 10.0 * u * std::fabs(theta)) || stalled)) {
-            // low-precision phase done: restart from the Ritz vector in FP64
-            prec = Prec::F64;
-            refined = true;
-            launch_copy(Vp, xr.as<double>(), n, s);
-            apply(Vp, Wp);
-            ++napply;
-            k = 1;
-            G[0] = dots.run(Vp, 0, 1, Wp, n, s)[0];
-            continue;
-        }
-        const bool low = !refined && o.refine_tol > 0;
-        if ((rn <= o.dav_tol && !low) || napply >= o.dav_max_iter) break;
-        if (k >= ms) {
-            // thick restart from the `keep` lowest Ritz vectors
-            for (int i = 0; i < keep; ++i) {
-                Coefs c{};
-                for (int a = 0; a < k; ++a) c.c[a] = U[a * k + i];
-                launch_lincomb(scr.as<double>() + int64_t(i) * n, Vp, n, k, c, n, s);
-            }
-            for (int i = 0; i < keep; ++i) launch_copy(Vp + int64_t(i) * n, scr.as<double>() + int64_t(i) * n, n, s);
-            for (int i = 0; i < keep; ++i) {
-                Coefs c{};
-                for (int a = 0; a < k; ++a) c.c[a] = U[a * k + i];
-                launch_lincomb(scr.as<double>() + int64_t(i) * n, Wp, n, k, c, n, s);
-            }
-            for (int i = 0; i < keep; ++i) launch_copy(Wp + int64_t(i) * n, scr.as<double>() + int64_t(i) * n, n, s);
-            std::fill(G.begin(), G.end(), 0.0);
-            for (int i = 0; i < keep; ++i) G[i * ms + i] = w[i];
-            k = keep;
-        }
-        launch_precond(t.as<double>(), r.as<double>(), st.diag.as<double>(), theta, n, s);
-        for (int pass = 0; pass < 2; ++pass) {
-            const auto& c = dots.run(Vp, n, k, t.as<double>(), n, s);
-            Coefs cc{};
-            for (int a = 0; a < k; ++a) cc.c[a] = c[a];
-            launch_axpy_many(t.as<double>(), Vp, n, k, cc, n, s);
-        }
-        const double nt = std::sqrt(dots.run(t.as<double>(), 0, 1, t.as<double>(), n, s)[0]);
-        check_finite(nt, "Davidson correction");
-        if (nt < 1e-14) break;
-        launch_copy(Vp + int64_t(k) * n, t.as<double>(), n, s);
-        launch_scale(Vp + int64_t(k) * n, 1.0 / nt, n, s);
-        apply(Vp + int64_t(k) * n, Wp + int64_t(k) * n);
-        ++napply;
-        const auto& g = dots.run(Vp, n, k + 1, Wp + int64_t(k) * n, n, s);
-        for (int a = 0; a <= k; ++a) {
-            G[a * ms + k] = g[a];
-            G[k * ms + a] = g[a];
-        }
-        ++k;
+        ++k_;
     }
-    launch_copy(x, xr.as<double>(), n, s);
-    DMRG_HIP(hipStreamSynchronize(s));
-    out.iters = napply;
-    return out;
+    const int k = k_, ms = ms_;
+    std::vector<double> Gk(size_t(k) * k);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) Gk[a * k + b] = 0.5 * (G_[a * ms + b] + G_[b * ms + a]);
+    sym_eig(k, Gk, w_, U_);
+    const double theta = w_[0];
+    check_finite(theta, "Rayleigh quotient");
+    Coefs cu{};
+    for (int a = 0; a < k; ++a) cu.c[a] = U_[a * k + 0];
+    launch_lincomb(xr_.as<double>(), Vp, n, k, cu, n, s_);
+    launch_lincomb(wr_.as<double>(), Wp, n, k, cu, n, s_);
+    launch_residual(r_.as<double>(), wr_.as<double>(), xr_.as<double>(), theta, n, s_);
+    const double rn = std::sqrt(dots(r_.as<double>(), 0, 1, r_.as<double>())[0]);
+    check_finite(rn, "Davidson residual");
+    res_ = {theta, rn, napply_};
+    // the low-precision residual cannot fall below ~u |theta| (u = unit
+    // roundoff of the contraction precision): refine once it reaches that
+    // floor, the requested tolerance, or stops decreasing
+    bool stalled = false;
+    if (!refined_) {
+        rn_hist_.push_back(rn);
+        const size_t h = rn_hist_.size();
+        if (h >= 4) stalled = rn > 0.9 * std::min(rn_hist_[h - 4], rn_hist_[h - 3]);
+    }
+    const double u = prec_ == Prec::BF16 ? 0x1p-8 : 0x1p-24;
+    if (!refined_ && o_.refine_tol > 0 &&
+        (rn <= std::max(o_.refine_tol, 10.0 * u * std::fabs(theta)) || stalled)) {
+        // low-precision phase done: restart from the Ritz vector in FP64
+        prec_ = Prec::F64;
+        refined_ = true;
+        launch_copy(Vp, xr_.as<double>(), n, s_);
+        req_ = 0;
+        first_ = true;
+        return true;
+    }
+    const bool low = !refined_ && o_.refine_tol > 0;
+    if ((rn <= o_.dav_tol && !low) || napply_ >= o_.dav_max_iter) {
+        finish();
+        return false;
+    }
+    if (k >= ms) {
+        // thick restart from the `keep` lowest Ritz vectors
+        for (double* B : {Vp, Wp}) {
+            for (int i = 0; i < keep_; ++i) {
+                Coefs c{};
+                for (int a = 0; a < k; ++a) c.c[a] = U_[a * k + i];
+                launch_lincomb(scr_.as<double>() + int64_t(i) * n, B, n, k, c, n, s_);
+            }
+            for (int i = 0; i < keep_; ++i) launch_copy(B + int64_t(i) * n, scr_.as<double>() + int64_t(i) * n, n, s_);
+        }
+        std::fill(G_.begin(), G_.end(), 0.0);
+        for (int i = 0; i < keep_; ++i) G_[i * ms + i] = w_[i];
+        k_ = keep_;
+    }
+    double* t = t_.as<double>();
+    launch_precond(t, r_.as<double>(), st_.diag.as<double>(), theta, n, s_);
+    for (int pass = 0; pass < 2; ++pass) {
+        const auto& c = dots(Vp, n, k_, t);
+        Coefs cc{};
+        for (int a = 0; a < k_; ++a) cc.c[a] = c[a];
+        launch_axpy_many(t, Vp, n, k_, cc, n, s_);
+    }
+    const double nt = std::sqrt(dots(t, 0, 1, t)[0]);
+    check_finite(nt, "Davidson correction");
+    if (nt < 1e-14) {
+        finish();
+        return false;
+    }
+    launch_copy(Vp + int64_t(k_) * n, t, n, s_);
+    launch_scale(Vp + int64_t(k_) * n, 1.0 / nt, n, s_);
+    req_ = k_;
+    return true;
+}
+
+namespace {
+
+DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& stats) {
+    DavSolver d(st, x, n, o, stats);
+    while (true) {
+        st.sigma(d.in(), d.out(), d.prec(), &stats);
+        if (!d.advance()) break;
+    }
+    return d.result();
 }
 
 }  // namespace
@@ -1451,6 +1485,20 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool
         M = std::numeric_limits<int>::max();
         t1 = t2 = t0;
     }
+    const auto t3 = clk::now();
+    return finish_step(M, forward, o, stt, solve, dv, sec(t0, t1), sec(t1, t2), sec(t2, t3), sig0);
+}
+
+// Truncation (sector SVD), new site tensors, environment update and the next
+// two-site guess, after the two-site vector has been solved for.
+double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool solve,
+                          const DavOut& dv, double tb, double td, double tv, double sig0) {
+    const int K = mpo->K;
+    const int j = center;
+    hipStream_t s = ctx->stream;
+    using clk = std::chrono::steady_clock;
+    auto sec = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+    if (!solve) M = std::numeric_limits<int>::max();
     const auto t3 = clk::now();
 
     // sector-wise SVD of psi_q (rows sys, cols env)
@@ -1640,9 +1688,8 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool
                 "block+lists %.3fs diag %.3fs davidson %.3fs (sigma %.3fs) svd %.3fs "
                 "update+next %.3fs total %.3fs\n",
                 j, forward ? "fwd" : "bwd", (long long)ts_n_at_solve, ts_nq_at_solve, dv.iters,
-                dv.theta, dv.rnorm, bonds[forward ? j + 1 : j + 1].total, stt.discarded, sec(t0, t1),
-                sec(t1, t2), sec(t2, t3), stt.sigma_seconds - sig0, sec(t3, t4), sec(t4, t5),
-                sec(t0, t5));
+                dv.theta, dv.rnorm, bonds[j + 1].total, stt.discarded, tb, td, tv,
+                stt.sigma_seconds - sig0, sec(t3, t4), sec(t4, t5), tb + td + tv + sec(t3, t5));
     }
     return dv.theta;
 }

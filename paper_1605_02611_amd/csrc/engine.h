@@ -119,8 +119,13 @@ struct GemmList {
         flops = model_flops = 0;
     }
     bool sigma_role = false;  // launch under the sigma-vector kernel symbol
+    DevBuf dbases;            // device copy of the buffer table
+    Bases hbases{};           // host copy (kept alive for the async upload)
     void upload(hipStream_t s);
-    void launch(Prec p, const Bases& b, hipStream_t s) const;
+    // upload the 8-entry buffer table and launch
+    void launch(Prec p, const Bases& b, hipStream_t s);
+    // launch with a device buffer table already in place
+    void launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const;
 };
 // Check every access of a task list against the element counts of the
 // buffers it addresses (throws instead of letting a kernel fault).
@@ -152,6 +157,7 @@ struct Ctx {
     rocblas_handle blas = nullptr;
     std::string err;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    int max_lds = 0;  // bytes of LDS one workgroup may allocate on this device
 };
 
 struct SweepOpts {
@@ -169,6 +175,49 @@ struct StepStats {
     double gemm_seconds = 0;  // the two grouped-GEMM launches of each sigma
     int64_t sigma_calls = 0, dav_iters = 0, gemm_launches = 0;
     int max_bond = 0;
+};
+
+struct DavOut {
+    double theta = 0, rnorm = 0;
+    int iters = 0;
+};
+
+class State;
+
+// Davidson eigensolver (FP64 control) advanced one sigma at a time, so that
+// several instances can share one grouped sigma launch per iteration.
+// Diagonal preconditioner r / (theta - H_ii), two classical Gram-Schmidt
+// passes, thick restart from the `keep` lowest Ritz vectors; low-precision
+// contractions hand over to FP64 once the residual reaches their floor.
+class DavSolver {
+  public:
+    DavSolver(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& stats);
+    const double* in() const { return V_.as<double>() + int64_t(req_) * n_; }
+    double* out() const { return W_.as<double>() + int64_t(req_) * n_; }
+    Prec prec() const { return prec_; }
+    bool done() const { return done_; }
+    // consume the sigma result in out(); false when finished (x holds the vector)
+    bool advance();
+    DavOut result() const { return res_; }
+    StepStats& stats() { return stats_; }
+
+  private:
+    const std::vector<double>& dots(const double* Vb, int64_t stride, int k, const double* w);
+    void finish();
+    double* V() { return V_.as<double>(); }
+    double* W() { return W_.as<double>(); }
+    State& st_;
+    double* x_;
+    int64_t n_;
+    SweepOpts o_;
+    StepStats& stats_;
+    hipStream_t s_;
+    int ms_ = 24, keep_ = 4, k_ = 0, req_ = 0, napply_ = 0;
+    bool first_ = true, refined_ = true, done_ = false;
+    Prec prec_ = Prec::F64;
+    DevBuf V_, W_, r_, t_, xr_, wr_, scr_, part_, dout_;
+    std::vector<double> hdot_, G_, w_, U_, rn_hist_;
+    DavOut res_;
 };
 
 // The MPS with its environments and the current two-site center.
@@ -201,9 +250,12 @@ class State {
                         const double* values, int center_j);
     // operations
     void prepare();                      // blocking + task lists at the center
+    void ensure_f32();                   // FP32 copies of the blocked operators
     void sigma(const double* x, double* y, Prec p, StepStats* st);
     void build_diag();
     double step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve = true);
+    double finish_step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve,
+                       const DavOut& dv, double tb, double td, double tv, double sig0);
     double energy();
     void env_dense(int side, int bond, std::vector<double>& out);
 
@@ -217,5 +269,10 @@ class State {
     void form_center_from_pair(const Merged& A, const Merged& B);
     void release_workspace();
 };
+
+// Lockstep sweeps of independent instances with batched sigma launches.
+void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M, int n_sweeps,
+                   const SweepOpts& o, std::vector<std::vector<StepStats>>& stats,
+                   std::vector<std::vector<double>>& seconds, double* batch_sigma_seconds);
 
 }  // namespace dmrg

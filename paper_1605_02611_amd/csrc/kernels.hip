@@ -63,13 +63,15 @@ struct Cfg<2> {
 template <int MODE, int ROLE>
 __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                     const GemmTerm* __restrict__ terms,
-                                                    Bases bases) {
+                                                    void* const* __restrict__ bases,
+                                                    const int* __restrict__ active) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
     __shared__ T As[KS][kTile + 4];
     __shared__ T Bs[KS][kTile + 4];
 
     const GemmTask task = tasks[blockIdx.x];
+    if (active && !active[task.inst]) return;  // uniform per workgroup
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -79,13 +81,17 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
     const int lk = lane >> 4;   // k-group of the lane
 
     Acc acc[2][2];
+    bool act[2][2];  // 16x16 sub-tile overlaps the task's m x n (uniform per wave)
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = Acc{0, 0, 0, 0};
+            act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
+        }
 
     for (int l = task.l_begin; l < task.l_end; ++l) {
         const GemmTerm g = terms[l];
-        const T* A = static_cast<const T*>(bases.p[g.a_buf]) + g.a_off;
-        const T* B = static_cast<const T*>(bases.p[g.b_buf]) + g.b_off;
+        const T* A = static_cast<const T*>(bases[g.a_buf]) + g.a_off;
+        const T* B = static_cast<const T*>(bases[g.b_buf]) + g.b_off;
         const T alpha = T(g.alpha);
         const bool ta = g.flags & GT_TA;
         const bool tb = g.flags & GT_TB;
@@ -118,27 +124,29 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
                 Bs[kb][c] = u;
             }
             __syncthreads();
+            // skip 16x16 sub-tiles outside the task and K-steps past the slice
+            const int kv = min(KS, g.k - k0);
             if constexpr (MODE == 0) {
-                for (int ks = 0; ks < KS; ks += 4) {
-                    double a0 = As[ks + lk][wm + lr];
-                    double a1 = As[ks + lk][wm + 16 + lr];
-                    double b0 = Bs[ks + lk][wn + lr];
-                    double b1 = Bs[ks + lk][wn + 16 + lr];
-                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                for (int ks = 0; ks < kv; ks += 4) {
+                    const double a0 = As[ks + lk][wm + lr];
+                    const double a1 = As[ks + lk][wm + 16 + lr];
+                    const double b0 = Bs[ks + lk][wn + lr];
+                    const double b1 = Bs[ks + lk][wn + 16 + lr];
+                    if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                    if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                    if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                    if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
                 }
             } else if constexpr (MODE == 1) {
-                for (int ks = 0; ks < KS; ks += 4) {
-                    float a0 = As[ks + lk][wm + lr];
-                    float a1 = As[ks + lk][wm + 16 + lr];
-                    float b0 = Bs[ks + lk][wn + lr];
-                    float b1 = Bs[ks + lk][wn + 16 + lr];
-                    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+                for (int ks = 0; ks < kv; ks += 4) {
+                    const float a0 = As[ks + lk][wm + lr];
+                    const float a1 = As[ks + lk][wm + 16 + lr];
+                    const float b0 = Bs[ks + lk][wn + lr];
+                    const float b1 = Bs[ks + lk][wn + 16 + lr];
+                    if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                    if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                    if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                    if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
                 }
             } else {
                 // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
@@ -150,8 +158,8 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
                     }
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j)
-                        acc[i][j] =
-                            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                        if (act[i][j])
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
     // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds
     // row 4 lk + e for the FP32 MFMAs but row 4 e + lk for the FP64 MFMA
     // (checked on gfx950 with a probe of known products).
-    T* C = static_cast<T*>(bases.p[task.c_buf]) + task.c_off;
+    T* C = static_cast<T*>(bases[task.c_buf]) + task.c_off;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int e = 0; e < 4; ++e) {
@@ -346,15 +354,19 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs) {
+__global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs, int lds_elems) {
+    extern __shared__ double smem[];
     const SvdJob job = jobs[blockIdx.x];
     const int R = job.rows, C = job.cols;
     const bool tr = R < C;
     const int m = tr ? C : R;  // column length
     const int n = tr ? R : C;  // number of columns (= r)
-    double* A = job.work;               // column j at A + j * m
-    double* V = job.work + int64_t(m) * n;  // column j at V + j * n
-    double* nrm = V + int64_t(n) * n;
+    // the working columns (and the rotations when they fit too) live in LDS
+    const bool a_lds = int64_t(m) * n <= lds_elems;
+    const bool v_lds = int64_t(m) * n + int64_t(n) * n <= lds_elems;
+    double* A = a_lds ? smem : job.work;  // column j at A + j * m
+    double* V = v_lds ? smem + int64_t(m) * n : job.work + int64_t(m) * n;  // column j at V + j * n
+    double* nrm = job.work + int64_t(m) * n + int64_t(n) * n;
     int* perm = reinterpret_cast<int*>(nrm + n);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int64_t e = tid; e < int64_t(m) * n; e += blockDim.x) {
@@ -467,20 +479,20 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 template <int ROLE>
 static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                             const Bases& b, hipStream_t s) {
+                             void* const* b, const int* act, hipStream_t s) {
     if (n_tasks <= 0) return;
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
         const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((grouped_gemm<0, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((grouped_gemm<1, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((grouped_gemm<2, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
                 break;
         }
     }
@@ -488,12 +500,12 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 }
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 const Bases& b, hipStream_t s) {
-    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, s);
+                 void* const* b, const int* act, hipStream_t s) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, s);
 }
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       const Bases& b, hipStream_t s) {
-    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, s);
+                       void* const* b, const int* act, hipStream_t s) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, s);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {
@@ -598,9 +610,10 @@ void launch_gather_rows(double* dst, int dld, const double* src, int sld, const 
     DMRG_HIP(hipGetLastError());
 }
 
-void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, hipStream_t s) {
+void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, int lds_elems, hipStream_t s) {
     if (n_jobs <= 0) return;
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(n_jobs), dim3(256), 0, s, jobs);
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(n_jobs), dim3(256), size_t(lds_elems) * sizeof(double), s,
+                       jobs, lds_elems);
     DMRG_HIP(hipGetLastError());
 }
 

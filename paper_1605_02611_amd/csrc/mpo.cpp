@@ -18,6 +18,7 @@
 // operators.  The rules below are that identity applied to each operator of
 // Eqs. Sm / norm_complementary; hermitian-conjugate channels use
 // W[xbar, ybar] = eps_x eps_y W[x, y]^T (eps = -1 for odd channels).
+#include <algorithm>
 #include <cmath>
 #include <unordered_map>
 
@@ -449,6 +450,8 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
     Builder b(h, v, K, m->switch_bond);
     m->W.resize(K);
     m->fine.resize(K);
+    m->sys_groups.resize(K);
+    m->env_groups.resize(K);
     for (int j = 0; j < K; ++j) {
         b.site(j, m->chans[j], m->chans[j + 1], m->W[j]);
         auto& f = m->fine[j];
@@ -457,6 +460,33 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
                 for (int s = 0; s < 4; ++s)
                     if (mat(sp, s) != 0.0)
                         f.push_back({xy.first, xy.second, int8_t(sp), int8_t(s), mat(sp, s)});
+        // groupings used by the blocking step, sorted once here
+        for (int side = 0; side < 2; ++side) {
+            std::vector<int> idx(f.size());
+            for (size_t i = 0; i < idx.size(); ++i) idx[i] = int(i);
+            auto key = [&](const FineW& e) { return side == 0 ? e.y : e.x; };
+            auto other = [&](const FineW& e) { return side == 0 ? e.x : e.y; };
+            std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+                const FineW &p = f[a], &q = f[b];
+                if (key(p) != key(q)) return key(p) < key(q);
+                if (p.sp != q.sp) return p.sp < q.sp;
+                if (p.s != q.s) return p.s < q.s;
+                return other(p) < other(q);
+            });
+            WGroups& G = side == 0 ? m->sys_groups[j] : m->env_groups[j];
+            for (size_t i = 0; i < idx.size();) {
+                const FineW& hd = f[idx[i]];
+                size_t e = i;
+                while (e < idx.size() && key(f[idx[e]]) == key(hd) && f[idx[e]].sp == hd.sp &&
+                       f[idx[e]].s == hd.s)
+                    ++e;
+                WGroup g{key(hd), hd.sp, hd.s, int(G.terms.size()), 0};
+                for (size_t k = i; k < e; ++k) G.terms.push_back({other(f[idx[k]]), f[idx[k]].c});
+                g.end = int(G.terms.size());
+                G.groups.push_back(g);
+                i = e;
+            }
+        }
     }
     return m;
 }

@@ -238,3 +238,37 @@ def test_full_size_energy_is_gauge_invariant(big):
     e2 = mps.energy()
     assert abs(e1 - e0) <= 1e-10 * abs(e0)
     assert abs(e2 - e0) <= 1e-10 * abs(e0)
+
+
+# --- batched lockstep sweeps -----------------------------------------------------------
+
+def _batch_instances():
+    out = []
+    for K, N, M, seed, kind in [(6, 6, 12, 201, "chain"), (7, 7, 16, 202, "chain"),
+                                (5, 4, 8, 203, "random"), (8, 8, 24, 204, "chain")]:
+        I = (chain_integrals(K, n_elec=N, seed=seed) if kind == "chain"
+             else random_integrals_cfg1(K=K, n_elec=N, seed=seed, rank=3))
+        out.append((I, M, seed))
+    return out
+
+
+@pytest.mark.parametrize("prec", [P.DMRG_FP64, P.DMRG_FP32])
+def test_batched_sweeps_equal_individual_sweeps(ctx, prec):
+    _log("batched", prec)
+    opts = P.default_opts(prec=prec, refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    inst = _batch_instances()
+    mpos = [P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz) for I, M, seed in inst]
+    singles = []
+    for (I, M, seed), mpo in zip(inst, mpos):
+        mps = P.Mps.random(ctx, mpo, M, mps_values(seed, mpo.n_values(M)))
+        st, _ = mps.sweep(M, 2, opts)
+        singles.append(([s["energy"] for s in st], mps.energy(), mps.bond(I.K // 2)))
+    states = [P.Mps.random(ctx, mpo, M, mps_values(seed, mpo.n_values(M)))
+              for (I, M, seed), mpo in zip(inst, mpos)]
+    stats, bsec = P.sweep_batched(ctx, states, [M for _, M, _ in inst], 2, opts)
+    assert bsec > 0
+    for b, ((I, M, seed), mps) in enumerate(zip(inst, states)):
+        es = [s["energy"] for s in stats[b]]
+        assert np.abs(np.array(es) - np.array(singles[b][0])).max() < 1e-9
+        assert abs(mps.energy() - singles[b][1]) < 1e-9
+        assert mps.bond(I.K // 2) == singles[b][2]
