@@ -275,8 +275,8 @@ void State::set_bond(int k, const std::vector<std::pair<QN, int>>& secs) {
 std::unique_ptr<Env> State::trivial_env(int bond) {
     auto e = std::make_unique<Env>();
     e->bond = bond;
-    e->off = {0};
-    e->total = 1;
+    e->lay_out(bonds[bond], {QN{0, 0}});
+    require(e->total == 1, "internal: boundary bond must hold one state", E_STATE);
     e->buf.alloc(sizeof(double), ctx->stream);
     launch_fill(e->buf.as<double>(), 1.0, 1, ctx->stream);
     return e;
@@ -286,79 +286,186 @@ std::unique_ptr<Env> State::trivial_env(int bond) {
 // blocking: Y_(y,sp,s) = sum_x W_j[x,y](sp,s) L_j[x]   (left block (x) site j)
 //           Z_(x,sp,s) = sum_y W_k[x,y](sp,s) R_{k+1}[y] (site k (x) right block)
 
-static void run_wsum(Blocked& B, const double* src_base, const std::vector<int64_t>& src_off,
-                     hipStream_t s) {
-    std::vector<SumItem> items;
-    std::vector<SumTerm> terms;
-    terms.reserve(B.terms.size());
-    for (auto& [x, c] : B.terms) terms.push_back({src_base + src_off[x], c});
-    constexpr int64_t kChunk = 16384;
-    for (const BRow& r : B.rows) {
-        const int64_t n = r.lay->size;
-        for (int64_t e = 0; e < n; e += kChunk)
-            items.push_back({B.buf.as<double>() + r.off, e, std::min(n, e + kChunk), r.t_begin,
-                             r.t_end});
+void Env::lay_out(const BondL& b, const std::vector<QN>& chan_dq) {
+    const int nch = int(chan_dq.size());
+    off.assign(nch, 0);
+    cls.clear();
+    cls_of.assign(nch, -1);
+    pos.assign(nch, -1);
+    std::map<QN, int> idx;
+    for (int x = 0; x < nch; ++x) {
+        auto it = idx.find(chan_dq[x]);
+        if (it == idx.end()) {
+            it = idx.emplace(chan_dq[x], int(cls.size())).first;
+            EnvClass c;
+            c.dq = chan_dq[x];
+            c.stride = b.layout(chan_dq[x]).size;
+            cls.push_back(c);
+        }
+        cls_of[x] = it->second;
+        pos[x] = int(cls[it->second].chans.size());
+        cls[it->second].chans.push_back(x);
     }
-    if (items.empty()) return;
-    DevBuf di(items.size() * sizeof(SumItem), s), dt(std::max<size_t>(1, terms.size()) * sizeof(SumTerm), s);
-    DMRG_HIP(hipMemcpyAsync(di.p, items.data(), items.size() * sizeof(SumItem), hipMemcpyHostToDevice, s));
-    if (!terms.empty())
-        DMRG_HIP(hipMemcpyAsync(dt.p, terms.data(), terms.size() * sizeof(SumTerm),
-                                hipMemcpyHostToDevice, s));
-    launch_wsum(di.as<SumItem>(), int64_t(items.size()), dt.as<SumTerm>(), s);
-    DMRG_HIP(hipStreamSynchronize(s));
+    total = 0;
+    for (EnvClass& c : cls) {
+        c.base = total;
+        for (int x : c.chans) off[x] = total + int64_t(pos[x]) * c.stride;
+        total += int64_t(c.chans.size()) * c.stride;
+    }
 }
 
 // side 0: Y rows from L_j and the groups of W[j] by right channel
 // side 1: Z rows from R_{k+1} and the groups of W[k] by left channel
-static Blocked make_blocked(const MPO& mpo, const BondL& bond, const WGroups& G,
-                            const std::vector<QN>& src_dq, int n_chan, int id_kind,
-                            const std::vector<Chan>& row_chans) {
+// Rows are stored grouped by the class (shift) of their source operators.
+static Blocked make_blocked(const BondL& bond, const WGroups& G, const Env& src, int n_chan,
+                            int id_kind, const std::vector<Chan>& row_chans) {
     Blocked B;
     B.n_chan = n_chan;
     B.find.assign(size_t(n_chan) * 16, -1);
+    B.cls.resize(src.cls.size());
+    for (size_t c = 0; c < src.cls.size(); ++c) B.cls[c].src = int(c);
     for (const WGroup& g : G.groups) {
-        const QN dq = src_dq[G.terms[g.begin].first];
-        const OpLayout& lay = bond.layout(dq);
+        const int c = src.cls_of[G.terms[g.begin].first];
+        const EnvClass& ec = src.cls[c];
+        const OpLayout& lay = bond.layout(ec.dq);
         if (lay.size == 0) continue;
         BRow r;
         r.y = g.ch;
         r.sp = g.sp;
         r.s = g.s;
-        r.dq = dq;
-        r.off = B.total;
+        r.dq = ec.dq;
         r.lay = &lay;
         r.t_begin = int(B.terms.size());
         for (int k = g.begin; k < g.end; ++k) {
-            require(bond.layout(src_dq[G.terms[k].first]).size == lay.size,
-                    "internal: blocking terms with different layouts", E_STATE);
+            require(src.cls_of[G.terms[k].first] == c, "internal: blocking terms of different shifts",
+                    E_STATE);
             B.terms.push_back(G.terms[k]);
         }
         r.t_end = int(B.terms.size());
         r.identity = row_chans[g.ch].kind == id_kind;
         B.find[size_t(g.ch) * 16 + g.sp * 4 + g.s] = int(B.rows.size());
+        B.cls[c].rows.push_back(int(B.rows.size()));
         B.rows.push_back(r);
-        B.total += lay.size;
     }
-    (void)mpo;
+    for (BClass& bc : B.cls) {
+        bc.size = src.cls[bc.src].stride;
+        bc.base = B.total;
+        for (size_t i = 0; i < bc.rows.size(); ++i) B.rows[bc.rows[i]].off = B.total + int64_t(i) * bc.size;
+        B.total += int64_t(bc.rows.size()) * bc.size;
+    }
     return B;
 }
 
+// Blocking of one class is the product (coefficients: rows x source
+// operators) x (source operators x layout elements).  Classes whose rows sum
+// many operators run as a GEMM on the MFMA kernel (each source element is
+// read once for all rows); the few-term classes run the weighted-sum kernel.
+void State::run_blocking(Blocked& B, const Env& src, int plan_key) {
+    hipStream_t s = ctx->stream;
+    const int nc = int(B.cls.size());
+    std::vector<int64_t> key;
+    key.reserve(size_t(nc) * 4);
+    for (const BClass& bc : B.cls) {
+        key.push_back(int64_t(bc.rows.size()));
+        key.push_back(bc.size);
+        key.push_back(bc.base);
+        key.push_back(src.cls[bc.src].base);
+    }
+    BlockPlan& P = plans[plan_key];
+    if (P.key != key) {
+        P.key = key;
+        P.gemm.clear();
+        P.dense.assign(nc, 0);
+        std::vector<int64_t> cm_off(nc, -1);
+        int64_t cm_tot = 0;
+        for (int c = 0; c < nc; ++c) {
+            const BClass& bc = B.cls[c];
+            const int64_t nr = int64_t(bc.rows.size()), nx = int64_t(src.cls[bc.src].chans.size());
+            if (nr == 0 || bc.size == 0) continue;
+            int64_t nt = 0;
+            for (int ri : bc.rows) nt += B.rows[ri].t_end - B.rows[ri].t_begin;
+            // seconds: weighted sums read every term's operator; the GEMM
+            // pays its flops and one pass over sources and rows
+            const double t_sum = double(nt + nr) * bc.size * 8.0 / 3e12;
+            const double t_gemm = 2.0 * nr * nx * bc.size / 15e12 + double(nr + nx) * bc.size * 8.0 / 4e12;
+            if (nx < 2 || t_gemm >= t_sum) continue;
+            P.dense[c] = 1;
+            cm_off[c] = cm_tot;
+            cm_tot += nr * nx;
+        }
+        std::vector<double> cm(std::max<int64_t>(1, cm_tot), 0.0);
+        std::vector<UTerm> ut(1);
+        for (int c = 0; c < nc; ++c) {
+            if (!P.dense[c]) continue;
+            const BClass& bc = B.cls[c];
+            const EnvClass& ec = src.cls[bc.src];
+            const int nx = int(ec.chans.size());
+            for (size_t i = 0; i < bc.rows.size(); ++i) {
+                const BRow& r = B.rows[bc.rows[i]];
+                for (int t = r.t_begin; t < r.t_end; ++t)
+                    cm[cm_off[c] + int64_t(i) * nx + src.pos[B.terms[t].first]] += B.terms[t].second;
+            }
+            ut[0] = {0, cm_off[c], nx, false, 1, ec.base, int(bc.size), false, nx, 1.0, false};
+            add_unit(P.gemm, 2, bc.base, int(bc.size), int(bc.rows.size()), int(bc.size), 0, ut);
+        }
+        P.cm.alloc(cm.size() * sizeof(double), s);
+        DMRG_HIP(hipMemcpyAsync(P.cm.p, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        int64_t sz[kMaxBufs] = {int64_t(cm.size()), src.total, B.total};
+        validate_list(P.gemm, sz);
+        P.gemm.upload(s);
+    }
+    if (!P.gemm.tasks.empty()) {
+        Bases b{};
+        b.p[0] = P.cm.p;
+        b.p[1] = src.buf.p;
+        b.p[2] = B.buf.p;
+        P.gemm.launch(Prec::F64, b, s);
+    }
+    // the remaining classes: weighted sums
+    std::vector<SumItem> items;
+    std::vector<SumTerm> terms;
+    const double* src_base = src.buf.as<double>();
+    constexpr int64_t kChunk = 16384;
+    for (int c = 0; c < nc; ++c) {
+        if (P.dense[c]) continue;
+        for (int ri : B.cls[c].rows) {
+            const BRow& r = B.rows[ri];
+            const int tb = int(terms.size());
+            for (int t = r.t_begin; t < r.t_end; ++t)
+                terms.push_back({src_base + src.off[B.terms[t].first], B.terms[t].second});
+            const int64_t n = r.lay->size;
+            for (int64_t e = 0; e < n; e += kChunk)
+                items.push_back({B.buf.as<double>() + r.off, e, std::min(n, e + kChunk), tb, int(terms.size())});
+        }
+    }
+    DevBuf di, dt;
+    if (!items.empty()) {
+        di.alloc(items.size() * sizeof(SumItem), s);
+        dt.alloc(std::max<size_t>(1, terms.size()) * sizeof(SumTerm), s);
+        DMRG_HIP(hipMemcpyAsync(di.p, items.data(), items.size() * sizeof(SumItem), hipMemcpyHostToDevice, s));
+        if (!terms.empty())
+            DMRG_HIP(hipMemcpyAsync(dt.p, terms.data(), terms.size() * sizeof(SumTerm),
+                                    hipMemcpyHostToDevice, s));
+        launch_wsum(di.as<SumItem>(), int64_t(items.size()), dt.as<SumTerm>(), s);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+}
+
 Blocked State::block_sys(int j, const Env& Lj) {
-    Blocked B = make_blocked(*mpo, bonds[j], mpo->sys_groups[j], mpo->chan_dq[j],
-                             int(mpo->chans[j + 1].size()), CK_I, mpo->chans[j + 1]);
+    Blocked B = make_blocked(bonds[j], mpo->sys_groups[j], Lj, int(mpo->chans[j + 1].size()), CK_I,
+                             mpo->chans[j + 1]);
     B.bond = j;
     B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
-    run_wsum(B, Lj.buf.as<double>(), Lj.off, ctx->stream);
+    run_blocking(B, Lj, j);
     return B;
 }
 
 Blocked State::block_env(int k, const Env& Rk1) {
-    Blocked B = make_blocked(*mpo, bonds[k + 1], mpo->env_groups[k], mpo->chan_dq[k + 1],
-                             int(mpo->chans[k].size()), CK_H, mpo->chans[k]);
+    Blocked B = make_blocked(bonds[k + 1], mpo->env_groups[k], Rk1, int(mpo->chans[k].size()), CK_H,
+                             mpo->chans[k]);
     B.bond = k + 1;
     B.buf.alloc(std::max<int64_t>(1, B.total) * sizeof(double), ctx->stream);
-    run_wsum(B, Rk1.buf.as<double>(), Rk1.off, ctx->stream);
+    run_blocking(B, Rk1, 4096 + k);
     return B;
 }
 
@@ -429,11 +536,7 @@ std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged
 
     auto E = std::make_unique<Env>();
     E->bond = j + 1;
-    E->off.resize(nch);
-    for (int y = 0; y < nch; ++y) {
-        E->off[y] = E->total;
-        E->total += bn.layout(mpo->chan_dq[j + 1][y]).size;
-    }
+    E->lay_out(bn, mpo->chan_dq[j + 1]);
     E->buf.alloc(std::max<int64_t>(1, E->total) * sizeof(double), s);
     GemmList p2;
     for (int y = 0; y < nch; ++y) {
@@ -521,11 +624,7 @@ std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merge
 
     auto E = std::make_unique<Env>();
     E->bond = k;
-    E->off.resize(nch);
-    for (int x = 0; x < nch; ++x) {
-        E->off[x] = E->total;
-        E->total += bn.layout(mpo->chan_dq[k][x]).size;
-    }
+    E->lay_out(bn, mpo->chan_dq[k]);
     E->buf.alloc(std::max<int64_t>(1, E->total) * sizeof(double), s);
     GemmList p2;
     for (int x = 0; x < nch; ++x) {

@@ -77,11 +77,23 @@ struct Merged {
 
 // Renormalized operators of a block at one bond: one block-sparse operator
 // per MPO channel, laid out by the channel's quantum-number shift.
+// Renormalized operators of one shift (change of quantum numbers) share one
+// block layout; they are stored back to back so that the operators of a
+// class form one row-major matrix (operators x layout elements).
+struct EnvClass {
+    QN dq;
+    int64_t base = 0, stride = 0;  // offset of the first operator; elements per operator
+    std::vector<int> chans;        // channels in storage order
+};
 struct Env {
     int bond = -1;
     std::vector<int64_t> off;
     int64_t total = 0;
     DevBuf buf;
+    std::vector<EnvClass> cls;
+    std::vector<int> cls_of, pos;  // per channel: class and position inside it
+    // offsets grouped by shift, classes in order of first appearance
+    void lay_out(const BondL& b, const std::vector<QN>& chan_dq);
 };
 
 // Blocked operators (Eq. prenormmatrix): for each (channel y, local sp <- s)
@@ -94,10 +106,18 @@ struct BRow {
     int t_begin, t_end;  // terms in Blocked::terms
     bool identity;       // a pure identity (costs no model flops)
 };
+// Rows of one source class: stored back to back (stride = layout size).
+struct BClass {
+    int src = -1;      // class of the source environment
+    int64_t base = 0;  // offset of the first row
+    int64_t size = 0;  // elements per row
+    std::vector<int> rows;
+};
 struct Blocked {
     int bond = -1;
     int n_chan = 0;
     std::vector<BRow> rows;
+    std::vector<BClass> cls;
     std::vector<std::pair<int, double>> terms;  // (source channel, coefficient)
     std::vector<int> find;                      // [y*16 + sp*4 + s] -> row or -1
     int64_t total = 0;
@@ -244,6 +264,16 @@ class State {
     DevBuf diag;
     bool diag_ok = false;
 
+    // blocking plans per (side, site): dense coefficient matrices of the
+    // classes that go through the GEMM and their task lists
+    struct BlockPlan {
+        std::vector<int64_t> key;
+        DevBuf cm;
+        GemmList gemm;
+        std::vector<char> dense;  // per blocked class
+    };
+    std::map<int, BlockPlan> plans;
+
     // setup
     void init_random(int M, const double* values, int64_t n_values);
     void import_tensors(const std::vector<std::vector<std::pair<QN, int>>>& bonds_in,
@@ -262,6 +292,7 @@ class State {
   private:
     void set_bond(int k, const std::vector<std::pair<QN, int>>& secs);
     std::unique_ptr<Env> trivial_env(int bond);
+    void run_blocking(Blocked& B, const Env& src, int plan_key);
     Blocked block_sys(int j, const Env& Lj);
     Blocked block_env(int k, const Env& Rk1);
     std::unique_ptr<Env> decimate_left(const Blocked& Yb, int j, const Merged& A);
