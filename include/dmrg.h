@@ -169,10 +169,12 @@ dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bo
  * accumulate != 0).  A, B, C are DEVICE FP64 pointers, row-major with leading
  * dimensions lda, ldb, ldc; op(A) is m x k (ta != 0: A is stored k x m),
  * op(B) is k x n (tb != 0: B is stored n x k).  With DMRG_FP32 / DMRG_BF16
- * the operands are rounded to FP32 first and the result converted back. */
+ * the operands are rounded to FP32 first and the result converted back.
+ * tile: 64 (workgroup tiles staged through LDS) or 32 (one task per wave,
+ * operands loaded straight into registers). */
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
-                            double* C, int ldc, int accumulate);
+                            double* C, int ldc, int accumulate, int tile);
 
 /* ---- sweeps (Sec. 2.1) ---------------------------------------------------- */
 

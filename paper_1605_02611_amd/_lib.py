@@ -64,7 +64,7 @@ SIGNATURES = {
     "dmrg_sigma_diag": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_env_export": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double)]),
     "dmrg_debug_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
-                                c_void_p, c_int, c_void_p, c_int, c_void_p, c_int, c_int]),
+                                c_void_p, c_int, c_void_p, c_int, c_void_p, c_int, c_int, c_int]),
     "dmrg_sweep_opts_default": (None, [P(SweepOpts)]),
     "dmrg_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, P(SweepOpts),
                            P(SweepStat), P(c_double)]),

@@ -65,8 +65,12 @@ struct BatchSigma {
         yout.resize(nb);
         flops.resize(nb);
         htab[0].assign(size_t(8) * nb, nullptr);
+        p1.tile = st[0]->pass1.tile;
+        p2.tile = st[0]->pass2.tile;
         for (int b = 0; b < nb; ++b) {
             State& S = *st[b];
+            require(S.pass1.tile == p1.tile && S.pass2.tile == p2.tile,
+                    "batched sigma: instances with different tile edges", E_STATE);
             merge(p1, S.pass1, b, r1);
             merge(p2, S.pass2, b, r2);
             flops[b] = S.pass1.model_flops + S.pass2.model_flops;

@@ -338,10 +338,11 @@ dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bo
 
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
-                            double* C, int ldc, int accumulate) {
+                            double* C, int ldc, int accumulate, int tile) {
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
+        require(tile == 64 || tile == 32, "tile must be 64 or 32");
         require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
         require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
         use_device(ctx->c);
@@ -350,6 +351,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
         const int64_t nb = tb ? int64_t(n - 1) * ldb + k : int64_t(k - 1) * ldb + n;
         const int64_t nc = int64_t(m - 1) * ldc + n;
         GemmList L;
+        L.tile = tile;
         std::vector<UTerm> terms = {{0, 0, lda, ta != 0, 1, 0, ldb, tb != 0, k, alpha, true}};
         add_unit(L, 2, 0, ldc, m, n, accumulate ? 1 : 0, terms);
         int64_t sz[kMaxBufs] = {na, nb, nc};

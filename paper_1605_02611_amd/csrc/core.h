@@ -154,7 +154,7 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
 // serves the FP64 buffers and their FP32 copies alike.
 struct GemmTask {
     int64_t c_off;
-    int c_buf, ldc, m, n;  // m, n <= kTile
+    int c_buf, ldc, m, n;  // m, n <= the list's tile edge (64 or 32)
     int accumulate;
     int l_begin, l_end;
     int inst;  // instance of a batched launch (skipped when inactive)
@@ -178,11 +178,12 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 // bases: DEVICE array of buffer base pointers indexed by the buffer ids of
 // the tasks and terms; active: DEVICE flags per instance or nullptr
+// tile: output tile edge of every task (64 or 32)
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* bases, const int* active, hipStream_t s);
+                 void* const* bases, const int* active, hipStream_t s, int tile = kTile);
 // same kernel, separate symbol for the two passes of the sigma vector
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* bases, const int* active, hipStream_t s);
+                       void* const* bases, const int* active, hipStream_t s, int tile = kTile);
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]
 struct SumItem {

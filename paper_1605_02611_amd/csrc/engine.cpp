@@ -91,9 +91,10 @@ void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int 
         }
         for (; part < splits; ++part) cut[part] = terms.size();
     }
-    for (int r0 = 0; r0 < m; r0 += kTile)
-        for (int c0 = 0; c0 < n; c0 += kTile) {
-            const int tm = std::min(kTile, m - r0), tn = std::min(kTile, n - c0);
+    const int ts = L.tile;
+    for (int r0 = 0; r0 < m; r0 += ts)
+        for (int c0 = 0; c0 < n; c0 += ts) {
+            const int tm = std::min(ts, m - r0), tn = std::min(ts, n - c0);
             for (int sp = 0; sp < splits; ++sp) {
                 GemmTask tk;
                 tk.c_buf = c_buf;
@@ -145,16 +146,16 @@ void GemmList::launch(Prec p, const Bases& b, hipStream_t s) {
 void GemmList::launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const {
     if (sigma_role)
         launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                          dev_bases, active, s);
+                          dev_bases, active, s, tile);
     else
         launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                    dev_bases, active, s);
+                    dev_bases, active, s, tile);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
     auto bad = [](const char* what) { throw Error(E_STATE, std::string("internal: task list ") + what + " out of bounds"); };
     for (const GemmTask& t : L.tasks) {
-        if (t.c_buf < 0 || t.c_buf >= kMaxBufs || t.m < 1 || t.n < 1 || t.m > kTile || t.n > kTile) bad("task shape");
+        if (t.c_buf < 0 || t.c_buf >= kMaxBufs || t.m < 1 || t.n < 1 || t.m > L.tile || t.n > L.tile) bad("task shape");
         if (t.c_off < 0 || t.c_off + int64_t(t.m - 1) * t.ldc + t.n > sizes[t.c_buf]) bad("output");
         if (t.l_begin < 0 || t.l_end < t.l_begin || t.l_end > int(L.terms.size())) bad("term range");
         for (int l = t.l_begin; l < t.l_end; ++l) {
@@ -1175,6 +1176,7 @@ void State::prepare() {
         }
     }
     pass1.clear();
+    pass1.tile = tile_pass[0];
     std::vector<UTerm> terms;
     for (int y = 0; y < nch; ++y) {
         const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
@@ -1206,14 +1208,9 @@ void State::prepare() {
     }
     // sigma_q' [:, (t', Q'_r)] = sum_y sum_t T_y(q)[:, (t, Q_r)] Z_(y,t',t)^T
     pass2.clear();
-    int64_t tiles2 = 0;
+    pass2.tile = tile_pass[1];
     std::vector<int> unit_base(nq + 1, 0);
-    for (int iq2 = 0; iq2 < nq; ++iq2) {
-        unit_base[iq2 + 1] = unit_base[iq2] + int(ts.env[iq2].segs.size());
-        for (const Seg& so : ts.env[iq2].segs)
-            tiles2 += int64_t((ts.sys[iq2].dim + kTile - 1) / kTile) * ((so.dim + kTile - 1) / kTile);
-    }
-    splits = int(std::max<int64_t>(1, std::min<int64_t>(16, (4096 + tiles2 - 1) / std::max<int64_t>(1, tiles2))));
+    for (int iq2 = 0; iq2 < nq; ++iq2) unit_base[iq2 + 1] = unit_base[iq2] + int(ts.env[iq2].segs.size());
     std::vector<std::vector<UTerm>> uterms(unit_base[nq]);
     for (int y = 0; y < nch; ++y) {
         if (!hy[y] || !hz[y]) continue;
@@ -1243,12 +1240,35 @@ void State::prepare() {
             }
         }
     }
+    // split-K per unit in proportion to its K (sum of term lengths) so that
+    // every workgroup of pass 2 gets about the same share: the units of the
+    // large sectors would otherwise finish long after the rest.  Piece p of
+    // a unit writes slice p of the partial buffer; slices a unit does not
+    // use stay zero, and the slices are summed in a fixed order.
+    std::vector<int64_t> ku(unit_base[nq], 0), tu(unit_base[nq], 0);
+    double work = 0;
+    for (int iq2 = 0; iq2 < nq; ++iq2)
+        for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
+            const int u = unit_base[iq2] + int(ui);
+            for (const UTerm& t : uterms[u]) ku[u] += t.k;
+            tu[u] = int64_t((ts.sys[iq2].dim + pass2.tile - 1) / pass2.tile) *
+                    ((ts.env[iq2].segs[ui].dim + pass2.tile - 1) / pass2.tile);
+            work += double(tu[u]) * ku[u];
+        }
+    constexpr int kMaxSplits = 32;
+    const double k_target = std::max(64.0, work / sigma_pieces);
+    std::vector<int> su(unit_base[nq], 1);
+    splits = 1;
+    for (size_t u = 0; u < su.size(); ++u) {
+        su[u] = int(std::min<double>(kMaxSplits, std::max(1.0, std::ceil(ku[u] / k_target))));
+        splits = std::max(splits, su[u]);
+    }
     for (int iq2 = 0; iq2 < nq; ++iq2) {
         const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
         for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
             const Seg& so = ts.env[iq2].segs[ui];
-            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[unit_base[iq2] + ui],
-                     splits, ts.n);
+            const int u = unit_base[iq2] + int(ui);
+            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[u], su[u], ts.n);
         }
     }
     const BondL& br = bonds[j + 2];
@@ -1264,7 +1284,10 @@ void State::prepare() {
     pass1.upload(s);
     pass2.upload(s);
     tbuf.alloc(std::max<int64_t>(1, t_total) * sizeof(double), s);
-    if (splits > 1) part.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(double), s);
+    if (splits > 1) {
+        part.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(double), s);
+        DMRG_HIP(hipMemsetAsync(part.p, 0, part.bytes, s));
+    }
     DMRG_HIP(hipStreamSynchronize(s));
     prepared = true;
     diag_ok = false;
@@ -1287,7 +1310,10 @@ void State::ensure_f32() {
     psi32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
     sig32.alloc(std::max<int64_t>(1, ts.n) * sizeof(float), s);
     tbuf32.alloc(std::max<int64_t>(1, t_total) * sizeof(float), s);
-    if (splits > 1) part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
+    if (splits > 1) {
+        part32.alloc(std::max<int64_t>(1, int64_t(splits) * ts.n) * sizeof(float), s);
+        DMRG_HIP(hipMemsetAsync(part32.p, 0, part32.bytes, s));
+    }
 }
 
 void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
@@ -1300,6 +1326,7 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
         b1.p[1] = const_cast<double*>(x);
         b1.p[2] = tbuf.p;
         pass1.launch(Prec::F64, b1, s);
+        DMRG_HIP(hipEventRecord(ctx->ev3, s));
         Bases b2{};
         b2.p[0] = tbuf.p;
         b2.p[1] = Z.buf.p;
@@ -1316,6 +1343,7 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
         b1.p[1] = psi32.p;
         b1.p[2] = tbuf32.p;
         pass1.launch(p, b1, s);
+        DMRG_HIP(hipEventRecord(ctx->ev3, s));
         Bases b2{};
         b2.p[0] = tbuf32.p;
         b2.p[1] = Z.buf32.p;
@@ -1328,9 +1356,11 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
     DMRG_HIP(hipEventRecord(ctx->ev1, s));
     DMRG_HIP(hipEventSynchronize(ctx->ev1));
     if (st) {
-        float ms = 0, mg = 0;
+        float ms = 0, mg = 0, m1 = 0;
         DMRG_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         DMRG_HIP(hipEventElapsedTime(&mg, ctx->ev0, ctx->ev2));
+        DMRG_HIP(hipEventElapsedTime(&m1, ctx->ev0, ctx->ev3));
+        st->pass1_seconds += m1 * 1e-3;
         st->sigma_flops += pass1.model_flops + pass2.model_flops;
         st->sigma_seconds += ms * 1e-3;
         st->gemm_seconds += mg * 1e-3;
@@ -1784,11 +1814,12 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
         const auto t5 = clk::now();
         fprintf(stderr,
                 "[dmrg] pair %d %s n=%lld sectors=%zu iters=%d theta=%.12f |r|=%.2e kept=%d disc=%.2e "
-                "block+lists %.3fs diag %.3fs davidson %.3fs (sigma %.3fs) svd %.3fs "
+                "block+lists %.3fs diag %.3fs davidson %.3fs (sigma %.3fs, pass 1 %.3fs) svd %.3fs "
                 "update+next %.3fs total %.3fs\n",
                 j, forward ? "fwd" : "bwd", (long long)ts_n_at_solve, ts_nq_at_solve, dv.iters,
                 dv.theta, dv.rnorm, bonds[j + 1].total, stt.discarded, tb, td, tv,
-                stt.sigma_seconds - sig0, sec(t3, t4), sec(t4, t5), tb + td + tv + sec(t3, t5));
+                stt.sigma_seconds - sig0, stt.pass1_seconds, sec(t3, t4), sec(t4, t5),
+                tb + td + tv + sec(t3, t5));
     }
     return dv.theta;
 }

@@ -5,6 +5,8 @@
 #include <rocblas/rocblas.h>
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <string>
@@ -139,6 +141,7 @@ struct GemmList {
         flops = model_flops = 0;
     }
     bool sigma_role = false;  // launch under the sigma-vector kernel symbol
+    int tile = kTile;         // output tile edge of the tasks (64 or 32)
     DevBuf dbases;            // device copy of the buffer table
     Bases hbases{};           // host copy (kept alive for the async upload)
     void upload(hipStream_t s);
@@ -193,6 +196,7 @@ struct SweepOpts {
 struct StepStats {
     double theta = 0, discarded = 0, sigma_flops = 0, sigma_seconds = 0;
     double gemm_seconds = 0;  // the two grouped-GEMM launches of each sigma
+    double pass1_seconds = 0; // the first of them
     int64_t sigma_calls = 0, dav_iters = 0, gemm_launches = 0;
     int max_bond = 0;
 };
@@ -243,7 +247,20 @@ class DavSolver {
 // The MPS with its environments and the current two-site center.
 class State {
   public:
-    State(Ctx* c, const MPO* m) : ctx(c), mpo(m) {}
+    State(Ctx* c, const MPO* m) : ctx(c), mpo(m) {
+        // optional override of the sigma tile edges, "t1,t2" with t in {32, 64}
+        if (const char* e = std::getenv("DMRG_SIGMA_TILES")) {
+            int a = 0, b = 0;
+            if (std::sscanf(e, "%d,%d", &a, &b) == 2 && (a == 32 || a == 64) && (b == 32 || b == 64)) {
+                tile_pass[0] = a;
+                tile_pass[1] = b;
+            }
+        }
+        if (const char* e = std::getenv("DMRG_SIGMA_PIECES")) {
+            const double v = std::atof(e);
+            if (v >= 256 && v <= 1e7) sigma_pieces = v;
+        }
+    }
     Ctx* ctx;
     const MPO* mpo;
     std::vector<BondL> bonds;  // 0..K
@@ -260,6 +277,8 @@ class State {
     std::vector<int64_t> t_off;  // T_y(q) offsets, [y * nq + iq], -1 if absent
     int64_t t_total = 0;
     int splits = 1;
+    int tile_pass[2] = {kTile, kTile};  // output tile edge of the two sigma passes
+    double sigma_pieces = 16384;        // target workgroups (split-K pieces) of pass 2
     DevBuf tbuf, part, psi32, sig32, tbuf32, part32;
     DevBuf diag;
     bool diag_ok = false;

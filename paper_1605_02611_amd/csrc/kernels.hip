@@ -60,23 +60,25 @@ struct Cfg<2> {
 
 // ROLE only separates the symbol of the sigma-vector launches (1) from every
 // other use (0) so that profiles report them apart; the code is identical.
-template <int MODE, int ROLE>
-__global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__ tasks,
-                                                    const GemmTerm* __restrict__ terms,
-                                                    void* const* __restrict__ bases,
-                                                    const int* __restrict__ active) {
+// TS: output tile edge (64: four waves of 32x32, 32: one wave).
+template <int MODE, int ROLE, int TS>
+__global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const GemmTask* __restrict__ tasks,
+                                                                           const GemmTerm* __restrict__ terms,
+                                                                           void* const* __restrict__ bases,
+                                                                           const int* __restrict__ active) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
-    __shared__ T As[KS][kTile + 4];
-    __shared__ T Bs[KS][kTile + 4];
+    constexpr int NT = (TS / 32) * (TS / 32) * 64;
+    __shared__ T As[KS][TS + 4];
+    __shared__ T Bs[KS][TS + 4];
 
     const GemmTask task = tasks[blockIdx.x];
     if (active && !active[task.inst]) return;  // uniform per workgroup
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int wm = (wave >> 1) * 32;
-    const int wn = (wave & 1) * 32;
+    const int wm = (wave / (TS / 32)) * 32;
+    const int wn = (wave % (TS / 32)) * 32;
     const int lr = lane & 15;   // row / column inside a 16x16 MFMA tile
     const int lk = lane >> 4;   // k-group of the lane
 
@@ -97,14 +99,14 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
         const bool tb = g.flags & GT_TB;
         for (int k0 = 0; k0 < g.k; k0 += KS) {
             // stage A (m x KS) as As[kk][r] and B (KS x n) as Bs[kk][c]
-            for (int idx = tid; idx < kTile * KS; idx += 256) {
+            for (int idx = tid; idx < TS * KS; idx += NT) {
                 int r, kk;
                 if (!ta) {
                     r = idx / KS;
                     kk = idx % KS;
                 } else {
-                    kk = idx / kTile;
-                    r = idx % kTile;
+                    kk = idx / TS;
+                    r = idx % TS;
                 }
                 T v = T(0);
                 if (r < task.m && k0 + kk < g.k)
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
                 As[kk][r] = v * alpha;
                 int c, kb;
                 if (!tb) {
-                    kb = idx / kTile;
-                    c = idx % kTile;
+                    kb = idx / TS;
+                    c = idx % TS;
                 } else {
                     c = idx / KS;
                     kb = idx % KS;
@@ -176,6 +178,105 @@ __global__ __launch_bounds__(256) void grouped_gemm(const GemmTask* __restrict__
                 if (r < task.m && c < task.n) {
                     T* p = C + int64_t(r) * task.ldc + c;
                     T v = T(acc[i][j][e]);
+                    *p = task.accumulate ? *p + v : v;
+                }
+            }
+}
+
+// Wave-level variant for lists of small blocks: every wave owns one task
+// (output tile <= 32 x 32) and feeds the MFMAs straight from global memory
+// (L2) into registers, without LDS or barriers; the loads of up to 16 K
+// values of a term are issued together so that one memory round trip covers
+// them.  Same operand conventions and output as grouped_gemm.
+template <int MODE, int ROLE>
+__global__ __launch_bounds__(256) void wave_gemm(const GemmTask* __restrict__ tasks, int64_t n_tasks,
+                                                 const GemmTerm* __restrict__ terms,
+                                                 void* const* __restrict__ bases,
+                                                 const int* __restrict__ active) {
+    using T = typename Cfg<MODE>::T;
+    using Acc = typename Cfg<MODE>::Acc;
+    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (w >= n_tasks) return;
+    const GemmTask task = tasks[w];
+    if (active && !active[task.inst]) return;
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const bool r1 = task.m > 16, c1 = task.n > 16;  // second row / column sub-tile in use
+    Acc acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    const int ra = lr, rb = 16 + lr;  // rows (A) and columns (B) of this lane
+    for (int l = task.l_begin; l < task.l_end; ++l) {
+        const GemmTerm g = terms[l];
+        const T* A = static_cast<const T*>(bases[g.a_buf]) + g.a_off;
+        const T* B = static_cast<const T*>(bases[g.b_buf]) + g.b_off;
+        const bool ta = g.flags & GT_TA, tb = g.flags & GT_TB;
+        const int64_t sar = ta ? 1 : g.lda, sak = ta ? g.lda : 1;  // A[r][k] = A[r*sar + k*sak]
+        const int64_t sbc = tb ? g.ldb : 1, sbk = tb ? 1 : g.ldb;  // B[k][c] = B[c*sbc + k*sbk]
+        const T alpha = T(g.alpha);
+        if constexpr (MODE == 2) {
+            // BF16: each lane holds 4 consecutive K values of a 16-wide step
+            for (int k0 = 0; k0 < g.k; k0 += 16) {
+                shrt4 a[2], b[2];
+                for (int e = 0; e < 4; ++e) {
+                    const int kk = k0 + 4 * lk + e;
+                    const bool kin = kk < g.k;
+                    const T a0 = (kin && ra < task.m) ? A[ra * sar + kk * sak] * alpha : T(0);
+                    const T a1 = (kin && r1 && rb < task.m) ? A[rb * sar + kk * sak] * alpha : T(0);
+                    const T b0 = (kin && ra < task.n) ? B[ra * sbc + kk * sbk] : T(0);
+                    const T b1 = (kin && c1 && rb < task.n) ? B[rb * sbc + kk * sbk] : T(0);
+                    a[0][e] = short(f32_to_bf16_rne(a0));
+                    a[1][e] = short(f32_to_bf16_rne(a1));
+                    b[0][e] = short(f32_to_bf16_rne(b0));
+                    b[1][e] = short(f32_to_bf16_rne(b1));
+                }
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], acc[0][0], 0, 0, 0);
+                if (c1) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], acc[0][1], 0, 0, 0);
+                if (r1) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], acc[1][0], 0, 0, 0);
+                if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[1], acc[1][1], 0, 0, 0);
+            }
+        } else {
+            constexpr int U = 4;  // 4-wide K steps per batch of loads
+            for (int k0 = 0; k0 < g.k; k0 += 4 * U) {
+                T a0[U], a1[U], b0[U], b1[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int kk = k0 + 4 * u + lk;
+                    const bool kin = kk < g.k;
+                    a0[u] = (kin && ra < task.m) ? A[ra * sar + kk * sak] : T(0);
+                    a1[u] = (kin && r1 && rb < task.m) ? A[rb * sar + kk * sak] : T(0);
+                    b0[u] = (kin && ra < task.n) ? B[ra * sbc + kk * sbk] : T(0);
+                    b1[u] = (kin && c1 && rb < task.n) ? B[rb * sbc + kk * sbk] : T(0);
+                }
+                const int steps = min(U, (g.k - k0 + 3) / 4);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (u >= steps) break;
+                    const T x0 = a0[u] * alpha, x1 = a1[u] * alpha;
+                    if constexpr (MODE == 0) {
+                        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b0[u], acc[0][0], 0, 0, 0);
+                        if (c1) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, b1[u], acc[0][1], 0, 0, 0);
+                        if (r1) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b0[u], acc[1][0], 0, 0, 0);
+                        if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, b1[u], acc[1][1], 0, 0, 0);
+                    } else {
+                        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, b0[u], acc[0][0], 0, 0, 0);
+                        if (c1) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, b1[u], acc[0][1], 0, 0, 0);
+                        if (r1) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, b0[u], acc[1][0], 0, 0, 0);
+                        if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, b1[u], acc[1][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    T* C = static_cast<T*>(bases[task.c_buf]) + task.c_off;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
+                const int c = 16 * j + lr;
+                if (r < task.m && c < task.n) {
+                    T* p = C + int64_t(r) * task.ldc + c;
+                    const T v = T(acc[i][j][e]);
                     *p = task.accumulate ? *p + v : v;
                 }
             }
@@ -477,22 +578,47 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 }  // namespace
 
-template <int ROLE>
-static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+template <int ROLE, int TS>
+static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                              void* const* b, const int* act, hipStream_t s) {
-    if (n_tasks <= 0) return;
+    constexpr int NT = (TS / 32) * (TS / 32) * 64;
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
         const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((grouped_gemm<0, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((grouped_gemm<1, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((grouped_gemm<2, ROLE>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
+                break;
+        }
+    }
+}
+
+template <int ROLE>
+static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
+                             void* const* b, const int* act, int tile, hipStream_t s) {
+    if (n_tasks <= 0) return;
+    require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
+    if (tile == 64) {
+        launch_gemm_tile<ROLE, 64>(p, tasks, n_tasks, terms, b, act, s);
+    } else {
+        // four tasks per workgroup, one per wave
+        const int64_t g = (n_tasks + 3) / 4;
+        require(g < (int64_t(1) << 31), "grouped GEMM: too many tasks");
+        switch (p) {
+            case Prec::F64:
+                hipLaunchKernelGGL((wave_gemm<0, ROLE>), dim3(unsigned(g)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                break;
+            case Prec::F32:
+                hipLaunchKernelGGL((wave_gemm<1, ROLE>), dim3(unsigned(g)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                break;
+            case Prec::BF16:
+                hipLaunchKernelGGL((wave_gemm<2, ROLE>), dim3(unsigned(g)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
                 break;
         }
     }
@@ -500,12 +626,12 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 }
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* b, const int* act, hipStream_t s) {
-    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, s);
+                 void* const* b, const int* act, hipStream_t s, int tile) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s);
 }
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* b, const int* act, hipStream_t s) {
-    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, s);
+                       void* const* b, const int* act, hipStream_t s, int tile) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {

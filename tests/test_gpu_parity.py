@@ -45,10 +45,11 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (16, 16, 4), (17, 33, 19), (64, 64, 16), (65, 63
           (70, 130, 50), (130, 65, 200), (3, 300, 2)]
 
 
+@pytest.mark.parametrize("tile", [64, 32])
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_gemm_kernel(ctx, m, n, k, ta, tb):
-    _log("gemm", m, n, k, ta, tb)
+def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
+    _log("gemm", m, n, k, ta, tb, tile)
     rng = np.random.default_rng(m * 1000 + n * 10 + k + 7 * ta + 3 * tb)
     Ah = rng.standard_normal((k, m + 3) if ta else (m, k + 3))
     Bh = rng.standard_normal((n, k + 2) if tb else (k, n + 2))
@@ -60,7 +61,7 @@ def test_gemm_kernel(ctx, m, n, k, ta, tb):
             ref = 0.7 * opA @ opB + (Ch[:, :n] if acc else 0)
             Cd = _dev(Ch)
             ctx.gemm(_dev(Ah), _dev(Bh), Cd, m, n, k, ta=bool(ta), tb=bool(tb), alpha=0.7,
-                     accumulate=acc, prec=prec)
+                     accumulate=acc, prec=prec, tile=tile)
             out = Cd.cpu().numpy()
             err = np.abs(out[:, :n] - ref).max() / max(1.0, np.abs(ref).max())
             assert err <= tol, (prec, acc, err)
