@@ -93,6 +93,34 @@ def cpu_baseline(P, ctx, m_sample, seed):
     }
 
 
+def full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t_setup):
+    """Full sweeps (forward and back over all pairs) from the random initial
+    state; one JSON line with the energy and time of every sweep."""
+    opts = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
+                          refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    rows = []
+    for sw in range(args.sweeps):
+        t1 = time.time()
+        stats, _ = mps.sweep(M, 1, opts)
+        st = stats[0]
+        st["wall"] = time.time() - t1
+        rows.append(st)
+        log("sweep %d E %.10f %.1fs sigma %.1fs (%d calls, %.2f TFLOP/s) dav_iters %d disc %.2e" % (
+            sw, st["energy"], st["wall"], st["sigma_seconds"], st["sigma_calls"],
+            st["sigma_flops"] / max(st["sigma_seconds"], 1e-30) / 1e12, st["dav_iters"], st["discarded"]))
+    e = mps.energy()
+    fl = sum(r["sigma_flops"] for r in rows)
+    ss = sum(r["sigma_seconds"] for r in rows)
+    out = {"mode": "sweeps", "precision": args.prec, "K": K, "M": M, "n_sweeps": args.sweeps,
+           "energy": e, "sweep_energies": [r["energy"] for r in rows],
+           "sweep_seconds": [r["wall"] for r in rows], "sigma_tflops": fl / ss / 1e12,
+           "sigma_seconds": ss, "sigma_calls": sum(r["sigma_calls"] for r in rows),
+           "dav_iters": [r["dav_iters"] for r in rows], "discarded": [r["discarded"] for r in rows],
+           "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
+           "setup_seconds": time.time() - t_setup - sum(r["wall"] for r in rows)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +130,9 @@ def main():
     ap.add_argument("--dav-tol", type=float, default=1e-7)
     ap.add_argument("--dav-iter", type=int, default=24)
     ap.add_argument("--sweep", action="store_true", help="also time one full sweep")
+    ap.add_argument("--sweeps", type=int, default=0,
+                    help="instead of middle steps: run this many full sweeps from the random "
+                         "initial state and report energies and sweep seconds")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
     ap.add_argument("--calib", action="store_true",
@@ -134,12 +165,14 @@ def main():
     n = mpo.n_values(M)
     mps = P.Mps.random(ctx, mpo, M, mps_values(c["seed"], n))
     j = K // 2 - 1
-    for _ in range(j):
+    for _ in range(0 if args.sweeps else j):
         mps.move(True)
     log("setup %.1fs: center %d, psi %d, D_mid %d" % (time.time() - t0, mps.center(), mps.psi_size(),
                                                       mpo.bond_dims()[j + 1]))
     opts = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
                           refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    if args.sweeps:
+        return full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t0)
     fwd = True
     for w in range(args.warmup):
         th, st = mps.step(M, fwd, opts)
