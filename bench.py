@@ -20,10 +20,32 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA, TFLOP/s
+
+
+def recorded_traffic(prec, steps, warmup):
+    """HBM bytes per sigma launch from the committed rocprofv3 counter summary,
+    only while the kernel source is the one the counters were taken on and the
+    run is the recorded one; otherwise None."""
+    import hashlib
+    try:
+        src = open(os.path.join(ROOT, "paper_1605_02611_amd", "csrc", "kernels.hip"), "rb").read()
+        txt = open(os.path.join(ROOT, "profiles", "hbm_traffic_sigma_k36_m1024_fp64.txt")).read()
+    except OSError:
+        return None
+    rec = None
+    for line in txt.splitlines():
+        if line.startswith("machine-readable:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if (rec is None or rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest()
+            or prec != "fp64" or rec.get("steps") != steps or rec.get("warmup") != warmup):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def log(*a):
@@ -121,6 +143,56 @@ def full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t_setup):
     print(json.dumps(out), flush=True)
 
 
+def batched(args, P, torch):
+    """The molecule batch: each instance swept alone in FP64 and in FP32, then
+    all of them in lockstep with merged sigma launches (FP32)."""
+    from workloads import batched_instances, chain_integrals, mps_values
+    ctx = P.Context(0)
+    n_sw = args.sweeps or 1
+    inst = batched_instances(64)[:args.batched]
+    mpos = []
+    for K, M, seed in inst:
+        I = chain_integrals(K, n_elec=K, seed=seed, rank=K)
+        mpos.append(P.Mpo(ctx, I.h, I.v, K, K % 2))
+    def fresh(b):
+        K, M, seed = inst[b]
+        return P.Mps.random(ctx, mpos[b], M, mps_values(seed, mpos[b].n_values(M)))
+    res = {}
+    for name, prec in (("seq_fp64", P.DMRG_FP64), ("seq_fp32", P.DMRG_FP32)):
+        o = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
+                           refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+        t0 = time.time()
+        en = []
+        for b in range(len(inst)):
+            m = fresh(b)
+            torch.cuda.synchronize()
+            m.sweep(inst[b][1], n_sw, o)
+            en.append(m.energy())
+            del m
+        res[name] = (time.time() - t0, en)
+        log("%s %.1fs" % (name, res[name][0]))
+    o = P.default_opts(prec=P.DMRG_FP32, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter, refine_tol=1e-4)
+    states = [fresh(b) for b in range(len(inst))]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    stats, bsig = P.sweep_batched(ctx, states, [x[1] for x in inst], n_sw, o)
+    tb = time.time() - t0
+    eb = [m.energy() for m in states]
+    log("batched_fp32 %.1fs (batched sigma %.1fs)" % (tb, bsig))
+    e64, e32 = np.array(res["seq_fp64"][1]), np.array(res["seq_fp32"][1])
+    out = {"mode": "batched", "instances": len(inst), "sweeps": n_sw,
+           "sizes": [[K, M] for K, M, _ in inst],
+           "seconds": {"sequential_fp64": res["seq_fp64"][0], "sequential_fp32": res["seq_fp32"][0],
+                       "batched_fp32": tb, "batched_sigma_wall": bsig},
+           "speedup_vs_sequential_fp64": res["seq_fp64"][0] / tb,
+           "speedup_vs_sequential_fp32": res["seq_fp32"][0] / tb,
+           "max_abs_dE_batched_vs_sequential_fp32": float(np.abs(np.array(eb) - e32).max()),
+           "max_abs_dE_batched_vs_sequential_fp64": float(np.abs(np.array(eb) - e64).max()),
+           "energies_fp64": e64.tolist(), "energies_batched_fp32": eb,
+           "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +205,10 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0,
                     help="instead of middle steps: run this many full sweeps from the random "
                          "initial state and report energies and sweep seconds")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="instead of middle steps: the first N instances of the 64-molecule batch "
+                         "(K 12-24, M 128-512), --sweeps sweeps (default 1) sequential FP64, sequential "
+                         "FP32 and batched FP32; energies and speedups")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
     ap.add_argument("--calib", action="store_true",
@@ -156,6 +232,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batched:
+        return batched(args, P, torch)
     c = CONFIGS[3]
     K, M = c["K"], c["M"]
     ctx = P.Context(0)
@@ -222,7 +300,8 @@ def main():
         "step_tflops_wall": tot["flops"] / wall / 1e12,
         "thetas": thetas,
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK[args.prec],
-                     "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec], "traffic": None,
+                     "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec],
+                     "traffic": recorded_traffic(args.prec, args.steps, args.warmup),
                      "kernel": "grouped_gemm<%d,1>" % prec,
                      "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
                      "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},

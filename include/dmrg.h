@@ -72,6 +72,7 @@ typedef enum {
 typedef struct dmrg_ctx dmrg_ctx;
 typedef struct dmrg_mpo dmrg_mpo;
 typedef struct dmrg_mps dmrg_mps;
+typedef struct dmrg_mlp dmrg_mlp;
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -187,6 +188,10 @@ typedef struct {
     double svd_cutoff;  /* drop singular values <= cutoff * sigma_max */
     double refine_tol;  /* low-precision runs: switch to FP64 sigma once
                            ||r|| <= refine_tol (0 = never) */
+    int precond;        /* 0: diagonal t = r / (theta - H_ii); 1: learned
+                           correction of the network `mlp` (dmrg_mlp_*) */
+    int collect;        /* != 0: append training samples of every step to `mlp` */
+    dmrg_mlp* mlp;      /* borrowed; required when precond == 1 or collect != 0 */
 } dmrg_sweep_opts;
 
 typedef struct {
@@ -201,6 +206,8 @@ typedef struct {
     int64_t dav_iters;      /* Davidson iterations summed over steps */
     int32_t max_bond;       /* largest bond dimension after the sweep */
     int32_t n_steps;
+    int64_t precond_fallbacks; /* steps whose learned correction fell back to the diagonal one */
+    int64_t samples;        /* training samples appended to the network */
 } dmrg_sweep_stat;
 
 /* Default options (FP64, tol 1e-9, 200 iterations, subspace 24, keep 4). */
@@ -231,6 +238,64 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps,
  * two-site vector is split exactly by SVD (singular values <= 1e-14 sigma_max
  * dropped) and the environment on the side left behind is updated. */
 dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward);
+/* ---- learned Davidson preconditioner --------------------------------------
+ *
+ * Not part of the paper, whose solver is left open (Sec. 2.1, "solving"): an
+ * optional correction of the diagonal preconditioner.  A network of 12
+ * inputs -> 64 tanh -> 64 tanh -> 1 maps features of element i of the two-
+ * site vector to g_i and the correction is t_i = r_i / (theta - H_ii) *
+ * exp(clamp(g_i, -3, 3)).  Parameters: DMRG_MLP_PARAMS FP32 values ordered
+ * W1 (64 x 12, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3.
+ * Features of element i (sector (Q_l, s, t, Q_r), u the Ritz vector, r the
+ * residual, n the vector length):
+ *   (theta - H_ii) / max(1, |theta|), log(max(|theta - H_ii|, 1e-12)) / 10,
+ *   r_i sqrt(n) / ||r||, u_i sqrt(n), N(Q_l) / max(1, N), 2S_z(Q_l) / max(1, N),
+ *   n(s) / 2, n(t) / 2, 2s_z(s), 2s_z(t), log(1 + m(Q_l)) / 8, (j + 0.5) / K.
+ * Training samples (collect != 0): at each Davidson iteration k of a step
+ * 4096 sampled elements; once the step's vector psi is known the target is
+ * clamp(log rho_i, -3, 3) with rho = alpha t* / (d r), t* = psi - (psi.u_k) u_k,
+ * alpha the least-squares scale of t* onto d r (-3 where rho <= 0, 0 where
+ * d r = 0).  Loss: mean squared error; training: Adam (0.9, 0.999, 1e-8).
+ * In Davidson, a learned correction after which the residual grew twice in
+ * a row is replaced by the diagonal one for the rest of the step.
+ * All pointers marked "device" are device memory of the context's GPU. */
+#define DMRG_MLP_FEATURES 12
+#define DMRG_MLP_PARAMS 5057
+/* params: host array of DMRG_MLP_PARAMS values, or NULL for a seeded
+ * initialisation; capacity: training samples the network can hold. */
+dmrg_status dmrg_mlp_create(dmrg_ctx* ctx, const float* params, uint64_t seed, int64_t capacity,
+                            dmrg_mlp** out);
+void dmrg_mlp_free(dmrg_mlp* mlp);
+/* Current parameters into a host array of DMRG_MLP_PARAMS values. */
+dmrg_status dmrg_mlp_params(dmrg_ctx* ctx, const dmrg_mlp* mlp, float* out);
+/* out[i] = g(feat[i]) for n rows of 12 features (device, FP32). */
+dmrg_status dmrg_mlp_forward(dmrg_ctx* ctx, const dmrg_mlp* mlp, const float* feat, int64_t n, float* out);
+/* Mean squared error of g(feat) against target (n rows, device) and its
+ * gradient into grad (device, DMRG_MLP_PARAMS; may be NULL). */
+dmrg_status dmrg_mlp_loss_grad(dmrg_ctx* ctx, dmrg_mlp* mlp, const float* feat, const float* target,
+                               int64_t n, float* grad, double* loss);
+/* One Adam step with the given gradient (device). */
+dmrg_status dmrg_mlp_adam_step(dmrg_ctx* ctx, dmrg_mlp* mlp, const float* grad, double lr);
+/* Static features (8 per element, columns 4..11) at the current center,
+ * into a host array of psi_size * 8 values. */
+dmrg_status dmrg_mlp_static(dmrg_ctx* ctx, dmrg_mps* mps, float* out);
+/* All 12 features at the current center for given theta, residual r and
+ * Ritz vector u (device, psi_size each) into feat (device, psi_size x 12). */
+dmrg_status dmrg_mlp_features(dmrg_ctx* ctx, dmrg_mps* mps, double theta, const double* r, const double* u,
+                              float* feat);
+/* Training targets of one iteration at sampled elements idx (device): psi
+ * and u full vectors, c = psi . u, dr the sampled d r values (device). */
+dmrg_status dmrg_mlp_targets(dmrg_ctx* ctx, const double* psi, const double* u, double c, const double* dr,
+                             const int32_t* idx, int64_t n_sample, float* out);
+/* Number of collected samples; with non-NULL host arrays also the samples
+ * (features n x 12, targets n). */
+dmrg_status dmrg_mlp_dataset(dmrg_ctx* ctx, const dmrg_mlp* mlp, int64_t* n, float* feat, float* target);
+/* Adam over the collected samples for `epochs` passes in seeded random
+ * order, mini-batches of `batch`; loss: mean batch loss of the last epoch.
+ * DMRG_E_STATE when no samples were collected. */
+dmrg_status dmrg_mlp_train(dmrg_ctx* ctx, dmrg_mlp* mlp, int epochs, int batch, double lr, uint64_t seed,
+                           double* loss);
+
 /* <Psi|H|Psi>/<Psi|Psi> of the current state, accumulated in FP64
  * (Eqs. transferop, energy_expect, at the center bond). */
 dmrg_status dmrg_energy(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* E);

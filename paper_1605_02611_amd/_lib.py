@@ -29,7 +29,7 @@ class MpoOpts(C.Structure):
 class SweepOpts(C.Structure):
     _fields_ = [("prec", c_int), ("dav_tol", c_double), ("dav_max_iter", c_int),
                 ("dav_max_space", c_int), ("dav_keep", c_int), ("svd_cutoff", c_double),
-                ("refine_tol", c_double)]
+                ("refine_tol", c_double), ("precond", c_int), ("collect", c_int), ("mlp", c_void_p)]
 
 
 class SweepStat(C.Structure):
@@ -37,7 +37,7 @@ class SweepStat(C.Structure):
                 ("sigma_flops", c_double), ("sigma_seconds", c_double),
                 ("sigma_calls", c_int64), ("gemm_seconds", c_double), ("gemm_launches", c_int64),
                 ("dav_iters", c_int64), ("max_bond", c_int32),
-                ("n_steps", c_int32)]
+                ("n_steps", c_int32), ("precond_fallbacks", c_int64), ("samples", c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -74,7 +74,21 @@ SIGNATURES = {
     "dmrg_mps_move": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "dmrg_sweep_batched": (c_int, [c_void_p, c_int, P(c_void_p), P(c_void_p), P(c_int), c_int,
                                    P(SweepOpts), P(SweepStat), P(c_double)]),
+    "dmrg_mlp_create": (c_int, [c_void_p, P(C.c_float), C.c_uint64, c_int64, P(c_void_p)]),
+    "dmrg_mlp_free": (None, [c_void_p]),
+    "dmrg_mlp_params": (c_int, [c_void_p, c_void_p, P(C.c_float)]),
+    "dmrg_mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+    "dmrg_mlp_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                                   P(c_double)]),
+    "dmrg_mlp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double]),
+    "dmrg_mlp_static": (c_int, [c_void_p, c_void_p, P(C.c_float)]),
+    "dmrg_mlp_features": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
+    "dmrg_mlp_targets": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_int64,
+                                 c_void_p]),
+    "dmrg_mlp_dataset": (c_int, [c_void_p, c_void_p, P(c_int64), P(C.c_float), P(C.c_float)]),
+    "dmrg_mlp_train": (c_int, [c_void_p, c_void_p, c_int, c_int, c_double, C.c_uint64, P(c_double)]),
 }
+MLP_FEATURES, MLP_PARAMS = 12, 5057
 
 _lib = None
 

@@ -138,6 +138,8 @@ def default_opts(**kw):
     o = L.SweepOpts()
     L.load().dmrg_sweep_opts_default(C.byref(o))
     for k, v in kw.items():
+        if k == "mlp" and v is not None and not isinstance(v, int):
+            v = v.h.value  # an Mlp object
         setattr(o, k, v)
     return o
 
@@ -245,6 +247,84 @@ class Mps:
         if getattr(self, "h", None):
             self.lib.dmrg_mps_free(self.h)
             self.h = None
+
+
+class Mlp:
+    """Network of the learned Davidson preconditioner (dmrg_mlp_*)."""
+
+    def __init__(self, ctx, params=None, seed=0, capacity=1 << 21):
+        self.ctx, self.lib = ctx, ctx.lib
+        out = C.c_void_p()
+        pp = None
+        if params is not None:
+            self._p = np.ascontiguousarray(params, dtype=np.float32)
+            assert self._p.size == L.MLP_PARAMS
+            pp = self._p.ctypes.data_as(C.POINTER(C.c_float))
+        ctx.check(self.lib.dmrg_mlp_create(ctx.h, pp, seed, capacity, C.byref(out)))
+        self.h = out
+
+    def params(self):
+        out = np.zeros(L.MLP_PARAMS, dtype=np.float32)
+        self.ctx.check(self.lib.dmrg_mlp_params(self.ctx.h, self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def forward(self, feat_dev, out_dev):
+        _torch_sync()
+        self.ctx.check(self.lib.dmrg_mlp_forward(self.ctx.h, self.h, C_void(feat_dev), feat_dev.shape[0],
+                                                 C_void(out_dev)))
+
+    def loss_grad(self, feat_dev, target_dev, grad_dev=None):
+        _torch_sync()
+        loss = C.c_double()
+        self.ctx.check(self.lib.dmrg_mlp_loss_grad(
+            self.ctx.h, self.h, C_void(feat_dev), C_void(target_dev), feat_dev.shape[0],
+            C_void(grad_dev) if grad_dev is not None else None, C.byref(loss)))
+        return loss.value
+
+    def adam_step(self, grad_dev, lr):
+        _torch_sync()
+        self.ctx.check(self.lib.dmrg_mlp_adam_step(self.ctx.h, self.h, C_void(grad_dev), lr))
+
+    def dataset(self, fetch=True):
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_mlp_dataset(self.ctx.h, self.h, C.byref(n), None, None))
+        if not fetch:
+            return n.value
+        X = np.zeros((n.value, L.MLP_FEATURES), dtype=np.float32)
+        y = np.zeros(n.value, dtype=np.float32)
+        if n.value:
+            self.ctx.check(self.lib.dmrg_mlp_dataset(
+                self.ctx.h, self.h, C.byref(n), X.ctypes.data_as(C.POINTER(C.c_float)),
+                y.ctypes.data_as(C.POINTER(C.c_float))))
+        return X, y
+
+    def train(self, epochs, batch=4096, lr=1e-3, seed=0):
+        loss = C.c_double()
+        self.ctx.check(self.lib.dmrg_mlp_train(self.ctx.h, self.h, epochs, batch, lr, seed, C.byref(loss)))
+        return loss.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.dmrg_mlp_free(self.h)
+            self.h = None
+
+
+def mlp_static(ctx, mps):
+    n = mps.psi_size()
+    out = np.zeros((n, 8), dtype=np.float32)
+    ctx.check(ctx.lib.dmrg_mlp_static(ctx.h, mps.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+    return out
+
+
+def mlp_features(ctx, mps, theta, r_dev, u_dev, feat_dev):
+    _torch_sync()
+    ctx.check(ctx.lib.dmrg_mlp_features(ctx.h, mps.h, theta, C_void(r_dev), C_void(u_dev), C_void(feat_dev)))
+
+
+def mlp_targets(ctx, psi_dev, u_dev, c, dr_dev, idx_dev, out_dev):
+    _torch_sync()
+    ctx.check(ctx.lib.dmrg_mlp_targets(ctx.h, C_void(psi_dev), C_void(u_dev), c, C_void(dr_dev),
+                                       C_void(idx_dev), idx_dev.shape[0], C_void(out_dev)))
 
 
 def sweep_batched(ctx, states, Ms, n_sweeps, opts=None):

@@ -18,6 +18,9 @@ struct dmrg_mpo {
 struct dmrg_mps {
     std::unique_ptr<State> st;
 };
+struct dmrg_mlp {
+    std::unique_ptr<Mlp> m;
+};
 
 namespace dmrg {
 int64_t initial_value_count(const MPO& m, int M);
@@ -58,7 +61,28 @@ SweepOpts to_opts(const dmrg_sweep_opts* o) {
     r.dav_keep = o->dav_keep;
     r.svd_cutoff = o->svd_cutoff;
     r.refine_tol = o->refine_tol;
+    require(o->precond == 0 || o->precond == 1, "precond must be 0 (diagonal) or 1 (learned)");
+    require((o->precond == 0 && !o->collect) || o->mlp, "learned preconditioner or collection needs a network");
+    r.precond = o->precond;
+    r.collect = o->collect != 0;
+    r.mlp = o->mlp ? o->mlp->m.get() : nullptr;
     return r;
+}
+
+void fill_stat(dmrg_sweep_stat& d, const StepStats& x, double energy, double seconds, int n_steps) {
+    d.energy = energy;
+    d.discarded = x.discarded;
+    d.seconds = seconds;
+    d.sigma_flops = x.sigma_flops;
+    d.sigma_seconds = x.sigma_seconds;
+    d.sigma_calls = x.sigma_calls;
+    d.gemm_seconds = x.gemm_seconds;
+    d.gemm_launches = x.gemm_launches;
+    d.dav_iters = x.dav_iters;
+    d.max_bond = x.max_bond;
+    d.n_steps = n_steps;
+    d.precond_fallbacks = x.precond_fallbacks;
+    d.samples = x.samples;
 }
 
 void use_device(const Ctx& c) {
@@ -389,6 +413,9 @@ void dmrg_sweep_opts_default(dmrg_sweep_opts* o) {
     o->dav_keep = 4;
     o->svd_cutoff = 1e-12;
     o->refine_tol = 0.0;
+    o->precond = 0;
+    o->collect = 0;
+    o->mlp = nullptr;
 }
 
 dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
@@ -405,19 +432,7 @@ dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, 
         double th = mps->st->step(M, forward != 0, o, s);
         auto t1 = std::chrono::steady_clock::now();
         if (theta) *theta = th;
-        if (stat) {
-            stat->energy = th;
-            stat->discarded = s.discarded;
-            stat->seconds = std::chrono::duration<double>(t1 - t0).count();
-            stat->sigma_flops = s.sigma_flops;
-            stat->sigma_seconds = s.sigma_seconds;
-            stat->sigma_calls = s.sigma_calls;
-            stat->gemm_seconds = s.gemm_seconds;
-            stat->gemm_launches = s.gemm_launches;
-            stat->dav_iters = s.dav_iters;
-            stat->max_bond = s.max_bond;
-            stat->n_steps = 1;
-        }
+        if (stat) fill_stat(*stat, s, th, std::chrono::duration<double>(t1 - t0).count(), 1);
     });
 }
 
@@ -447,19 +462,7 @@ dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
                 if (thetas && sw == n_sweeps - 1) thetas[step] = th;
             }
             auto t1 = std::chrono::steady_clock::now();
-            if (stats) {
-                stats[sw].energy = th;
-                stats[sw].discarded = s.discarded;
-                stats[sw].seconds = std::chrono::duration<double>(t1 - t0).count();
-                stats[sw].sigma_flops = s.sigma_flops;
-                stats[sw].sigma_seconds = s.sigma_seconds;
-                stats[sw].sigma_calls = s.sigma_calls;
-                stats[sw].gemm_seconds = s.gemm_seconds;
-                stats[sw].gemm_launches = s.gemm_launches;
-                stats[sw].dav_iters = s.dav_iters;
-                stats[sw].max_bond = s.max_bond;
-                stats[sw].n_steps = step;
-            }
+            if (stats) fill_stat(stats[sw], s, th, std::chrono::duration<double>(t1 - t0).count(), step);
         }
     });
 }
@@ -506,20 +509,148 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps, const
         if (stats)
             for (int b = 0; b < n; ++b)
                 for (int sw = 0; sw < n_sweeps; ++sw) {
-                    dmrg_sweep_stat& d = stats[size_t(b) * n_sweeps + sw];
                     const StepStats& x = S[b][sw];
-                    d.energy = x.theta;
-                    d.discarded = x.discarded;
-                    d.seconds = secs[b][sw];
-                    d.sigma_flops = x.sigma_flops;
-                    d.sigma_seconds = x.sigma_seconds;
-                    d.sigma_calls = x.sigma_calls;
-                    d.gemm_seconds = x.gemm_seconds;
-                    d.gemm_launches = x.gemm_launches;
-                    d.dav_iters = x.dav_iters;
-                    d.max_bond = x.max_bond;
-                    d.n_steps = 2 * (mpo[b]->m->K - 1);
+                    fill_stat(stats[size_t(b) * n_sweeps + sw], x, x.theta, secs[b][sw], 2 * (mpo[b]->m->K - 1));
                 }
+    });
+}
+
+// ---- learned preconditioner ---------------------------------------------------
+
+dmrg_status dmrg_mlp_create(dmrg_ctx* ctx, const float* params, uint64_t seed, int64_t capacity,
+                            dmrg_mlp** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(out != nullptr && capacity >= 0, "bad network arguments");
+        use_device(ctx->c);
+        auto h = std::make_unique<dmrg_mlp>();
+        h->m = std::make_unique<Mlp>();
+        h->m->init(ctx->c.stream, params, seed, capacity);
+        *out = h.release();
+    });
+}
+
+void dmrg_mlp_free(dmrg_mlp* mlp) { delete mlp; }
+
+dmrg_status dmrg_mlp_params(dmrg_ctx* ctx, const dmrg_mlp* mlp, float* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp && out, "null argument");
+        use_device(ctx->c);
+        DMRG_HIP(hipMemcpyAsync(out, mlp->m->params.p, kMlpP * sizeof(float), hipMemcpyDeviceToHost, mlp->m->s));
+        DMRG_HIP(hipStreamSynchronize(mlp->m->s));
+    });
+}
+
+dmrg_status dmrg_mlp_forward(dmrg_ctx* ctx, const dmrg_mlp* mlp, const float* feat, int64_t n, float* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp && feat && out && n >= 0, "bad forward arguments");
+        use_device(ctx->c);
+        launch_mlp_forward(mlp->m->params.as<float>(), feat, n, out, ctx->c.stream);
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_mlp_loss_grad(dmrg_ctx* ctx, dmrg_mlp* mlp, const float* feat, const float* target, int64_t n,
+                               float* grad, double* loss) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp && feat && target && n >= 1, "bad gradient arguments");
+        use_device(ctx->c);
+        const double l = mlp->m->loss_grad(feat, target, nullptr, n);
+        if (grad) {
+            DMRG_HIP(hipMemcpyAsync(grad, mlp->m->grad.p, kMlpP * sizeof(float), hipMemcpyDeviceToDevice,
+                                    mlp->m->s));
+            DMRG_HIP(hipStreamSynchronize(mlp->m->s));
+        }
+        if (loss) *loss = l;
+    });
+}
+
+dmrg_status dmrg_mlp_adam_step(dmrg_ctx* ctx, dmrg_mlp* mlp, const float* grad, double lr) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp && grad && lr > 0, "bad Adam arguments");
+        use_device(ctx->c);
+        DMRG_HIP(hipMemcpyAsync(mlp->m->grad.p, grad, kMlpP * sizeof(float), hipMemcpyDeviceToDevice, mlp->m->s));
+        mlp->m->adam(lr);
+        DMRG_HIP(hipStreamSynchronize(mlp->m->s));
+    });
+}
+
+dmrg_status dmrg_mlp_static(dmrg_ctx* ctx, dmrg_mps* mps, float* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && out, "null argument");
+        use_device(ctx->c);
+        State& st = *mps->st;
+        st.build_mlp_static();
+        DMRG_HIP(hipMemcpyAsync(out, st.mlp_stat.p, size_t(st.ts.n) * kMlpStatic * sizeof(float),
+                                hipMemcpyDeviceToHost, ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_mlp_features(dmrg_ctx* ctx, dmrg_mps* mps, double theta, const double* r, const double* u,
+                              float* feat) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && r && u && feat, "null argument");
+        use_device(ctx->c);
+        State& st = *mps->st;
+        st.build_diag();
+        st.build_mlp_static();
+        const int64_t n = st.ts.n;
+        // ||r|| on the host from a device copy (test hook, small vectors)
+        std::vector<double> hr(n);
+        DMRG_HIP(hipMemcpyAsync(hr.data(), r, n * sizeof(double), hipMemcpyDeviceToHost, ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+        double rn = 0;
+        for (double x : hr) rn += x * x;
+        rn = std::sqrt(rn);
+        launch_mlp_features(st.diag.as<double>(), r, u, st.mlp_stat.as<float>(), theta,
+                            rn > 0 ? std::sqrt(double(n)) / rn : 0.0, std::sqrt(double(n)), nullptr, n, feat,
+                            ctx->c.stream);
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_mlp_targets(dmrg_ctx* ctx, const double* psi, const double* u, double c, const double* dr,
+                             const int32_t* idx, int64_t n_sample, float* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(psi && u && dr && idx && out && n_sample >= 0, "bad target arguments");
+        use_device(ctx->c);
+        launch_mlp_targets(psi, u, c, dr, idx, n_sample, out, ctx->c.stream);
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_mlp_dataset(dmrg_ctx* ctx, const dmrg_mlp* mlp, int64_t* n, float* feat, float* target) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp && n, "null argument");
+        const Mlp& m = *mlp->m;
+        *n = m.ds_n;
+        if (m.ds_n == 0 || (!feat && !target)) return;
+        use_device(ctx->c);
+        if (feat)
+            DMRG_HIP(hipMemcpyAsync(feat, m.ds_x.p, size_t(m.ds_n) * kMlpF * sizeof(float), hipMemcpyDeviceToHost, m.s));
+        if (target)
+            DMRG_HIP(hipMemcpyAsync(target, m.ds_y.p, size_t(m.ds_n) * sizeof(float), hipMemcpyDeviceToHost, m.s));
+        DMRG_HIP(hipStreamSynchronize(m.s));
+    });
+}
+
+dmrg_status dmrg_mlp_train(dmrg_ctx* ctx, dmrg_mlp* mlp, int epochs, int batch, double lr, uint64_t seed,
+                           double* loss) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mlp, "null argument");
+        use_device(ctx->c);
+        const double l = mlp->m->train(epochs, batch, lr, seed);
+        if (loss) *loss = l;
     });
 }
 

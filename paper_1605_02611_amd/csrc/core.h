@@ -255,6 +255,14 @@ inline int64_t svd_work_elems(int rows, int cols) {
 // lds_elems: doubles of dynamic LDS per workgroup (0 = all in global memory)
 void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, int lds_elems, hipStream_t s);
 constexpr int kJacobiLds = 20000;  // 160 000 bytes of the 160 KiB LDS
+// round-parallel variant for large sectors: A, V in the job's work area;
+// slots (job, pair index) list every pair of every job; live / rotated:
+// one int per job (device)
+void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s);
+void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
+                         int* rotated, hipStream_t s);
+void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s);
+constexpr int kJacobiRoundMin = 160;  // sectors with at least this many columns use the round launches
 
 // ---------------------------------------------------------------------------
 // device memory: stream-ordered allocations

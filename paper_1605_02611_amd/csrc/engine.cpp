@@ -893,7 +893,7 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
     info.alloc(std::max<size_t>(1, mats.size()) * sizeof(rocblas_int), s);
     double* w = work.as<double>();
     // small sectors: batched one-sided Jacobi kernel; large ones: rocSOLVER
-    static const int jmax = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 256;
+    static const int jmax = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 768;
     std::vector<char> jac(mats.size(), 0);
     std::vector<SvdJob> jobs;
     int64_t jtot = 0;
@@ -913,16 +913,61 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
                             w + o.s_off, w + o.v_off, info.as<rocblas_int>() + i});
             pos += svd_work_elems(o.rows, o.cols);
         }
+        // small sectors in one kernel (all rounds inside); large ones by
+        // round launches parallel over pairs and sectors
+        std::stable_partition(jobs.begin(), jobs.end(), [](const SvdJob& jb) {
+            return std::min(jb.rows, jb.cols) < kJacobiRoundMin;
+        });
+        const size_t n_small = size_t(std::count_if(jobs.begin(), jobs.end(), [](const SvdJob& jb) {
+            return std::min(jb.rows, jb.cols) < kJacobiRoundMin;
+        }));
         djobs.alloc(jobs.size() * sizeof(SvdJob), s);
         DMRG_HIP(hipMemcpyAsync(djobs.p, jobs.data(), jobs.size() * sizeof(SvdJob), hipMemcpyHostToDevice, s));
-        // the largest working set decides whether the launch asks for LDS
-        int64_t need = 0;
-        for (const SvdJob& jb : jobs) {
-            const int64_t mm = std::max(jb.rows, jb.cols), nn = std::min(jb.rows, jb.cols);
-            need = std::max(need, mm * nn + nn * nn);
+        if (n_small > 0) {
+            // the largest working set decides whether the launch asks for LDS
+            int64_t need = 0;
+            for (size_t i = 0; i < n_small; ++i) {
+                const int64_t mm = std::max(jobs[i].rows, jobs[i].cols), nn = std::min(jobs[i].rows, jobs[i].cols);
+                need = std::max(need, mm * nn + nn * nn);
+            }
+            const int64_t cap = std::min<int64_t>(kJacobiLds, (ctx->max_lds - 64) / int64_t(sizeof(double)));
+            launch_jacobi_svd(djobs.as<SvdJob>(), int(n_small), int(std::max<int64_t>(0, std::min(need, cap))), s);
         }
-        const int64_t cap = std::min<int64_t>(kJacobiLds, (ctx->max_lds - 64) / int64_t(sizeof(double)));
-        launch_jacobi_svd(djobs.as<SvdJob>(), int(jobs.size()), int(std::max<int64_t>(0, std::min(need, cap))), s);
+        const int nb = int(jobs.size() - n_small);
+        if (nb > 0) {
+            const SvdJob* big = djobs.as<SvdJob>() + n_small;
+            std::vector<int2> slots;
+            int rounds = 0;
+            for (size_t i = n_small; i < jobs.size(); ++i) {
+                const int n = std::min(jobs[i].rows, jobs[i].cols), nn = n + (n & 1);
+                rounds = std::max(rounds, nn - 1);
+                for (int pi = 0; pi < nn / 2; ++pi) slots.push_back(int2{int(i - n_small), pi});
+            }
+            DevBuf dslots(slots.size() * sizeof(int2), s), dlive(nb * sizeof(int), s), drot(nb * sizeof(int), s),
+                dinfo(nb * sizeof(int), s);
+            DMRG_HIP(hipMemcpyAsync(dslots.p, slots.data(), slots.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+            std::vector<int> live(nb, 1), rot(nb, 0), sweeps(nb, -1);
+            launch_jacobi_init(big, nb, s);
+            int left = nb;
+            for (int sw = 0; sw < 60 && left > 0; ++sw) {
+                DMRG_HIP(hipMemcpyAsync(dlive.p, live.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+                DMRG_HIP(hipMemsetAsync(drot.p, 0, nb * sizeof(int), s));
+                for (int rd = 0; rd < rounds; ++rd)
+                    launch_jacobi_round(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
+                                        drot.as<int>(), s);
+                DMRG_HIP(hipMemcpyAsync(rot.data(), drot.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+                DMRG_HIP(hipStreamSynchronize(s));
+                for (int b = 0; b < nb; ++b)
+                    if (live[b] && !rot[b]) {
+                        live[b] = 0;
+                        sweeps[b] = sw + 1;
+                        --left;
+                    }
+            }
+            DMRG_HIP(hipMemcpyAsync(dinfo.p, sweeps.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+            launch_jacobi_finish(big, nb, dinfo.as<int>(), s);
+            DMRG_HIP(hipStreamSynchronize(s));
+        }
     }
     for (size_t i = 0; i < mats.size(); ++i) {
         const SvdOut& o = outs[i];
@@ -1137,6 +1182,8 @@ void State::release_workspace() {
     part32.free();
     diag.free();
     diag_ok = false;
+    mlp_stat.free();
+    mlp_stat_ok = false;
     prepared = false;
 }
 
@@ -1291,6 +1338,7 @@ void State::prepare() {
     DMRG_HIP(hipStreamSynchronize(s));
     prepared = true;
     diag_ok = false;
+    mlp_stat_ok = false;
     if (std::getenv("DMRG_TRACE")) {
         const auto tp3 = std::chrono::steady_clock::now();
         auto d = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
@@ -1367,6 +1415,41 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
         st->gemm_launches += 2;
         st->sigma_calls += 1;
     }
+}
+
+// Static features of the learned preconditioner for every element of the
+// two-site vector: labels of its left sector and of the two site states.
+void State::build_mlp_static() {
+    prepare();
+    if (mlp_stat_ok) return;
+    const int j = center;
+    const Bond& bl = bonds[j];
+    const int K = mpo->K;
+    const double nn = std::max(1, mpo->n_elec);
+    std::vector<float> h(size_t(std::max<int64_t>(1, ts.n)) * kMlpStatic);
+    for (size_t iq = 0; iq < ts.q.size(); ++iq) {
+        const Space& sy = ts.sys[iq];
+        const Space& en = ts.env[iq];
+        for (const Seg& sg : sy.segs) {
+            const QN ql = bl.q[sg.sec];
+            const int ml = bl.dim[sg.sec];
+            const QN qs = kSiteQN[sg.st];
+            for (int r = 0; r < sg.dim; ++r)
+                for (const Seg& eg : en.segs) {
+                    const QN qt = kSiteQN[eg.st];
+                    const float f[kMlpStatic] = {float(ql.n / nn), float(ql.sz / nn), float(qs.n / 2.0),
+                                                 float(qt.n / 2.0), float(qs.sz), float(qt.sz),
+                                                 float(std::log1p(double(ml)) / 8.0), float((j + 0.5) / K)};
+                    const int64_t row = ts.off[iq] + int64_t(sg.off + r) * en.dim + eg.off;
+                    for (int c = 0; c < eg.dim; ++c)
+                        std::copy(f, f + kMlpStatic, h.begin() + (row + c) * kMlpStatic);
+                }
+        }
+    }
+    mlp_stat.alloc(h.size() * sizeof(float), ctx->stream);
+    DMRG_HIP(hipMemcpyAsync(mlp_stat.p, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    DMRG_HIP(hipStreamSynchronize(ctx->stream));
+    mlp_stat_ok = true;
 }
 
 void State::build_diag() {
@@ -1462,6 +1545,27 @@ DavSolver::DavSolver(State& st, double* x, int64_t n, const SweepOpts& o, StepSt
     G_.assign(size_t(ms_) * ms_, 0.0);
     prec_ = o.prec;
     refined_ = (prec_ == Prec::F64);
+    learned_ = o.precond == 1;
+    collect_ = o.collect != 0;
+    if (learned_ || collect_) {
+        require(o.mlp != nullptr, "learned preconditioner or sample collection without a network", E_INVAL);
+        st.build_mlp_static();
+    }
+    if (learned_) {
+        featall_.alloc(sizeof(float) * n * kMlpF, s_);
+        gall_.alloc(sizeof(float) * n, s_);
+    }
+    if (collect_) {
+        ns_ = int(std::min<int64_t>(kMlpSample, n));
+        const std::vector<int> idx = o.mlp->draw_sample(n, ns_);
+        idx_.alloc(sizeof(int) * ns_, s_);
+        DMRG_HIP(hipMemcpyAsync(idx_.p, idx.data(), sizeof(int) * ns_, hipMemcpyHostToDevice, s_));
+        const int nrec = std::min(kMlpMaxRec, o.dav_max_iter);
+        featrec_.alloc(sizeof(float) * size_t(nrec) * ns_ * kMlpF, s_);
+        drrec_.alloc(sizeof(double) * size_t(nrec) * ns_, s_);
+        urec_.alloc(sizeof(double) * size_t(nrec) * n, s_);
+        tgt_.alloc(sizeof(float) * size_t(nrec) * ns_, s_);
+    }
     const double nx = std::sqrt(dots(x, 0, 1, x)[0]);
     check_finite(nx, "Davidson start vector");
     require(nx > 0, "Davidson start vector is zero", E_NUMERIC);
@@ -1480,10 +1584,38 @@ const std::vector<double>& DavSolver::dots(const double* Vb, int64_t stride, int
 }
 
 void DavSolver::finish() {
+    if (collect_ && n_rec_ > 0) emit_samples();
     launch_copy(x_, xr_.as<double>(), n_, s_);
     DMRG_HIP(hipStreamSynchronize(s_));
     res_.iters = napply_;
     done_ = true;
+}
+
+// Features and diagonal corrections of the sampled elements and the Ritz
+// vector of this iteration, kept until the step's vector is known.
+void DavSolver::record(double theta, double rn) {
+    const int nrec = std::min(kMlpMaxRec, o_.dav_max_iter);
+    if (n_rec_ >= nrec) return;
+    const double rscale = rn > 0 ? std::sqrt(double(n_)) / rn : 0.0;
+    launch_mlp_features(st_.diag.as<double>(), r_.as<double>(), xr_.as<double>(), st_.mlp_stat.as<float>(), theta,
+                        rscale, std::sqrt(double(n_)), idx_.as<int>(), ns_,
+                        featrec_.as<float>() + size_t(n_rec_) * ns_ * kMlpF, s_);
+    launch_mlp_diag_corr(r_.as<double>(), st_.diag.as<double>(), theta, idx_.as<int>(), ns_,
+                         drrec_.as<double>() + size_t(n_rec_) * ns_, s_);
+    launch_copy(urec_.as<double>() + int64_t(n_rec_) * n_, xr_.as<double>(), n_, s_);
+    ++n_rec_;
+}
+
+// Targets of every recorded iteration against the final vector, appended to
+// the network's training set.
+void DavSolver::emit_samples() {
+    const double* psi = xr_.as<double>();
+    const std::vector<double> c = dots(urec_.as<double>(), n_, n_rec_, psi);
+    for (int k = 0; k < n_rec_; ++k)
+        launch_mlp_targets(psi, urec_.as<double>() + int64_t(k) * n_, c[k], drrec_.as<double>() + size_t(k) * ns_,
+                           idx_.as<int>(), ns_, tgt_.as<float>() + size_t(k) * ns_, s_);
+    stats_.samples += o_.mlp->append(featrec_.as<float>(), tgt_.as<float>(), int64_t(n_rec_) * ns_);
+    n_rec_ = 0;
 }
 
 bool DavSolver::advance() {
@@ -1559,7 +1691,29 @@ bool DavSolver::advance() {
         k_ = keep_;
     }
     double* t = t_.as<double>();
-    launch_precond(t, r_.as<double>(), st_.diag.as<double>(), theta, n, s_);
+    if (collect_) record(theta, rn);
+    if (learned_ && !fallback_) {
+        // a correction that raised the residual twice in a row is dropped
+        // for the diagonal one for the rest of the step
+        bad_ = (napply_ > 1 && rn > prev_rn_) ? bad_ + 1 : 0;
+        if (bad_ >= 2) {
+            fallback_ = true;
+            stats_.precond_fallbacks += 1;
+            if (std::getenv("DMRG_TRACE"))
+                fprintf(stderr, "[dmrg] learned preconditioner dropped at iteration %d (|r| %.3e > %.3e)\n",
+                        napply_, rn, prev_rn_);
+        }
+    }
+    prev_rn_ = rn;
+    if (learned_ && !fallback_) {
+        launch_mlp_features(st_.diag.as<double>(), r_.as<double>(), xr_.as<double>(), st_.mlp_stat.as<float>(),
+                            theta, rn > 0 ? std::sqrt(double(n)) / rn : 0.0, std::sqrt(double(n)), nullptr, n,
+                            featall_.as<float>(), s_);
+        launch_mlp_forward(o_.mlp->params.as<float>(), featall_.as<float>(), n, gall_.as<float>(), s_);
+        launch_mlp_precond(t, r_.as<double>(), st_.diag.as<double>(), theta, gall_.as<float>(), n, s_);
+    } else {
+        launch_precond(t, r_.as<double>(), st_.diag.as<double>(), theta, n, s_);
+    }
     for (int pass = 0; pass < 2; ++pass) {
         const auto& c = dots(Vp, n, k_, t);
         Coefs cc{};

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "core.h"
+#include "mlp.h"
 
 namespace dmrg {
 
@@ -191,13 +192,20 @@ struct SweepOpts {
     int dav_keep = 4;
     double svd_cutoff = 1e-12;
     double refine_tol = 0.0;
+    int precond = 0;       // 0 diagonal, 1 learned correction (mlp)
+    int collect = 0;       // append training samples of every step to mlp
+    Mlp* mlp = nullptr;
 };
+constexpr int kMlpSample = 4096;  // sampled elements per Davidson step for training
+constexpr int kMlpMaxRec = 40;    // recorded iterations per step
 
 struct StepStats {
     double theta = 0, discarded = 0, sigma_flops = 0, sigma_seconds = 0;
     double gemm_seconds = 0;  // the two grouped-GEMM launches of each sigma
     double pass1_seconds = 0; // the first of them
     int64_t sigma_calls = 0, dav_iters = 0, gemm_launches = 0;
+    int64_t precond_fallbacks = 0;  // steps whose learned correction was dropped for the diagonal one
+    int64_t samples = 0;            // training samples collected
     int max_bond = 0;
 };
 
@@ -242,6 +250,13 @@ class DavSolver {
     DevBuf V_, W_, r_, t_, xr_, wr_, scr_, part_, dout_;
     std::vector<double> hdot_, G_, w_, U_, rn_hist_;
     DavOut res_;
+    // learned preconditioner and training-sample collection
+    void record(double theta, double rn);
+    void emit_samples();
+    bool learned_ = false, collect_ = false, fallback_ = false;
+    int bad_ = 0, n_rec_ = 0, ns_ = 0;
+    double prev_rn_ = 0;
+    DevBuf idx_, featrec_, drrec_, urec_, tgt_, featall_, gall_;
 };
 
 // The MPS with its environments and the current two-site center.
@@ -282,6 +297,9 @@ class State {
     DevBuf tbuf, part, psi32, sig32, tbuf32, part32;
     DevBuf diag;
     bool diag_ok = false;
+    DevBuf mlp_stat;  // static features of the learned preconditioner (n x 8, FP32)
+    bool mlp_stat_ok = false;
+    void build_mlp_static();
 
     // blocking plans per (side, site): dense coefficient matrices of the
     // classes that go through the GEMM and their task lists

@@ -11,6 +11,8 @@
 //    sums, linear combinations, preconditioner) and small gathers.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "core.h"
 
 namespace dmrg {
@@ -58,21 +60,42 @@ struct Cfg<2> {
     using Acc = flt4;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b % 8), and each XCD has its own L2.  Give XCD x a contiguous run of the
+// task list instead, so that neighbouring tasks -- which read the same
+// rows of their operands -- share an L2.  A bijection on [0, g).
+__device__ inline int64_t xcd_task(int64_t b, int64_t g) {
+    const int64_t per = g / 8, rem = g % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
+// One packed K column of a grouped-GEMM step (see grouped_gemm).
+template <class T>
+struct PackCol {
+    const T* a;
+    const T* b;
+    int64_t sa, sb;
+    T alpha;
+};
+
 // ROLE only separates the symbol of the sigma-vector launches (1) from every
 // other use (0) so that profiles report them apart; the code is identical.
 // TS: output tile edge (64: four waves of 32x32, 32: one wave).
-template <int MODE, int ROLE, int TS>
+// PACK: K-steps packed across terms (else one staging round per term and
+// K-step); XCD: task order remapped per XCD (see xcd_task).
+template <int MODE, int ROLE, int TS, bool PACK>
 __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                                            const GemmTerm* __restrict__ terms,
                                                                            void* const* __restrict__ bases,
-                                                                           const int* __restrict__ active) {
+                                                                           const int* __restrict__ active, int xcd) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
     __shared__ T As[KS][TS + 4];
     __shared__ T Bs[KS][TS + 4];
 
-    const GemmTask task = tasks[blockIdx.x];
+    const GemmTask task = tasks[xcd ? xcd_task(blockIdx.x, gridDim.x) : int64_t(blockIdx.x)];
     if (active && !active[task.inst]) return;  // uniform per workgroup
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -90,15 +113,67 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
             act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
         }
 
-    for (int l = task.l_begin; l < task.l_end; ++l) {
-        const GemmTerm g = terms[l];
-        const T* A = static_cast<const T*>(bases[g.a_buf]) + g.a_off;
-        const T* B = static_cast<const T*>(bases[g.b_buf]) + g.b_off;
-        const T alpha = T(g.alpha);
-        const bool ta = g.flags & GT_TA;
-        const bool tb = g.flags & GT_TB;
-        for (int k0 = 0; k0 < g.k; k0 += KS) {
-            // stage A (m x KS) as As[kk][r] and B (KS x n) as Bs[kk][c]
+    if constexpr (PACK) {
+        // The terms' K ranges are concatenated and cut into K-steps of KS packed
+        // columns: a step may span several short terms (typical K of a block is
+        // 5-35), so a task pays one staging round per KS columns rather than per
+        // term.  Column kk of the step is described by cols[kk]:
+        // A(r, kk) = a[r * sa], B(kk, c) = b[c * sb] (alpha folded into A).
+        __shared__ PackCol<T> cols[KS];
+        __shared__ int cur_l[2], cur_k[2], nvalid;
+        auto build = [&](int l0, int k0, int nxt) {
+            if (tid < KS) {
+                int l = l0, off = k0, pos = tid;
+                while (l < task.l_end) {
+                    const int kl = terms[l].k;
+                    if (off + pos < kl) break;
+                    pos -= kl - off;
+                    off = 0;
+                    ++l;
+                }
+                PackCol<T> c{nullptr, nullptr, 0, 0, T(0)};
+                if (l < task.l_end) {
+                    const GemmTerm g = terms[l];
+                    const int kk = off + pos;
+                    const T* A = static_cast<const T*>(bases[g.a_buf]) + g.a_off;
+                    const T* B = static_cast<const T*>(bases[g.b_buf]) + g.b_off;
+                    const bool ta = g.flags & GT_TA, tb = g.flags & GT_TB;
+                    c.a = ta ? A + int64_t(kk) * g.lda : A + kk;
+                    c.sa = ta ? 1 : g.lda;
+                    c.b = tb ? B + kk : B + int64_t(kk) * g.ldb;
+                    c.sb = tb ? g.ldb : 1;
+                    c.alpha = T(g.alpha);
+                }
+                cols[tid] = c;
+            }
+            if (tid == 0) {  // cursor of the following step
+                int l = l0, off = k0, left = KS;
+                while (l < task.l_end && left > 0) {
+                    const int kl = terms[l].k;
+                    const int take = min(left, kl - off);
+                    left -= take;
+                    off += take;
+                    if (off == kl) {
+                        ++l;
+                        off = 0;
+                    }
+                }
+                cur_l[nxt] = l;
+                cur_k[nxt] = off;
+                nvalid = KS - left;
+            }
+        };
+        // step s is described by cols and nvalid; cur_*[(s + 1) & 1] holds where
+        // step s + 1 starts (written while step s - 1 was multiplied)
+        build(task.l_begin, 0, 1);
+        __syncthreads();
+        for (int it = 0;; ++it) {
+            const int kv = nvalid;  // valid packed columns of this step (uniform)
+            if (kv == 0) break;
+            // stage A (m x KS) as As[kk][r] and B (KS x n) as Bs[kk][c]; the
+            // index order follows the storage order of the first column's term
+            const bool ta = cols[0].sa == 1 && cols[0].a != nullptr;
+            const bool tb = cols[0].sb != 1;
             for (int idx = tid; idx < TS * KS; idx += NT) {
                 int r, kk;
                 if (!ta) {
@@ -108,10 +183,10 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
                     kk = idx / TS;
                     r = idx % TS;
                 }
+                const PackCol<T>& ca = cols[kk];
                 T v = T(0);
-                if (r < task.m && k0 + kk < g.k)
-                    v = ta ? A[int64_t(k0 + kk) * g.lda + r] : A[int64_t(r) * g.lda + k0 + kk];
-                As[kk][r] = v * alpha;
+                if (r < task.m && ca.a) v = ca.a[int64_t(r) * ca.sa] * ca.alpha;
+                As[kk][r] = v;
                 int c, kb;
                 if (!tb) {
                     kb = idx / TS;
@@ -120,14 +195,19 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
                     c = idx / KS;
                     kb = idx % KS;
                 }
+                const PackCol<T>& cb = cols[kb];
                 T u = T(0);
-                if (c < task.n && k0 + kb < g.k)
-                    u = tb ? B[int64_t(c) * g.ldb + k0 + kb] : B[int64_t(k0 + kb) * g.ldb + c];
+                if (c < task.n && cb.b) u = cb.b[int64_t(c) * cb.sb];
                 Bs[kb][c] = u;
             }
             __syncthreads();
-            // skip 16x16 sub-tiles outside the task and K-steps past the slice
-            const int kv = min(KS, g.k - k0);
+            // describe the next step while the MFMAs run (cols is not read below)
+            const int nl = cur_l[(it + 1) & 1], nk = cur_k[(it + 1) & 1];
+            if (nl < task.l_end)
+                build(nl, nk, it & 1);
+            else if (tid == 0)
+                nvalid = 0;
+            // skip 16x16 sub-tiles outside the task and columns past the last term
             if constexpr (MODE == 0) {
                 for (int ks = 0; ks < kv; ks += 4) {
                     const double a0 = As[ks + lk][wm + lr];
@@ -164,6 +244,84 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
             }
             __syncthreads();
+        }
+    } else {
+        // one staging round per term and K-step of KS
+        for (int l = task.l_begin; l < task.l_end; ++l) {
+            const GemmTerm g = terms[l];
+            const T* A = static_cast<const T*>(bases[g.a_buf]) + g.a_off;
+            const T* B = static_cast<const T*>(bases[g.b_buf]) + g.b_off;
+            const T alpha = T(g.alpha);
+            const bool ta = g.flags & GT_TA;
+            const bool tb = g.flags & GT_TB;
+            for (int k0 = 0; k0 < g.k; k0 += KS) {
+                // stage A (m x KS) as As[kk][r] and B (KS x n) as Bs[kk][c]
+                for (int idx = tid; idx < TS * KS; idx += NT) {
+                    int r, kk;
+                    if (!ta) {
+                        r = idx / KS;
+                        kk = idx % KS;
+                    } else {
+                        kk = idx / TS;
+                        r = idx % TS;
+                    }
+                    T v = T(0);
+                    if (r < task.m && k0 + kk < g.k)
+                        v = ta ? A[int64_t(k0 + kk) * g.lda + r] : A[int64_t(r) * g.lda + k0 + kk];
+                    As[kk][r] = v * alpha;
+                    int c, kb;
+                    if (!tb) {
+                        kb = idx / TS;
+                        c = idx % TS;
+                    } else {
+                        c = idx / KS;
+                        kb = idx % KS;
+                    }
+                    T u = T(0);
+                    if (c < task.n && k0 + kb < g.k)
+                        u = tb ? B[int64_t(c) * g.ldb + k0 + kb] : B[int64_t(k0 + kb) * g.ldb + c];
+                    Bs[kb][c] = u;
+                }
+                __syncthreads();
+                // skip 16x16 sub-tiles outside the task and K-steps past the slice
+                const int kv = min(KS, g.k - k0);
+                if constexpr (MODE == 0) {
+                    for (int ks = 0; ks < kv; ks += 4) {
+                        const double a0 = As[ks + lk][wm + lr];
+                        const double a1 = As[ks + lk][wm + 16 + lr];
+                        const double b0 = Bs[ks + lk][wn + lr];
+                        const double b1 = Bs[ks + lk][wn + 16 + lr];
+                        if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                        if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                        if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                        if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                    }
+                } else if constexpr (MODE == 1) {
+                    for (int ks = 0; ks < kv; ks += 4) {
+                        const float a0 = As[ks + lk][wm + lr];
+                        const float a1 = As[ks + lk][wm + 16 + lr];
+                        const float b0 = Bs[ks + lk][wn + lr];
+                        const float b1 = Bs[ks + lk][wn + 16 + lr];
+                        if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                        if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                        if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                        if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+                    }
+                } else {
+                    // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
+                    shrt4 a[2], b[2];
+                    for (int i = 0; i < 2; ++i)
+                        for (int e = 0; e < 4; ++e) {
+                            a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
+                            b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
+                        }
+                    for (int i = 0; i < 2; ++i)
+                        for (int j = 0; j < 2; ++j)
+                            if (act[i][j])
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
+                __syncthreads();
+            }
         }
     }
     // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds
@@ -455,14 +613,132 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs, int lds_elems) {
+// One-sided Jacobi SVD (Hestenes).  The columns of the working matrix A
+// (column length m, n columns; the transpose when rows < cols) are rotated
+// pairwise until orthogonal; V accumulates the rotations.  A round of the
+// cyclic round-robin schedule holds n/2 disjoint pairs.
+
+// pair pi of round rd for nn (= n rounded up to even) columns
+__device__ inline void jacobi_pair_of(int nn, int rd, int pi, int& p, int& q) {
+    if (pi == 0) {
+        p = nn - 1;
+        q = rd;
+    } else {
+        p = (rd + pi) % (nn - 1);
+        q = (rd - pi + nn - 1) % (nn - 1);
+    }
+}
+
+// rotate columns p, q of A (and V) by one wave; true when a rotation was applied
+__device__ inline bool jacobi_rotate(double* A, double* V, int m, int n, int p, int q, int lane) {
+    double* a = A + int64_t(p) * m;
+    double* b = A + int64_t(q) * m;
+    double al = 0, be = 0, ga = 0;
+    for (int i = lane; i < m; i += 64) {
+        const double x = a[i], y = b[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return false;
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+    for (int i = lane; i < m; i += 64) {
+        const double x = a[i], y = b[i];
+        a[i] = c * x - s * y;
+        b[i] = s * x + c * y;
+    }
+    double* vp = V + int64_t(p) * n;
+    double* vq = V + int64_t(q) * n;
+    for (int i = lane; i < n; i += 64) {
+        const double x = vp[i], y = vq[i];
+        vp[i] = c * x - s * y;
+        vq[i] = s * x + c * y;
+    }
+    return true;
+}
+
+struct JacobiDims {
+    int R, C, m, n;
+    bool tr;
+};
+__device__ inline JacobiDims jacobi_dims(const SvdJob& job) {
+    JacobiDims d;
+    d.R = job.rows;
+    d.C = job.cols;
+    d.tr = d.R < d.C;
+    d.m = d.tr ? d.C : d.R;
+    d.n = d.tr ? d.R : d.C;
+    return d;
+}
+
+// A = the source (or its transpose) column by column, V = identity
+__device__ inline void jacobi_load(const SvdJob& job, const JacobiDims& d, double* A, double* V, int tid, int nt) {
+    for (int64_t e = tid; e < int64_t(d.m) * d.n; e += nt) {
+        const int j = int(e / d.m), i = int(e % d.m);
+        A[e] = d.tr ? job.src[int64_t(j) * d.C + i] : job.src[int64_t(i) * d.C + j];
+    }
+    for (int64_t e = tid; e < int64_t(d.n) * d.n; e += nt) V[e] = (e / d.n == e % d.n) ? 1.0 : 0.0;
+}
+
+// singular values = column norms, sorted descending (ties by index); U, S, Vt
+// written in the caller's layout; one workgroup
+__device__ inline void jacobi_output(const SvdJob& job, const JacobiDims& d, const double* A, const double* V,
+                                     double* nrm, int* perm, int tid, int nt, int info) {
+    const int lane = tid & 63, wave = tid >> 6, nw = nt / 64;
+    const int m = d.m, n = d.n, R = d.R, C = d.C;
+    for (int j = wave; j < n; j += nw) {
+        double ss = 0;
+        for (int i = lane; i < m; i += 64) ss += A[int64_t(j) * m + i] * A[int64_t(j) * m + i];
+        ss = wave_sum(ss);
+        if (lane == 0) nrm[j] = sqrt(ss);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += nt) {
+        int rank = 0;
+        const double sj = nrm[j];
+        for (int k = 0; k < n; ++k) rank += (nrm[k] > sj) || (nrm[k] == sj && k < j);
+        perm[rank] = j;
+    }
+    __syncthreads();
+    const int r = n;
+    for (int k = tid; k < r; k += nt) job.S[k] = nrm[perm[k]];
+    if (!d.tr) {
+        for (int64_t e = tid; e < int64_t(R) * r; e += nt) {
+            const int i = int(e / r), k = int(e % r);
+            const double sg = nrm[perm[k]];
+            job.U[e] = sg > 0 ? A[int64_t(perm[k]) * m + i] / sg : 0.0;
+        }
+        for (int64_t e = tid; e < int64_t(r) * C; e += nt) {
+            const int k = int(e / C), j = int(e % C);
+            job.Vt[e] = V[int64_t(perm[k]) * n + j];
+        }
+    } else {
+        for (int64_t e = tid; e < int64_t(R) * r; e += nt) {
+            const int i = int(e / r), k = int(e % r);
+            job.U[e] = V[int64_t(perm[k]) * n + i];
+        }
+        for (int64_t e = tid; e < int64_t(r) * C; e += nt) {
+            const int k = int(e / C), j = int(e % C);
+            const double sg = nrm[perm[k]];
+            job.Vt[e] = sg > 0 ? A[int64_t(perm[k]) * m + j] / sg : 0.0;
+        }
+    }
+    if (tid == 0) *job.info = info;
+}
+
+// Small sectors: one workgroup of 16 waves per sector, every round inside
+// the kernel; the working set lives in LDS when it fits.
+constexpr int kJacobiThreads = 1024;
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_svd_kernel(const SvdJob* __restrict__ jobs, int lds_elems) {
     extern __shared__ double smem[];
     const SvdJob job = jobs[blockIdx.x];
-    const int R = job.rows, C = job.cols;
-    const bool tr = R < C;
-    const int m = tr ? C : R;  // column length
-    const int n = tr ? R : C;  // number of columns (= r)
-    // the working columns (and the rotations when they fit too) live in LDS
+    const JacobiDims d = jacobi_dims(job);
+    const int m = d.m, n = d.n;
     const bool a_lds = int64_t(m) * n <= lds_elems;
     const bool v_lds = int64_t(m) * n + int64_t(n) * n <= lds_elems;
     double* A = a_lds ? smem : job.work;  // column j at A + j * m
@@ -470,11 +746,7 @@ __global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restric
     double* nrm = job.work + int64_t(m) * n + int64_t(n) * n;
     int* perm = reinterpret_cast<int*>(nrm + n);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t e = tid; e < int64_t(m) * n; e += blockDim.x) {
-        const int j = int(e / m), i = int(e % m);
-        A[e] = tr ? job.src[int64_t(j) * C + i] : job.src[int64_t(i) * C + j];
-    }
-    for (int64_t e = tid; e < int64_t(n) * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    jacobi_load(job, d, A, V, tid, blockDim.x);
     __shared__ int rotated;
     __syncthreads();
     const int nn = n + (n & 1);
@@ -484,89 +756,56 @@ __global__ __launch_bounds__(256) void jacobi_svd_kernel(const SvdJob* __restric
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int rd = 0; rd < nn - 1; ++rd) {
-            for (int pi = wave; pi < nn / 2; pi += 4) {
+            for (int pi = wave; pi < nn / 2; pi += kJacobiThreads / 64) {
                 int p, q;
-                if (pi == 0) {
-                    p = nn - 1;
-                    q = rd;
-                } else {
-                    p = (rd + pi) % (nn - 1);
-                    q = (rd - pi + nn - 1) % (nn - 1);
-                }
+                jacobi_pair_of(nn, rd, pi, p, q);
                 if (p >= n || q >= n) continue;
-                double* a = A + int64_t(p) * m;
-                double* b = A + int64_t(q) * m;
-                double al = 0, be = 0, ga = 0;
-                for (int i = lane; i < m; i += 64) {
-                    const double x = a[i], y = b[i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
-                }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
-                const double zeta = (be - al) / (2.0 * ga);
-                const double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int i = lane; i < m; i += 64) {
-                    const double x = a[i], y = b[i];
-                    a[i] = c * x - s * y;
-                    b[i] = s * x + c * y;
-                }
-                double* vp = V + int64_t(p) * n;
-                double* vq = V + int64_t(q) * n;
-                for (int i = lane; i < n; i += 64) {
-                    const double x = vp[i], y = vq[i];
-                    vp[i] = c * x - s * y;
-                    vq[i] = s * x + c * y;
-                }
-                if (lane == 0) rotated = 1;
+                if (jacobi_rotate(A, V, m, n, p, q, lane) && lane == 0) rotated = 1;
             }
             __syncthreads();
         }
         converged = (rotated == 0);
         __syncthreads();
     }
-    for (int j = wave; j < n; j += 4) {
-        double ss = 0;
-        for (int i = lane; i < m; i += 64) ss += A[int64_t(j) * m + i] * A[int64_t(j) * m + i];
-        ss = wave_sum(ss);
-        if (lane == 0) nrm[j] = sqrt(ss);
-    }
-    __syncthreads();
-    for (int j = tid; j < n; j += blockDim.x) {
-        int rank = 0;
-        const double sj = nrm[j];
-        for (int k = 0; k < n; ++k) rank += (nrm[k] > sj) || (nrm[k] == sj && k < j);
-        perm[rank] = j;
-    }
-    __syncthreads();
-    const int r = n;
-    for (int k = tid; k < r; k += blockDim.x) job.S[k] = nrm[perm[k]];
-    if (!tr) {
-        for (int64_t e = tid; e < int64_t(R) * r; e += blockDim.x) {
-            const int i = int(e / r), k = int(e % r);
-            const double sg = nrm[perm[k]];
-            job.U[e] = sg > 0 ? A[int64_t(perm[k]) * m + i] / sg : 0.0;
-        }
-        for (int64_t e = tid; e < int64_t(r) * C; e += blockDim.x) {
-            const int k = int(e / C), j = int(e % C);
-            job.Vt[e] = V[int64_t(perm[k]) * n + j];
-        }
-    } else {
-        for (int64_t e = tid; e < int64_t(R) * r; e += blockDim.x) {
-            const int i = int(e / r), k = int(e % r);
-            job.U[e] = V[int64_t(perm[k]) * n + i];
-        }
-        for (int64_t e = tid; e < int64_t(r) * C; e += blockDim.x) {
-            const int k = int(e / C), j = int(e % C);
-            const double sg = nrm[perm[k]];
-            job.Vt[e] = sg > 0 ? A[int64_t(perm[k]) * m + j] / sg : 0.0;
-        }
-    }
-    if (tid == 0) *job.info = converged ? sweep : -1;
+    jacobi_output(job, d, A, V, nrm, perm, tid, blockDim.x, converged ? sweep : -1);
+}
+
+// Large sectors: the working set in global memory, one launch per round
+// covering the pairs of every sector (one wave per pair).
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_init_kernel(const SvdJob* __restrict__ jobs) {
+    const SvdJob job = jobs[blockIdx.x];
+    const JacobiDims d = jacobi_dims(job);
+    jacobi_load(job, d, job.work, job.work + int64_t(d.m) * d.n, threadIdx.x, blockDim.x);
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const SvdJob* __restrict__ jobs,
+                                                           const int2* __restrict__ slots, int64_t n_slots,
+                                                           int rd, const int* __restrict__ live,
+                                                           int* __restrict__ rotated) {
+    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (w >= n_slots) return;
+    const int2 sl = slots[w];
+    if (!live[sl.x]) return;
+    const SvdJob job = jobs[sl.x];
+    const JacobiDims d = jacobi_dims(job);
+    const int nn = d.n + (d.n & 1);
+    if (rd >= nn - 1) return;
+    int p, q;
+    jacobi_pair_of(nn, rd, sl.y, p, q);
+    if (p >= d.n || q >= d.n) return;
+    double* A = job.work;
+    double* V = job.work + int64_t(d.m) * d.n;
+    if (jacobi_rotate(A, V, d.m, d.n, p, q, threadIdx.x & 63) && (threadIdx.x & 63) == 0) rotated[sl.x] = 1;
+}
+
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_finish_kernel(const SvdJob* __restrict__ jobs,
+                                                                      const int* __restrict__ info) {
+    const SvdJob job = jobs[blockIdx.x];
+    const JacobiDims d = jacobi_dims(job);
+    double* A = job.work;
+    double* V = job.work + int64_t(d.m) * d.n;
+    double* nrm = V + int64_t(d.n) * d.n;
+    jacobi_output(job, d, A, V, nrm, reinterpret_cast<int*>(nrm + d.n), threadIdx.x, blockDim.x, info[blockIdx.x]);
 }
 
 inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
@@ -578,22 +817,29 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 }  // namespace
 
-template <int ROLE, int TS>
+// Kernel variant switches (environment, read once): DMRG_GEMM_PACK=0 turns
+// the packed K-steps off, DMRG_GEMM_XCD=0 the per-XCD task order.
+static int gemm_env(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+template <int ROLE, int TS, bool PACK>
 static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                             void* const* b, const int* act, hipStream_t s) {
+                             void* const* b, const int* act, hipStream_t s, int xcd) {
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
         const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
         }
     }
@@ -604,8 +850,12 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
                              void* const* b, const int* act, int tile, hipStream_t s) {
     if (n_tasks <= 0) return;
     require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
+    static const int pack = gemm_env("DMRG_GEMM_PACK", 0), xcd = gemm_env("DMRG_GEMM_XCD", 0);
     if (tile == 64) {
-        launch_gemm_tile<ROLE, 64>(p, tasks, n_tasks, terms, b, act, s);
+        if (pack)
+            launch_gemm_tile<ROLE, 64, true>(p, tasks, n_tasks, terms, b, act, s, xcd);
+        else
+            launch_gemm_tile<ROLE, 64, false>(p, tasks, n_tasks, terms, b, act, s, xcd);
     } else {
         // four tasks per workgroup, one per wave
         const int64_t g = (n_tasks + 3) / 4;
@@ -736,9 +986,27 @@ void launch_gather_rows(double* dst, int dld, const double* src, int sld, const 
     DMRG_HIP(hipGetLastError());
 }
 
+void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return;
+    hipLaunchKernelGGL(jacobi_init_kernel, dim3(n_jobs), dim3(kJacobiThreads), 0, s, jobs);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
+                         int* rotated, hipStream_t s) {
+    if (n_slots <= 0) return;
+    hipLaunchKernelGGL(jacobi_round_kernel, dim3(unsigned((n_slots + 3) / 4)), dim3(256), 0, s, jobs, slots,
+                       n_slots, rd, live, rotated);
+    DMRG_HIP(hipGetLastError());
+}
+void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s) {
+    if (n_jobs <= 0) return;
+    hipLaunchKernelGGL(jacobi_finish_kernel, dim3(n_jobs), dim3(kJacobiThreads), 0, s, jobs, info);
+    DMRG_HIP(hipGetLastError());
+}
+
 void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, int lds_elems, hipStream_t s) {
     if (n_jobs <= 0) return;
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(n_jobs), dim3(256), size_t(lds_elems) * sizeof(double), s,
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(n_jobs), dim3(kJacobiThreads), size_t(lds_elems) * sizeof(double), s,
                        jobs, lds_elems);
     DMRG_HIP(hipGetLastError());
 }

@@ -1,0 +1,176 @@
+"""GPU parity of the learned Davidson preconditioner against oracle.mlp.
+
+Forward, gradient and Adam of the network, the features at an imported
+two-site center and the training targets are compared with the FP64 oracle
+on the same FP32-rounded inputs (tolerance 1e-5 relative); sweeps with the
+learned correction must reach the energies of the diagonal preconditioner.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1605_02611_amd as P  # noqa: E402
+from oracle import dmrg as od  # noqa: E402
+from oracle import mlp as om  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from workloads import chain_integrals, mps_values  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def _dev32(a):
+    return torch.tensor(_f32(a), device="cuda", dtype=torch.float32)
+
+
+def _dev64(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda", dtype=torch.float64)
+
+
+def _params(seed, scale=0.3):
+    return _f32(np.random.default_rng(seed).standard_normal(om.n_params()) * scale)
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000])
+def test_forward_matches_oracle(ctx, n):
+    _log("mlp forward", n)
+    p = _params(11)
+    X = _f32(np.random.default_rng(12).standard_normal((n, om.N_FEATURES)))
+    net = P.Mlp(ctx, p)
+    assert np.array_equal(net.params(), p)
+    out = torch.zeros(n, device="cuda", dtype=torch.float32)
+    net.forward(_dev32(X), out)
+    ref, _ = om.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [1, 64, 300])
+def test_gradient_matches_oracle(ctx, n):
+    _log("mlp gradient", n)
+    p = _params(13)
+    rng = np.random.default_rng(14)
+    X = _f32(rng.standard_normal((n, om.N_FEATURES)))
+    y = _f32(rng.standard_normal(n))
+    net = P.Mlp(ctx, p)
+    g = torch.zeros(om.n_params(), device="cuda", dtype=torch.float32)
+    loss = net.loss_grad(_dev32(X), _dev32(y), g)
+    lref, gref = om.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64))
+    assert abs(loss - lref) <= 1e-5 * max(1.0, lref)
+    gg = g.cpu().numpy()
+    assert np.linalg.norm(gg - gref) <= 1e-5 * np.linalg.norm(gref)
+    assert np.abs(gg - gref).max() <= 1e-5 * np.abs(gref).max()
+
+
+def test_adam_steps_match_oracle(ctx):
+    p = _params(15)
+    net = P.Mlp(ctx, p)
+    pr = p.astype(np.float64)
+    m = np.zeros_like(pr)
+    v = np.zeros_like(pr)
+    rng = np.random.default_rng(16)
+    for t in (1, 2, 3):
+        g = _f32(rng.standard_normal(om.n_params()))
+        net.adam_step(_dev32(g), 1e-2)
+        pr, m, v = om.adam_step(pr, m, v, t, g.astype(np.float64), 1e-2)
+        assert np.abs(net.params() - pr).max() <= 1e-5 * max(1.0, np.abs(pr).max()), t
+
+
+def test_targets_match_oracle(ctx):
+    rng = np.random.default_rng(17)
+    n, ns = 5000, 700
+    psi = rng.standard_normal(n)
+    u = rng.standard_normal(n)
+    u /= np.linalg.norm(u)
+    idx = rng.integers(0, n, ns).astype(np.int32)
+    dr = rng.standard_normal(ns)
+    dr[5] = 0.0
+    c = float(psi @ u)
+    out = torch.zeros(ns, device="cuda", dtype=torch.float32)
+    P.mlp_targets(ctx, _dev64(psi), _dev64(u), c, _dev64(dr),
+                  torch.tensor(idx, device="cuda", dtype=torch.int32), out)
+    ref = om.targets(psi[idx], u[idx], c, dr)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5 * 3.0
+
+
+def _imported_state(ctx, K=6, N=6, M=12, center=2, seed=21):
+    I = chain_integrals(K, n_elec=N, seed=seed)
+    d = od.DMRG(I.h, I.v, N, 0, M, mps_values(seed, od.n_mps_values(K, N, 0, M)))
+    for j in range(center):
+        d.step(j, True, False)
+    mpo = P.Mpo(ctx, I.h, I.v, N, 0)
+    bonds = [H.sectors(l) for l in d.labels]
+    fine = np.concatenate([H.site_fine_blocks(d.A[j], d.labels[j], d.labels[j + 1]) for j in range(K)])
+    return d, mpo, P.Mps.from_tensors(ctx, mpo, bonds, fine, center)
+
+
+def test_features_at_an_imported_center_match_oracle(ctx):
+    K, N, c = 6, 6, 2
+    d, mpo, mps = _imported_state(ctx, K=K, N=N, center=c)
+    lab_l, lab_r = np.asarray(d.labels[c]), np.asarray(d.labels[c + 2])
+    idx, (ml, _, _, mr) = H.merged_index(lab_l, lab_r)
+    a, s = idx // (16 * mr), (idx // (4 * mr)) % 4
+    t = (idx // mr) % 4
+    dims = {q: dd for q0, q1, dd in H.sectors(lab_l) for q in [(q0, q1)]}
+    st_ref = om.static_features(lab_l[a, 0], lab_l[a, 1], [H.SITE_QN[x][0] for x in s],
+                                [H.SITE_QN[x][0] for x in t], [H.SITE_QN[x][1] for x in s],
+                                [H.SITE_QN[x][1] for x in t], [dims[tuple(q)] for q in lab_l[a]], c, K, N)
+    st = P.mlp_static(ctx, mps)
+    assert np.abs(st - st_ref).max() <= 1e-6
+    n = mps.psi_size()
+    rng = np.random.default_rng(22)
+    r = rng.standard_normal(n)
+    u = rng.standard_normal(n)
+    u /= np.linalg.norm(u)
+    diag = torch.zeros(n, device="cuda", dtype=torch.float64)
+    mps.diag(diag)
+    theta = float(diag.min().item()) - 0.3
+    feat = torch.zeros((n, om.N_FEATURES), device="cuda", dtype=torch.float32)
+    P.mlp_features(ctx, mps, theta, _dev64(r), _dev64(u), feat)
+    ref = om.features(theta, diag.cpu().numpy(), r, u, st.astype(np.float64))
+    assert np.abs(feat.cpu().numpy() - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_collect_train_and_learned_sweeps(ctx):
+    """Sweeps that collect samples, training on them, then learned sweeps
+    that reach the energies of diagonal sweeps from the same state."""
+    K, N, M, seed = 8, 8, 24, 31
+    I = chain_integrals(K, n_elec=N, seed=seed)
+    mpo = P.Mpo(ctx, I.h, I.v, N, 0)
+    n = mpo.n_values(M)
+    net = P.Mlp(ctx, seed=5, capacity=1 << 20)
+    mps = P.Mps.random(ctx, mpo, M, mps_values(seed, n))
+    o = P.default_opts(dav_tol=1e-9, collect=1, mlp=net)
+    stats, _ = mps.sweep(M, 2, o)
+    ns = net.dataset(fetch=False)
+    assert ns == sum(s["samples"] for s in stats) > 0
+    X, y = net.dataset()
+    assert np.all(np.isfinite(X)) and np.all(np.abs(y) <= 3.0)
+    l1 = net.train(1, 4096, 1e-3, 1)
+    l2 = net.train(20, 4096, 1e-3, 2)
+    _log("mlp samples %d loss %.4f -> %.4f" % (ns, l1, l2))
+    assert np.isfinite(l2) and l2 < l1
+    # the same starting state twice: diagonal and learned
+    res = {}
+    for mode in (0, 1):
+        m2 = P.Mps.random(ctx, mpo, M, mps_values(seed, n))
+        o = P.default_opts(dav_tol=1e-9, precond=mode, mlp=net if mode else None)
+        st, th = m2.sweep(M, 3, o)
+        res[mode] = (m2.energy(), [s["dav_iters"] for s in st], sum(s["precond_fallbacks"] for s in st))
+        _log("precond %d energy %.12f iters %s fallbacks %d" % ((mode,) + res[mode]))
+    assert abs(res[0][0] - res[1][0]) <= 1e-8

@@ -273,3 +273,56 @@ def test_batched_sweeps_equal_individual_sweeps(ctx, prec):
         assert np.abs(np.array(es) - np.array(singles[b][0])).max() < 1e-9
         assert abs(mps.energy() - singles[b][1]) < 1e-9
         assert mps.bond(I.K // 2) == singles[b][2]
+
+
+# --- truncation with large sectors (round-parallel Jacobi SVD) --------------------
+
+def _sector_layout(bl, br):
+    """Middle sectors q (sorted) with (d_sys, d_env) from the bond sector lists
+    of bonds j and j+2 (rows (Q_l, s), columns (t, Q_r))."""
+    ml = {(a, b): d for a, b, d in bl}
+    mr = {(a, b): d for a, b, d in br}
+    qs = sorted({(a + H.SITE_QN[s][0], b + H.SITE_QN[s][1]) for (a, b) in ml for s in range(4)})
+    out = []
+    for q in qs:
+        ds = sum(ml.get((q[0] - H.SITE_QN[s][0], q[1] - H.SITE_QN[s][1]), 0) for s in range(4))
+        de = sum(mr.get((q[0] + H.SITE_QN[t][0], q[1] + H.SITE_QN[t][1]), 0) for t in range(4))
+        if ds and de:
+            out.append((q, ds, de))
+    return out
+
+
+def test_truncation_with_large_sectors_matches_numpy_svd(ctx):
+    """A K=12 random state at M=1024 has two-site sectors of a few hundred
+    columns at the middle: one truncating step to M=64 (Davidson limited to
+    the start vector) must discard exactly the weight and keep exactly the
+    sector counts that numpy's SVD of the exported vector gives."""
+    K, N, M0, M1 = 12, 12, 1024, 64
+    I = chain_integrals(K, n_elec=N, seed=41)
+    mpo = P.Mpo(ctx, I.h, I.v, N, 0)
+    mps = P.Mps.random(ctx, mpo, M0, mps_values(41, mpo.n_values(M0)))
+    j = 5
+    for _ in range(j):
+        mps.move(True)
+    lay = _sector_layout(mps.bond(j), mps.bond(j + 2))
+    big = max(min(ds, de) for _, ds, de in lay)
+    _log("largest sector min-dimension", big)
+    assert big >= 160  # the round-parallel path is exercised
+    psi = mps.psi()
+    psi = psi / np.linalg.norm(psi)
+    sv, off = [], 0
+    for q, ds, de in lay:
+        s = np.linalg.svd(psi[off:off + ds * de].reshape(ds, de), compute_uv=False)
+        sv += [(-x, q, i) for i, x in enumerate(s)]
+        off += ds * de
+    assert off == psi.size
+    sv.sort()
+    smax = -sv[0][0]
+    keep = [t for t in sv if -t[0] > 1e-12 * smax][:M1]
+    disc = sum(t[0] ** 2 for t in sv[len(keep):])
+    kept = {}
+    for _, q, _ in keep:
+        kept[q] = kept.get(q, 0) + 1
+    th, st = mps.step(M1, True, P.default_opts(dav_max_iter=1))
+    assert abs(st["discarded"] - disc) <= 1e-10 * max(disc, 1e-300) + 1e-15
+    assert {(a, b): d for a, b, d in mps.bond(j + 1)} == kept
