@@ -82,9 +82,11 @@ struct PackCol {
 // ROLE only separates the symbol of the sigma-vector launches (1) from every
 // other use (0) so that profiles report them apart; the code is identical.
 // TS: output tile edge (64: four waves of 32x32, 32: one wave).
-// PACK: K-steps packed across terms (else one staging round per term and
-// K-step); XCD: task order remapped per XCD (see xcd_task).
-template <int MODE, int ROLE, int TS, bool PACK>
+// VAR 0: one staging round per term and K-step; 1: K-steps packed across
+// terms; 2: software pipeline (the next step's operands are loaded into
+// registers while the current step is multiplied).  XCD: task order
+// remapped per XCD (see xcd_task).
+template <int MODE, int ROLE, int TS, int VAR>
 __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                                            const GemmTerm* __restrict__ terms,
                                                                            void* const* __restrict__ bases,
@@ -113,7 +115,104 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
             act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
         }
 
-    if constexpr (PACK) {
+    // the MFMAs of one staged K-step (kv valid columns)
+    auto mfma_step = [&](int kv) {
+        if constexpr (MODE == 0) {
+            for (int ks = 0; ks < kv; ks += 4) {
+                const double a0 = As[ks + lk][wm + lr];
+                const double a1 = As[ks + lk][wm + 16 + lr];
+                const double b0 = Bs[ks + lk][wn + lr];
+                const double b1 = Bs[ks + lk][wn + 16 + lr];
+                if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else if constexpr (MODE == 1) {
+            for (int ks = 0; ks < kv; ks += 4) {
+                const float a0 = As[ks + lk][wm + lr];
+                const float a1 = As[ks + lk][wm + 16 + lr];
+                const float b0 = Bs[ks + lk][wn + lr];
+                const float b1 = Bs[ks + lk][wn + 16 + lr];
+                if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else {
+            shrt4 a[2], b[2];
+            for (int i = 0; i < 2; ++i)
+                for (int e = 0; e < 4; ++e) {
+                    a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
+                    b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
+                }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    if (act[i][j])
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    if constexpr (VAR == 2) {
+        constexpr int PER = TS * KS / NT;  // A (and B) elements per thread per K-step
+        T ra[PER], rb[PER];
+        // operands of K-step (t, kb0) into registers
+        auto load = [&](const GemmTerm& t, int kb0) {
+            const T* A = static_cast<const T*>(bases[t.a_buf]) + t.a_off;
+            const T* B = static_cast<const T*>(bases[t.b_buf]) + t.b_off;
+            const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+            const T alpha = T(t.alpha);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int idx = tid + i * NT;
+                const int r = ta ? idx % TS : idx / KS, kk = ta ? idx / TS : idx % KS;
+                T v = T(0);
+                if (r < task.m && kb0 + kk < t.k)
+                    v = ta ? A[int64_t(kb0 + kk) * t.lda + r] : A[int64_t(r) * t.lda + kb0 + kk];
+                ra[i] = v * alpha;
+                const int c = tb ? idx / KS : idx % TS, kb = tb ? idx % KS : idx / TS;
+                T u = T(0);
+                if (c < task.n && kb0 + kb < t.k)
+                    u = tb ? B[int64_t(c) * t.ldb + kb0 + kb] : B[int64_t(kb0 + kb) * t.ldb + c];
+                rb[i] = u;
+            }
+        };
+        auto store = [&](const GemmTerm& t) {
+            const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int idx = tid + i * NT;
+                As[ta ? idx / TS : idx % KS][ta ? idx % TS : idx / KS] = ra[i];
+                Bs[tb ? idx % KS : idx / TS][tb ? idx / KS : idx % TS] = rb[i];
+            }
+        };
+        int l = task.l_begin, k0 = 0;
+        GemmTerm g{}, gn{};
+        if (l < task.l_end) {
+            g = terms[l];
+            if (l + 1 < task.l_end) gn = terms[l + 1];
+            load(g, 0);
+        }
+        while (l < task.l_end) {
+            store(g);
+            __syncthreads();
+            const int kv = min(KS, g.k - k0);
+            int nl = l, nk = k0 + KS;
+            if (nk >= g.k) {
+                nl = l + 1;
+                nk = 0;
+                if (nl < task.l_end) {
+                    g = gn;
+                    if (nl + 1 < task.l_end) gn = terms[nl + 1];
+                }
+            }
+            if (nl < task.l_end) load(g, nk);  // in flight during the MFMAs
+            mfma_step(kv);
+            __syncthreads();
+            l = nl;
+            k0 = nk;
+        }
+    } else if constexpr (VAR == 1) {
         // The terms' K ranges are concatenated and cut into K-steps of KS packed
         // columns: a step may span several short terms (typical K of a block is
         // 5-35), so a task pays one staging round per KS columns rather than per
@@ -817,14 +916,15 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 }  // namespace
 
-// Kernel variant switches (environment, read once): DMRG_GEMM_PACK=0 turns
-// the packed K-steps off, DMRG_GEMM_XCD=0 the per-XCD task order.
+// Kernel variant switches (environment, read once): DMRG_GEMM_VARIANT
+// (0 plain, 1 packed K-steps, 2 software pipeline) and DMRG_GEMM_XCD=1 for
+// the per-XCD task order.
 static int gemm_env(const char* name, int dflt) {
     const char* e = std::getenv(name);
     return e ? std::atoi(e) : dflt;
 }
 
-template <int ROLE, int TS, bool PACK>
+template <int ROLE, int TS, int VAR>
 static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                              void* const* b, const int* act, hipStream_t s, int xcd) {
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
@@ -833,13 +933,13 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
         const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, PACK>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
                 break;
         }
     }
@@ -850,12 +950,14 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
                              void* const* b, const int* act, int tile, hipStream_t s) {
     if (n_tasks <= 0) return;
     require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
-    static const int pack = gemm_env("DMRG_GEMM_PACK", 0), xcd = gemm_env("DMRG_GEMM_XCD", 0);
+    static const int var = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
     if (tile == 64) {
-        if (pack)
-            launch_gemm_tile<ROLE, 64, true>(p, tasks, n_tasks, terms, b, act, s, xcd);
+        if (var == 1)
+            launch_gemm_tile<ROLE, 64, 1>(p, tasks, n_tasks, terms, b, act, s, xcd);
+        else if (var == 2)
+            launch_gemm_tile<ROLE, 64, 2>(p, tasks, n_tasks, terms, b, act, s, xcd);
         else
-            launch_gemm_tile<ROLE, 64, false>(p, tasks, n_tasks, terms, b, act, s, xcd);
+            launch_gemm_tile<ROLE, 64, 0>(p, tasks, n_tasks, terms, b, act, s, xcd);
     } else {
         // four tasks per workgroup, one per wave
         const int64_t g = (n_tasks + 3) / 4;
