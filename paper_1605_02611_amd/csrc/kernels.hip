@@ -440,6 +440,216 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
             }
 }
 
+// Descriptors are the same for the whole workgroup: keep them in scalar
+// registers (the compiler cannot prove it across the persistent loop).
+__device__ inline int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline int64_t ufl64(int64_t x) {
+    return int64_t((uint64_t(uint32_t(ufl(int(uint64_t(x) >> 32)))) << 32) | uint32_t(ufl(int(x))));
+}
+__device__ inline GemmTask uniform_task(GemmTask t) {
+    t.c_off = ufl64(t.c_off);
+    t.c_buf = ufl(t.c_buf);
+    t.ldc = ufl(t.ldc);
+    t.m = ufl(t.m);
+    t.n = ufl(t.n);
+    t.accumulate = ufl(t.accumulate);
+    t.l_begin = ufl(t.l_begin);
+    t.l_end = ufl(t.l_end);
+    t.inst = ufl(t.inst);
+    return t;
+}
+__device__ inline GemmTerm uniform_term(GemmTerm g) {
+    g.a_off = ufl64(g.a_off);
+    g.b_off = ufl64(g.b_off);
+    g.a_buf = ufl(g.a_buf);
+    g.b_buf = ufl(g.b_buf);
+    g.k = ufl(g.k);
+    g.lda = ufl(g.lda);
+    g.ldb = ufl(g.ldb);
+    g.flags = ufl(g.flags);
+    g.alpha = __longlong_as_double(ufl64(__double_as_longlong(g.alpha)));
+    return g;
+}
+
+// Persistent variant: grid of about (CUs x occupancy) workgroups, workgroup
+// w takes tasks w, w + G, w + 2G, ... (static round robin, no atomics: every
+// workgroup ends after its last task).  The software pipeline of VAR 2 runs
+// across task boundaries: while the last K-step of a task is multiplied,
+// the first operands of the workgroup's next task are already loaded.
+template <int MODE, int ROLE>
+__global__ __launch_bounds__(256) void persistent_gemm(const GemmTask* __restrict__ tasks, int64_t n_tasks,
+                                                       const GemmTerm* __restrict__ terms,
+                                                       void* const* __restrict__ bases,
+                                                       const int* __restrict__ active) {
+    using T = typename Cfg<MODE>::T;
+    using Acc = typename Cfg<MODE>::Acc;
+    constexpr int TS = 64, NT = 256, PER = TS * KS / NT;
+    __shared__ T As[KS][TS + 4];
+    __shared__ T Bs[KS][TS + 4];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t G = gridDim.x;
+
+    auto live = [&](int64_t t) {  // next task of this workgroup that is not masked out
+        while (t < n_tasks && active && !active[ufl(tasks[t].inst)]) t += G;
+        return t;
+    };
+    auto write_empty = [&](const GemmTask& t) {  // a task without terms: C = 0 (or unchanged)
+        if (t.accumulate) return;
+        T* C = static_cast<T*>(bases[t.c_buf]) + t.c_off;
+        for (int e = tid; e < t.m * t.n; e += NT) C[int64_t(e / t.n) * t.ldc + e % t.n] = T(0);
+    };
+    T ra[PER], rb[PER];
+    auto load = [&](const GemmTask& tk, const GemmTerm& t, int kb0) {
+        const T* A = static_cast<const T*>(bases[t.a_buf]) + t.a_off;
+        const T* B = static_cast<const T*>(bases[t.b_buf]) + t.b_off;
+        const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+        const T alpha = T(t.alpha);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + i * NT;
+            const int r = ta ? idx % TS : idx / KS, kk = ta ? idx / TS : idx % KS;
+            T v = T(0);
+            if (r < tk.m && kb0 + kk < t.k) v = ta ? A[int64_t(kb0 + kk) * t.lda + r] : A[int64_t(r) * t.lda + kb0 + kk];
+            ra[i] = v * alpha;
+            const int c = tb ? idx / KS : idx % TS, kb = tb ? idx % KS : idx / TS;
+            T u = T(0);
+            if (c < tk.n && kb0 + kb < t.k) u = tb ? B[int64_t(c) * t.ldb + kb0 + kb] : B[int64_t(kb0 + kb) * t.ldb + c];
+            rb[i] = u;
+        }
+    };
+    auto store = [&](const GemmTerm& t) {
+        const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = tid + i * NT;
+            As[ta ? idx / TS : idx % KS][ta ? idx % TS : idx / KS] = ra[i];
+            Bs[tb ? idx % KS : idx / TS][tb ? idx / KS : idx % TS] = rb[i];
+        }
+    };
+
+    // first task with terms (tasks without terms are written on the way)
+    int64_t ti = live(blockIdx.x);
+    GemmTask task{};
+    while (ti < n_tasks) {
+        task = uniform_task(tasks[ti]);
+        if (task.l_begin < task.l_end) break;
+        write_empty(task);
+        ti = live(ti + G);
+    }
+    if (ti >= n_tasks) return;
+    Acc acc[2][2];
+    bool act[2][2];
+    auto reset = [&]() {
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                acc[i][j] = Acc{0, 0, 0, 0};
+                act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
+            }
+    };
+    reset();
+    GemmTerm g = uniform_term(terms[task.l_begin]);
+    GemmTerm gn = task.l_begin + 1 < task.l_end ? uniform_term(terms[task.l_begin + 1]) : g;
+    load(task, g, 0);
+    int l = task.l_begin, k0 = 0;
+    while (true) {
+        store(g);
+        __syncthreads();
+        const int kv = min(KS, g.k - k0);
+        int nl = l, nk = k0 + KS;
+        bool task_end = false;
+        GemmTask ntask = task;
+        int64_t nti = ti;
+        if (nk >= g.k) {
+            nl = l + 1;
+            nk = 0;
+            if (nl < task.l_end) {
+                g = gn;
+                if (nl + 1 < task.l_end) gn = uniform_term(terms[nl + 1]);
+            } else {
+                task_end = true;
+            }
+        }
+        if (!task_end) {
+            load(task, g, nk);
+        } else {
+            nti = live(ti + G);
+            while (nti < n_tasks) {
+                ntask = uniform_task(tasks[nti]);
+                if (ntask.l_begin < ntask.l_end) break;
+                write_empty(ntask);
+                nti = live(nti + G);
+            }
+            if (nti < n_tasks) {
+                g = uniform_term(terms[ntask.l_begin]);
+                gn = ntask.l_begin + 1 < ntask.l_end ? uniform_term(terms[ntask.l_begin + 1]) : g;
+                load(ntask, g, 0);  // in flight during the last MFMAs of this task
+            }
+        }
+        if constexpr (MODE == 0) {
+            for (int ks = 0; ks < kv; ks += 4) {
+                const double a0 = As[ks + lk][wm + lr];
+                const double a1 = As[ks + lk][wm + 16 + lr];
+                const double b0 = Bs[ks + lk][wn + lr];
+                const double b1 = Bs[ks + lk][wn + 16 + lr];
+                if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else if constexpr (MODE == 1) {
+            for (int ks = 0; ks < kv; ks += 4) {
+                const float a0 = As[ks + lk][wm + lr];
+                const float a1 = As[ks + lk][wm + 16 + lr];
+                const float b0 = Bs[ks + lk][wn + lr];
+                const float b1 = Bs[ks + lk][wn + 16 + lr];
+                if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else {
+            shrt4 a[2], b[2];
+            for (int i = 0; i < 2; ++i)
+                for (int e = 0; e < 4; ++e) {
+                    a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
+                    b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
+                }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    if (act[i][j])
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (!task_end) {
+            l = nl;
+            k0 = nk;
+            continue;
+        }
+        // the task is complete: write its tile
+        T* C = static_cast<T*>(bases[task.c_buf]) + task.c_off;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int e = 0; e < 4; ++e) {
+                    const int r = wm + 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
+                    const int c = wn + 16 * j + lr;
+                    if (r < task.m && c < task.n) {
+                        T* p = C + int64_t(r) * task.ldc + c;
+                        const T v = T(acc[i][j][e]);
+                        *p = task.accumulate ? *p + v : v;
+                    }
+                }
+        if (nti >= n_tasks) return;
+        task = ntask;
+        ti = nti;
+        reset();
+        l = task.l_begin;
+        k0 = 0;
+    }
+}
+
 // Wave-level variant for lists of small blocks: every wave owns one task
 // (output tile <= 32 x 32) and feeds the MFMAs straight from global memory
 // (L2) into registers, without LDS or barriers; the loads of up to 16 K
@@ -917,8 +1127,8 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 }  // namespace
 
 // Kernel variant switches (environment, read once): DMRG_GEMM_VARIANT
-// (0 plain, 1 packed K-steps, 2 software pipeline) and DMRG_GEMM_XCD=1 for
-// the per-XCD task order.
+// (0 plain, 1 packed K-steps, 2 software pipeline, 3 persistent software
+// pipeline) and DMRG_GEMM_XCD=1 for the per-XCD task order.
 static int gemm_env(const char* name, int dflt) {
     const char* e = std::getenv(name);
     return e ? std::atoi(e) : dflt;
@@ -952,7 +1162,42 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
     static const int var = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
     if (tile == 64) {
-        if (var == 1)
+        if (var == 3) {
+            // persistent workgroups: as many as are resident at once
+            static int cus = 0;
+            if (!cus) {
+                int dev = 0;
+                DMRG_HIP(hipGetDevice(&dev));
+                DMRG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                if (cus < 1) cus = 1;
+            }
+            static int occ[3] = {0, 0, 0};  // resident workgroups per CU, per precision
+            auto grid = [&](const void* fn) {
+                int& per = occ[int(p)];
+                if (!per) {
+                    DMRG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0));
+                    per = std::max(1, per);
+                }
+                return unsigned(std::min<int64_t>(n_tasks, int64_t(cus) * per));
+            };
+            switch (p) {
+                case Prec::F64: {
+                    const void* fn = reinterpret_cast<const void*>(&persistent_gemm<0, ROLE>);
+                    hipLaunchKernelGGL((persistent_gemm<0, ROLE>), dim3(grid(fn)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                    break;
+                }
+                case Prec::F32: {
+                    const void* fn = reinterpret_cast<const void*>(&persistent_gemm<1, ROLE>);
+                    hipLaunchKernelGGL((persistent_gemm<1, ROLE>), dim3(grid(fn)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                    break;
+                }
+                case Prec::BF16: {
+                    const void* fn = reinterpret_cast<const void*>(&persistent_gemm<2, ROLE>);
+                    hipLaunchKernelGGL((persistent_gemm<2, ROLE>), dim3(grid(fn)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                    break;
+                }
+            }
+        } else if (var == 1)
             launch_gemm_tile<ROLE, 64, 1>(p, tasks, n_tasks, terms, b, act, s, xcd);
         else if (var == 2)
             launch_gemm_tile<ROLE, 64, 2>(p, tasks, n_tasks, terms, b, act, s, xcd);
