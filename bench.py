@@ -2,9 +2,10 @@
 """Benchmark of the two-site DMRG hot path on one MI355X.
 
 Workload (default): the K=36, N=36, M=1024 chain molecule (integral seed
-1003).  Setup, untimed: build the MPO, draw the random initial MPS, move the
-center to the middle pair (17, 18) by exact SVD splits, run the warm-up
-steps.  A timed step is one complete two-site DMRG step at the middle bond:
+1003).  Setup, untimed: build the MPO, draw the random initial MPS, run
+--presweeps full sweeps (default 2) so that the state has the sector
+structure of a production sweep, move the center to the middle pair
+(17, 18) by exact SVD splits, run the warm-up steps.  A timed step is one complete two-site DMRG step at the middle bond:
 blocking of the renormalized operators, Davidson with the sigma vector,
 sector-wise SVD truncation to M, environment update and the next guess.
 Steps alternate between the pairs (17, 18) forward and (18, 19) backward, so
@@ -28,7 +29,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA, TFLOP/s
 
 
-def recorded_traffic(prec, steps, warmup):
+def recorded_traffic(prec, steps, warmup, presweeps):
     """HBM bytes per sigma launch from the committed rocprofv3 counter summary,
     only while the kernel source is the one the counters were taken on and the
     run is the recorded one; otherwise None."""
@@ -43,7 +44,8 @@ def recorded_traffic(prec, steps, warmup):
         if line.startswith("machine-readable:"):
             rec = json.loads(line.split(":", 1)[1])
     if (rec is None or rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest()
-            or prec != "fp64" or rec.get("steps") != steps or rec.get("warmup") != warmup):
+            or prec != "fp64" or rec.get("steps") != steps or rec.get("warmup") != warmup
+            or rec.get("presweeps", 0) != presweeps):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -193,6 +195,81 @@ def batched(args, P, torch):
     print(json.dumps(out), flush=True)
 
 
+def precision_check(args, P, mps, pre_e):
+    """The same two-site eigenproblem (middle pair, state after the
+    presweeps) solved from the same start vector in every precision."""
+    psi0 = mps.psi()
+    rows = {}
+    for name, prec, refine in (("fp64", P.DMRG_FP64, 0.0), ("fp32_refined", P.DMRG_FP32, 1e-4),
+                               ("bf16_refined", P.DMRG_BF16, 1e-4), ("fp32_only", P.DMRG_FP32, 0.0),
+                               ("bf16_only", P.DMRG_BF16, 0.0)):
+        mps.set_psi(psi0)
+        o = P.default_opts(prec=prec, dav_tol=1e-8, dav_max_iter=60, refine_tol=refine)
+        t0 = time.time()
+        th, rn, st = mps.solve(o)
+        rows[name] = {"theta": th, "rnorm": rn, "iters": st["dav_iters"], "sigma_calls": st["sigma_calls"],
+                      "sigma_seconds": st["sigma_seconds"], "seconds": time.time() - t0,
+                      "sigma_tflops": st["sigma_flops"] / max(st["sigma_seconds"], 1e-30) / 1e12}
+        log("%-13s theta %.12f |r| %.2e iters %d sigma %.3fs" % (name, th, rn, st["dav_iters"], st["sigma_seconds"]))
+    ref = rows["fp64"]["theta"]
+    for r in rows.values():
+        r["abs_dtheta_vs_fp64"] = abs(r["theta"] - ref)
+        r["speedup_vs_fp64"] = rows["fp64"]["seconds"] / r["seconds"]
+    print(json.dumps({"mode": "precision_check", "workload": "K=36 M=1024 middle pair after %d FP64 sweeps"
+                      % args.presweeps, "presweep_energy": pre_e, "psi_elements": int(psi0.size),
+                      "davidson_tol": 1e-8, "davidson_max_iter": 60, "runs": rows}), flush=True)
+
+
+def learned(args, P, torch):
+    """Learned vs diagonal Davidson preconditioner: both runs start from the
+    same random state; the learned run collects samples during the first
+    sweeps (diagonal preconditioner), trains, then continues with the learned
+    correction; the reference continues with the diagonal one."""
+    from workloads import CONFIGS, config_integrals, mps_values
+    cfg, n_col, n_cmp = (int(x) for x in args.learned.split(","))
+    c = CONFIGS[cfg]
+    K, M = c["K"], c["M"]
+    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
+    ctx = P.Context(0)
+    I = config_integrals(cfg)
+    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
+    vals = mps_values(c["seed"], mpo.n_values(M))
+    net = P.Mlp(ctx, seed=7, capacity=1 << 22)
+    kw = dict(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
+              refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    out = {"mode": "learned", "workload": cfg, "K": K, "M": M, "precision": args.prec,
+           "collect_sweeps": n_col, "compare_sweeps": n_cmp}
+    runs = {}
+    for mode in ("diagonal", "learned"):
+        m = P.Mps.random(ctx, mpo, M, vals)
+        o = P.default_opts(collect=1 if mode == "learned" else 0, mlp=net if mode == "learned" else None, **kw)
+        t0 = time.time()
+        st, _ = m.sweep(M, n_col, o)
+        log("%s: %d sweeps %.1fs E %.10f" % (mode, n_col, time.time() - t0, st[-1]["energy"]))
+        if mode == "learned":
+            t1 = time.time()
+            ns = net.dataset(fetch=False)
+            l0 = net.train(1, 4096, 1e-3, 11)
+            loss = net.train(args.train_epochs, 4096, 1e-3, 12)
+            out["training"] = {"samples": ns, "epochs": 1 + args.train_epochs, "loss_first_epoch": l0,
+                               "loss_last_epoch": loss, "seconds": time.time() - t1}
+            log("trained on %d samples: loss %.4f -> %.4f (%.1fs)" % (ns, l0, loss, out["training"]["seconds"]))
+            o = P.default_opts(precond=1, mlp=net, **kw)
+        t2 = time.time()
+        st2, _ = m.sweep(M, n_cmp, o)
+        runs[mode] = {"seconds": time.time() - t2, "sweep_seconds": [x["seconds"] for x in st2],
+                      "dav_iters": [x["dav_iters"] for x in st2], "energies": [x["energy"] for x in st2],
+                      "energy": m.energy(), "fallbacks": sum(x["precond_fallbacks"] for x in st2)}
+        log("%s: compare sweeps %.1fs iters %s E %.10f" % (mode, runs[mode]["seconds"], runs[mode]["dav_iters"],
+                                                           runs[mode]["energy"]))
+        del m
+    out["runs"] = runs
+    out["iteration_ratio"] = sum(runs["learned"]["dav_iters"]) / max(1, sum(runs["diagonal"]["dav_iters"]))
+    out["time_ratio"] = runs["learned"]["seconds"] / runs["diagonal"]["seconds"]
+    out["abs_dE"] = abs(runs["learned"]["energy"] - runs["diagonal"]["energy"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,8 +286,19 @@ def main():
                     help="instead of middle steps: the first N instances of the 64-molecule batch "
                          "(K 12-24, M 128-512), --sweeps sweeps (default 1) sequential FP64, sequential "
                          "FP32 and batched FP32; energies and speedups")
+    ap.add_argument("--learned", default="",
+                    help="instead of middle steps: 'cfg,collect,compare' e.g. '2,3,3': sweeps with the "
+                         "diagonal preconditioner collecting training samples, training, then "
+                         "`compare` sweeps learned vs diagonal from the same state")
+    ap.add_argument("--precision-check", action="store_true",
+                    help="instead of middle steps: after the presweeps, solve the middle two-site "
+                         "problem from the same start vector in FP64, FP32 and BF16 (with and without "
+                         "the FP64 refinement) and compare eigenvalues and sigma time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
+    ap.add_argument("--train-epochs", type=int, default=30)
+    ap.add_argument("--presweeps", type=int, default=2,
+                    help="untimed full sweeps from the random state before the timed middle steps")
     ap.add_argument("--calib", action="store_true",
                     help="run a 256 MiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -234,6 +322,8 @@ def main():
         del src, dst
     if args.batched:
         return batched(args, P, torch)
+    if args.learned:
+        return learned(args, P, torch)
     c = CONFIGS[3]
     K, M = c["K"], c["M"]
     ctx = P.Context(0)
@@ -243,12 +333,21 @@ def main():
     n = mpo.n_values(M)
     mps = P.Mps.random(ctx, mpo, M, mps_values(c["seed"], n))
     j = K // 2 - 1
+    opts = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
+                          refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    pre_e = None
+    if not args.sweeps and args.presweeps:
+        # untimed: bring the random state close to the ground state first, so
+        # that the timed steps see the sector structure of a production sweep
+        st, _ = mps.sweep(M, args.presweeps, opts)
+        pre_e = st[-1]["energy"]
+        log("presweeps %d: E %.10f (%.1fs)" % (args.presweeps, pre_e, time.time() - t0))
     for _ in range(0 if args.sweeps else j):
         mps.move(True)
     log("setup %.1fs: center %d, psi %d, D_mid %d" % (time.time() - t0, mps.center(), mps.psi_size(),
                                                       mpo.bond_dims()[j + 1]))
-    opts = P.default_opts(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
-                          refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
+    if args.precision_check:
+        return precision_check(args, P, mps, pre_e)
     if args.sweeps:
         return full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t0)
     fwd = True
@@ -291,8 +390,9 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "chain molecule K=36 N=36 2Sz=0 M=1024 (integral seed 1003), "
-                               "two-site steps at the middle bond",
+                               "two-site steps at the middle bond after %d untimed sweeps" % args.presweeps,
                    "K": K, "M": M, "D_mid": int(mpo.bond_dims()[j + 1]), "psi_elements": mps.psi_size(),
+                   "presweeps": args.presweeps, "presweep_energy": pre_e,
                    "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
                    "precision": args.prec},
         "sigma_calls": tot["calls"],
@@ -301,7 +401,7 @@ def main():
         "thetas": thetas,
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK[args.prec],
                      "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec],
-                     "traffic": recorded_traffic(args.prec, args.steps, args.warmup),
+                     "traffic": recorded_traffic(args.prec, args.steps, args.warmup, args.presweeps),
                      "kernel": "grouped_gemm<%d,1>" % prec,
                      "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
                      "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},

@@ -218,6 +218,15 @@ void dmrg_sweep_opts_default(dmrg_sweep_opts* o);
 dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
                        int n_sweeps, const dmrg_sweep_opts* opts, dmrg_sweep_stat* stats,
                        double* thetas);
+/* Replace the two-site vector at the current center (host, psi_size values,
+ * layout of dmrg_psi_export); DMRG_E_INVAL on non-finite values. */
+dmrg_status dmrg_psi_import(dmrg_ctx* ctx, dmrg_mps* mps, const double* psi_host);
+/* Davidson at the current center only (Sec. 2.1, "solving"): the two-site
+ * vector becomes the lowest eigenvector of the effective Hamiltonian of
+ * Eq. Hpartition, starting from the current one; no truncation, the center
+ * stays.  theta, rnorm (may be NULL): eigenvalue and final residual norm. */
+dmrg_status dmrg_solve(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const dmrg_sweep_opts* opts,
+                       double* theta, double* rnorm, dmrg_sweep_stat* stat);
 /* One two-site step at the current center (forward = 1 moves right). */
 dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
                       const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat);
@@ -238,6 +247,32 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps,
  * two-site vector is split exactly by SVD (singular values <= 1e-14 sigma_max
  * dropped) and the environment on the side left behind is updated. */
 dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward);
+/* ---- launch autotuner -----------------------------------------------------
+ *
+ * The sigma passes have a launch configuration: output tile edge of each
+ * pass (64: workgroup tiles through LDS; 32: one task per wave), target
+ * number of split-K pieces of the second pass, and the grouped-GEMM variant
+ * of tile-64 passes (0 plain, 1 packed K-steps, 2 software pipeline, 3
+ * persistent pipeline).  A process-wide tuning table maps a state's shape
+ * (K, bond dimension rounded up to a power of two, distance of the pair
+ * from the nearer end in power-of-two buckets) to a configuration; states
+ * without an entry use tile 64/64, 16384 pieces, variant 2.  Batched sweeps
+ * use the first instance's configuration for the whole batch. */
+/* Time every candidate configuration on `reps` sigma applications (after
+ * one warm-up) at the current center in precision prec, store the fastest
+ * in the table under this state's shape and use it.  report (caller-owned,
+ * may be NULL): JSON with the key, every candidate's average ms and the
+ * best; DMRG_E_INVAL if report_cap is too small. */
+dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmrg_prec prec, int reps,
+                          char* report, int64_t report_cap);
+/* The tuning table as JSON {"key": {"tile1": .., "tile2": .., "pieces": ..,
+ * "variant": ..}, ...}; *needed = bytes including the terminating zero; out
+ * may be NULL (size query). */
+dmrg_status dmrg_tune_table(char* out, int64_t cap, int64_t* needed);
+/* Merge the entries of a JSON table in that format (DMRG_E_INVAL if
+ * malformed or out of range; the table is then unchanged). */
+dmrg_status dmrg_tune_table_load(const char* json);
+
 /* ---- learned Davidson preconditioner --------------------------------------
  *
  * Not part of the paper, whose solver is left open (Sec. 2.1, "solving"): an

@@ -74,6 +74,12 @@ SIGNATURES = {
     "dmrg_mps_move": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "dmrg_sweep_batched": (c_int, [c_void_p, c_int, P(c_void_p), P(c_void_p), P(c_int), c_int,
                                    P(SweepOpts), P(SweepStat), P(c_double)]),
+    "dmrg_psi_import": (c_int, [c_void_p, c_void_p, P(c_double)]),
+    "dmrg_solve": (c_int, [c_void_p, c_void_p, c_void_p, P(SweepOpts), P(c_double), P(c_double),
+                           P(SweepStat)]),
+    "dmrg_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_char_p, c_int64]),
+    "dmrg_tune_table": (c_int, [c_char_p, c_int64, P(c_int64)]),
+    "dmrg_tune_table_load": (c_int, [c_char_p]),
     "dmrg_mlp_create": (c_int, [c_void_p, P(C.c_float), C.c_uint64, c_int64, P(c_void_p)]),
     "dmrg_mlp_free": (None, [c_void_p]),
     "dmrg_mlp_params": (c_int, [c_void_p, c_void_p, P(C.c_float)]),

@@ -235,6 +235,19 @@ class Mps:
                                           C.byref(opts), C.byref(th), C.byref(st)))
         return th.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
 
+    def set_psi(self, psi):
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        assert psi.size == self.psi_size()
+        self.ctx.check(self.lib.dmrg_psi_import(self.ctx.h, self.h, psi.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def solve(self, opts=None):
+        """Davidson at the current center (no truncation); (theta, |r|, stats)."""
+        opts = opts or default_opts()
+        th, rn, st = C.c_double(), C.c_double(), L.SweepStat()
+        self.ctx.check(self.lib.dmrg_solve(self.ctx.h, self.h, self.mpo.h, C.byref(opts), C.byref(th),
+                                           C.byref(rn), C.byref(st)))
+        return th.value, rn.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
+
     def move(self, forward=True):
         self.ctx.check(self.lib.dmrg_mps_move(self.ctx.h, self.h, self.mpo.h, int(bool(forward))))
 
@@ -247,6 +260,34 @@ class Mps:
         if getattr(self, "h", None):
             self.lib.dmrg_mps_free(self.h)
             self.h = None
+
+
+def autotune(ctx, mps, prec=L.DMRG_FP64, reps=3):
+    """Time the sigma launch configurations at the current center; the best
+    goes into the tuning table (dmrg_autotune). Returns the report dict."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    ctx.check(ctx.lib.dmrg_autotune(ctx.h, mps.h, mps.mpo.h, prec, reps, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def tune_table():
+    import json
+    lib = L.load()
+    need = C.c_int64()
+    st = lib.dmrg_tune_table(None, 0, C.byref(need))
+    buf = C.create_string_buffer(need.value)
+    st = lib.dmrg_tune_table(buf, need.value, C.byref(need))
+    if st != 0:
+        raise DmrgError(st, "dmrg_tune_table failed")
+    return json.loads(buf.value.decode())
+
+
+def tune_table_load(table):
+    import json
+    st = L.load().dmrg_tune_table_load(json.dumps(table).encode())
+    if st != 0:
+        raise DmrgError(st, "malformed tuning table")
 
 
 class Mlp:

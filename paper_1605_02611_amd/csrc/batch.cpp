@@ -67,10 +67,13 @@ struct BatchSigma {
         htab[0].assign(size_t(8) * nb, nullptr);
         p1.tile = st[0]->pass1.tile;
         p2.tile = st[0]->pass2.tile;
+        p1.variant = st[0]->pass1.variant;
+        p2.variant = st[0]->pass2.variant;
         for (int b = 0; b < nb; ++b) {
             State& S = *st[b];
-            require(S.pass1.tile == p1.tile && S.pass2.tile == p2.tile,
-                    "batched sigma: instances with different tile edges", E_STATE);
+            require(S.pass1.tile == p1.tile && S.pass2.tile == p2.tile && S.pass1.variant == p1.variant &&
+                        S.pass2.variant == p2.variant,
+                    "batched sigma: instances with different launch configurations", E_STATE);
             merge(p1, S.pass1, b, r1);
             merge(p2, S.pass2, b, r2);
             flops[b] = S.pass1.model_flops + S.pass2.model_flops;
@@ -184,6 +187,19 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                 E_STATE);
         nsteps[b] = 2 * (st[b]->mpo->K - 1);
         tmax = std::max(tmax, nsteps[b]);
+    }
+    // one launch configuration for the whole batch: the first instance's
+    // (its own setting, or the tuning table's entry for its shape)
+    {
+        SigmaConfig common = st[0]->cfg;
+        if (!st[0]->cfg_explicit) tune_lookup(st[0]->tune_key(), common);
+        for (State* S : st) {
+            if (S->cfg.tile1 != common.tile1 || S->cfg.tile2 != common.tile2 || S->cfg.variant != common.variant ||
+                S->cfg.pieces != common.pieces)
+                S->invalidate();
+            S->cfg = common;
+            S->cfg_explicit = true;
+        }
     }
     stats.assign(nb, std::vector<StepStats>(n_sweeps));
     seconds.assign(nb, std::vector<double>(n_sweeps, 0.0));

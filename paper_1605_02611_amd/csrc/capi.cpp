@@ -2,6 +2,7 @@
 // catches internal errors, stores the message on the context and returns a
 // status code.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 
 #include "../../include/dmrg.h"
@@ -320,6 +321,36 @@ dmrg_status dmrg_psi_export(dmrg_ctx* ctx, const dmrg_mps* mps, double* psi_host
     });
 }
 
+dmrg_status dmrg_psi_import(dmrg_ctx* ctx, dmrg_mps* mps, const double* psi_host) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && psi_host, "null argument");
+        use_device(ctx->c);
+        State& st = *mps->st;
+        for (int64_t i = 0; i < st.ts.n; ++i) require(std::isfinite(psi_host[i]), "non-finite two-site vector");
+        DMRG_HIP(hipMemcpyAsync(st.psi.p, psi_host, st.ts.n * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+    });
+}
+
+dmrg_status dmrg_solve(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const dmrg_sweep_opts* opts,
+                       double* theta, double* rnorm, dmrg_sweep_stat* stat) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        use_device(ctx->c);
+        SweepOpts o = to_opts(opts);
+        StepStats s;
+        auto t0 = std::chrono::steady_clock::now();
+        const DavOut dv = mps->st->solve(o, s);
+        auto t1 = std::chrono::steady_clock::now();
+        if (theta) *theta = dv.theta;
+        if (rnorm) *rnorm = dv.rnorm;
+        if (stat) fill_stat(*stat, s, dv.theta, std::chrono::duration<double>(t1 - t0).count(), 0);
+    });
+}
+
 dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
                        double* out, dmrg_prec prec, double* flops) {
     if (!ctx) return DMRG_E_INVAL;
@@ -513,6 +544,93 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps, const
                     fill_stat(stats[size_t(b) * n_sweeps + sw], x, x.theta, secs[b][sw], 2 * (mpo[b]->m->K - 1));
                 }
     });
+}
+
+// ---- autotuner -------------------------------------------------------------------
+
+dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmrg_prec prec, int reps,
+                          char* report, int64_t report_cap) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16 && reps >= 1, "bad autotune arguments");
+        use_device(ctx->c);
+        State& st = *mps->st;
+        hipStream_t s = ctx->c.stream;
+        std::vector<SigmaConfig> cand;
+        for (int t1 : {64, 32})
+            for (int t2 : {64, 32})
+                for (double pc : {4096.0, 16384.0, 65536.0})
+                    for (int v : {0, 2}) {
+                        if (t1 == 32 && t2 == 32 && v != 0) continue;  // the variant applies to tile-64 passes
+                        SigmaConfig c;
+                        c.tile1 = t1;
+                        c.tile2 = t2;
+                        c.pieces = pc;
+                        c.variant = v;
+                        cand.push_back(c);
+                    }
+        st.prepare();
+        const int64_t n = st.ts.n;
+        DevBuf y(std::max<int64_t>(1, n) * sizeof(double), s);
+        const double* x = st.psi.as<double>();
+        std::string rep = "{\"key\": \"" + st.tune_key() + "\", \"candidates\": [";
+        double best_t = 1e300;
+        SigmaConfig best;
+        for (size_t i = 0; i < cand.size(); ++i) {
+            st.cfg = cand[i];
+            st.cfg_explicit = true;
+            st.invalidate();
+            st.prepare();
+            st.sigma(x, y.as<double>(), Prec(prec), nullptr);  // warm-up
+            StepStats ss;
+            for (int r = 0; r < reps; ++r) st.sigma(x, y.as<double>(), Prec(prec), &ss);
+            const double t = ss.sigma_seconds / reps;
+            char buf[200];
+            std::snprintf(buf, sizeof buf, "%s{\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"ms\": %.4f}",
+                          i ? ", " : "", cand[i].tile1, cand[i].tile2, cand[i].pieces, cand[i].variant, t * 1e3);
+            rep += buf;
+            if (t < best_t) {
+                best_t = t;
+                best = cand[i];
+            }
+        }
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "], \"best\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"ms\": %.4f}}",
+                      best.tile1, best.tile2, best.pieces, best.variant, best_t * 1e3);
+        rep += buf;
+        tune_store(st.tune_key(), best);
+        st.cfg = best;
+        st.cfg_explicit = false;
+        st.invalidate();
+        st.prepare();
+        if (report) {
+            require(report_cap > int64_t(rep.size()), "autotune report buffer too small", E_INVAL);
+            std::memcpy(report, rep.c_str(), rep.size() + 1);
+        }
+    });
+}
+
+dmrg_status dmrg_tune_table(char* out, int64_t cap, int64_t* needed) {
+    const std::string js = tune_dump();
+    if (needed) *needed = int64_t(js.size()) + 1;
+    if (!out) return DMRG_OK;
+    if (cap < int64_t(js.size()) + 1) return DMRG_E_INVAL;
+    std::memcpy(out, js.c_str(), js.size() + 1);
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_tune_table_load(const char* json) {
+    if (!json) return DMRG_E_INVAL;
+    try {
+        tune_load(json);
+    } catch (const Error&) {
+        return DMRG_E_INVAL;
+    } catch (...) {
+        return DMRG_E_INVAL;
+    }
+    return DMRG_OK;
 }
 
 // ---- learned preconditioner ---------------------------------------------------

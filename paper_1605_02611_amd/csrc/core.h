@@ -178,12 +178,22 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 // bases: DEVICE array of buffer base pointers indexed by the buffer ids of
 // the tasks and terms; active: DEVICE flags per instance or nullptr
-// tile: output tile edge of every task (64 or 32)
+// tile: output tile edge of every task (64 or 32); variant (tile 64): 0
+// plain, 1 packed K-steps, 2 software pipeline, 3 persistent pipeline, -1
+// the process default (2, or DMRG_GEMM_VARIANT)
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* bases, const int* active, hipStream_t s, int tile = kTile);
+                 void* const* bases, const int* active, hipStream_t s, int tile = kTile, int variant = -1);
 // same kernel, separate symbol for the two passes of the sigma vector
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* bases, const int* active, hipStream_t s, int tile = kTile);
+                       void* const* bases, const int* active, hipStream_t s, int tile = kTile,
+                       int variant = -1);
+
+// Launch configuration of the two sigma passes (chosen by the autotuner).
+struct SigmaConfig {
+    int tile1 = kTile, tile2 = kTile;  // output tile edges of pass 1 and pass 2
+    double pieces = 16384;             // target split-K pieces of pass 2
+    int variant = -1;                  // grouped-GEMM variant of the tile-64 passes
+};
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]
 struct SumItem {

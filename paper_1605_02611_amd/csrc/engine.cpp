@@ -8,6 +8,8 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cctype>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -146,10 +148,10 @@ void GemmList::launch(Prec p, const Bases& b, hipStream_t s) {
 void GemmList::launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const {
     if (sigma_role)
         launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                          dev_bases, active, s, tile);
+                          dev_bases, active, s, tile, variant);
     else
         launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                    dev_bases, active, s, tile);
+                    dev_bases, active, s, tile, variant);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
@@ -1223,7 +1225,9 @@ void State::prepare() {
         }
     }
     pass1.clear();
-    pass1.tile = tile_pass[0];
+    if (!cfg_explicit) tune_lookup(tune_key(), cfg);
+    pass1.tile = cfg.tile1;
+    pass1.variant = cfg.variant;
     std::vector<UTerm> terms;
     for (int y = 0; y < nch; ++y) {
         const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
@@ -1255,7 +1259,8 @@ void State::prepare() {
     }
     // sigma_q' [:, (t', Q'_r)] = sum_y sum_t T_y(q)[:, (t, Q_r)] Z_(y,t',t)^T
     pass2.clear();
-    pass2.tile = tile_pass[1];
+    pass2.tile = cfg.tile2;
+    pass2.variant = cfg.variant;
     std::vector<int> unit_base(nq + 1, 0);
     for (int iq2 = 0; iq2 < nq; ++iq2) unit_base[iq2 + 1] = unit_base[iq2] + int(ts.env[iq2].segs.size());
     std::vector<std::vector<UTerm>> uterms(unit_base[nq]);
@@ -1303,7 +1308,7 @@ void State::prepare() {
             work += double(tu[u]) * ku[u];
         }
     constexpr int kMaxSplits = 32;
-    const double k_target = std::max(64.0, work / sigma_pieces);
+    const double k_target = std::max(64.0, work / cfg.pieces);
     std::vector<int> su(unit_base[nq], 1);
     splits = 1;
     for (size_t u = 0; u < su.size(); ++u) {
@@ -1666,13 +1671,14 @@ bool DavSolver::advance() {
         // low-precision phase done: restart from the Ritz vector in FP64
         prec_ = Prec::F64;
         refined_ = true;
+        iter0_ = napply_;
         launch_copy(Vp, xr_.as<double>(), n, s_);
         req_ = 0;
         first_ = true;
         return true;
     }
     const bool low = !refined_ && o_.refine_tol > 0;
-    if ((rn <= o_.dav_tol && !low) || napply_ >= o_.dav_max_iter) {
+    if ((rn <= o_.dav_tol && !low) || napply_ - iter0_ >= o_.dav_max_iter) {
         finish();
         return false;
     }
@@ -1744,6 +1750,15 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
 }
 
 }  // namespace
+
+DavOut State::solve(const SweepOpts& o, StepStats& stt) {
+    prepare();
+    build_diag();
+    const DavOut dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
+    stt.theta = dv.theta;
+    stt.dav_iters += dv.iters;
+    return dv;
+}
 
 double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool solve) {
     const int K = mpo->K;
@@ -1976,6 +1991,121 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
                 tb + td + tv + sec(t3, t5));
     }
     return dv.theta;
+}
+
+// ---------------------------------------------------------------------------
+// tuning table
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, SigmaConfig>& tune_table() {
+    static std::map<std::string, SigmaConfig> t;
+    return t;
+}
+}  // namespace
+
+std::string State::tune_key() const {
+    // K, the bond dimension rounded up to a power of two, and the pair's
+    // distance from the nearer end (sites 0-1, 2-3, 4-7, ... buckets)
+    int mb = 1;
+    for (const BondL& b : bonds) mb = std::max(mb, b.total);
+    int m2 = 1;
+    while (m2 < mb) m2 <<= 1;
+    const int d = std::min(center, mpo->K - 2 - center);
+    int db = 0;
+    while ((1 << (db + 1)) <= d + 1) ++db;
+    return "K" + std::to_string(mpo->K) + "_M" + std::to_string(m2) + "_d" + std::to_string(db);
+}
+
+bool tune_lookup(const std::string& key, SigmaConfig& out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = tune_table().find(key);
+    if (it == tune_table().end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, const SigmaConfig& c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_table()[key] = c;
+}
+
+std::string tune_dump() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string out = "{";
+    bool first = true;
+    for (auto& [k, c] : tune_table()) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "%s\"%s\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.17g, \"variant\": %d}",
+                      first ? "" : ", ", k.c_str(), c.tile1, c.tile2, c.pieces, c.variant);
+        out += buf;
+        first = false;
+    }
+    return out + "}";
+}
+
+// Reads the format tune_dump writes: {"key": {"tile1": a, "tile2": b, "pieces": p, "variant": v}, ...}
+void tune_load(const std::string& js) {
+    size_t pos = 0;
+    auto expect = [&](char ch) {
+        while (pos < js.size() && std::isspace(static_cast<unsigned char>(js[pos]))) ++pos;
+        require(pos < js.size() && js[pos] == ch, "tuning table: malformed JSON");
+        ++pos;
+    };
+    auto peek = [&]() {
+        while (pos < js.size() && std::isspace(static_cast<unsigned char>(js[pos]))) ++pos;
+        return pos < js.size() ? js[pos] : '\0';
+    };
+    auto str = [&]() {
+        expect('"');
+        const size_t e = js.find('"', pos);
+        require(e != std::string::npos, "tuning table: malformed JSON");
+        std::string v = js.substr(pos, e - pos);
+        pos = e + 1;
+        return v;
+    };
+    auto num = [&]() {
+        while (pos < js.size() && std::isspace(static_cast<unsigned char>(js[pos]))) ++pos;
+        char* end = nullptr;
+        const double v = std::strtod(js.c_str() + pos, &end);
+        require(end && end != js.c_str() + pos, "tuning table: malformed number");
+        pos = size_t(end - js.c_str());
+        return v;
+    };
+    std::map<std::string, SigmaConfig> add;
+    expect('{');
+    if (peek() != '}') {
+        while (true) {
+            const std::string key = str();
+            expect(':');
+            expect('{');
+            SigmaConfig c;
+            while (true) {
+                const std::string f = str();
+                expect(':');
+                const double v = num();
+                if (f == "tile1") c.tile1 = int(v);
+                else if (f == "tile2") c.tile2 = int(v);
+                else if (f == "pieces") c.pieces = v;
+                else if (f == "variant") c.variant = int(v);
+                else require(false, "tuning table: unknown field " + f);
+                if (peek() == ',') { ++pos; continue; }
+                expect('}');
+                break;
+            }
+            require((c.tile1 == 32 || c.tile1 == 64) && (c.tile2 == 32 || c.tile2 == 64) && c.pieces >= 256 &&
+                        c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 3,
+                    "tuning table: configuration out of range");
+            add[key] = c;
+            if (peek() == ',') { ++pos; continue; }
+            expect('}');
+            break;
+        }
+    } else {
+        expect('}');
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& [k, c] : add) tune_table()[k] = c;
 }
 
 double State::energy() {

@@ -143,6 +143,7 @@ struct GemmList {
     }
     bool sigma_role = false;  // launch under the sigma-vector kernel symbol
     int tile = kTile;         // output tile edge of the tasks (64 or 32)
+    int variant = -1;         // grouped-GEMM variant (-1: process default)
     DevBuf dbases;            // device copy of the buffer table
     Bases hbases{};           // host copy (kept alive for the async upload)
     void upload(hipStream_t s);
@@ -245,6 +246,7 @@ class DavSolver {
     StepStats& stats_;
     hipStream_t s_;
     int ms_ = 24, keep_ = 4, k_ = 0, req_ = 0, napply_ = 0;
+    int iter0_ = 0;  // applications before the FP64 refinement phase (which gets its own budget)
     bool first_ = true, refined_ = true, done_ = false;
     Prec prec_ = Prec::F64;
     DevBuf V_, W_, r_, t_, xr_, wr_, scr_, part_, dout_;
@@ -267,13 +269,17 @@ class State {
         if (const char* e = std::getenv("DMRG_SIGMA_TILES")) {
             int a = 0, b = 0;
             if (std::sscanf(e, "%d,%d", &a, &b) == 2 && (a == 32 || a == 64) && (b == 32 || b == 64)) {
-                tile_pass[0] = a;
-                tile_pass[1] = b;
+                cfg.tile1 = a;
+                cfg.tile2 = b;
+                cfg_explicit = true;
             }
         }
         if (const char* e = std::getenv("DMRG_SIGMA_PIECES")) {
             const double v = std::atof(e);
-            if (v >= 256 && v <= 1e7) sigma_pieces = v;
+            if (v >= 256 && v <= 1e7) {
+                cfg.pieces = v;
+                cfg_explicit = true;
+            }
         }
     }
     Ctx* ctx;
@@ -292,8 +298,10 @@ class State {
     std::vector<int64_t> t_off;  // T_y(q) offsets, [y * nq + iq], -1 if absent
     int64_t t_total = 0;
     int splits = 1;
-    int tile_pass[2] = {kTile, kTile};  // output tile edge of the two sigma passes
-    double sigma_pieces = 16384;        // target workgroups (split-K pieces) of pass 2
+    SigmaConfig cfg;            // launch configuration of the sigma passes
+    bool cfg_explicit = false;  // set by the caller / autotuner (else the tuning table decides)
+    std::string tune_key() const;  // key of this state's shape in the tuning table
+    void invalidate() { prepared = false; }
     DevBuf tbuf, part, psi32, sig32, tbuf32, part32;
     DevBuf diag;
     bool diag_ok = false;
@@ -321,6 +329,9 @@ class State {
     void sigma(const double* x, double* y, Prec p, StepStats* st);
     void build_diag();
     double step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve = true);
+    // Davidson at the current center only: psi becomes the lowest eigenvector
+    // of the effective Hamiltonian; no truncation, the center stays
+    DavOut solve(const SweepOpts& o, StepStats& st);
     double finish_step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve,
                        const DavOut& dv, double tb, double td, double tv, double sig0);
     double energy();
@@ -339,6 +350,11 @@ class State {
 };
 
 // Lockstep sweeps of independent instances with batched sigma launches.
+// Process-wide tuning table: shape key -> sigma configuration.
+bool tune_lookup(const std::string& key, SigmaConfig& out);
+void tune_store(const std::string& key, const SigmaConfig& c);
+std::string tune_dump();                  // JSON object
+void tune_load(const std::string& json);  // merge entries of a JSON object
 void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M, int n_sweeps,
                    const SweepOpts& o, std::vector<std::vector<StepStats>>& stats,
                    std::vector<std::vector<double>>& seconds, double* batch_sigma_seconds);

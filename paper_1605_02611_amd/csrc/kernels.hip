@@ -1157,10 +1157,12 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 
 template <int ROLE>
 static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                             void* const* b, const int* act, int tile, hipStream_t s) {
+                             void* const* b, const int* act, int tile, hipStream_t s, int variant) {
     if (n_tasks <= 0) return;
     require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
-    static const int var = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
+    static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
+    const int var = variant >= 0 ? variant : var_env;
+    require(var >= 0 && var <= 3, "grouped GEMM: unknown variant");
     if (tile == 64) {
         if (var == 3) {
             // persistent workgroups: as many as are resident at once
@@ -1223,12 +1225,12 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 }
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* b, const int* act, hipStream_t s, int tile) {
-    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s);
+                 void* const* b, const int* act, hipStream_t s, int tile, int variant) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s, variant);
 }
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* b, const int* act, hipStream_t s, int tile) {
-    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s);
+                       void* const* b, const int* act, hipStream_t s, int tile, int variant) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s, variant);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {

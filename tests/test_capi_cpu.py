@@ -122,3 +122,24 @@ def test_gpu_calls_on_host_context_fail_cleanly(hctx):
     with pytest.raises(P.DmrgError) as e:
         P.Mps.random(hctx, m, 8, np.zeros(n))
     assert e.value.status == 6
+
+
+def test_tuning_table_round_trip_and_validation():
+    base = P.tune_table()
+    entry = {"K99_M1024_d3": {"tile1": 64, "tile2": 32, "pieces": 4096.0, "variant": 2}}
+    P.tune_table_load(entry)
+    t = P.tune_table()
+    assert t["K99_M1024_d3"] == entry["K99_M1024_d3"]
+    for k in base:
+        assert t[k] == base[k]
+    # malformed or out-of-range tables are rejected and change nothing
+    for bad in ({"x": {"tile1": 48, "tile2": 64, "pieces": 4096, "variant": 0}},
+                {"x": {"tile1": 64, "tile2": 64, "pieces": 10, "variant": 0}},
+                {"x": {"tile1": 64, "tile2": 64, "pieces": 4096, "variant": 7}},
+                {"x": {"tile1": 64, "colour": 1}}):
+        with pytest.raises(P.DmrgError):
+            P.tune_table_load(bad)
+    assert P.tune_table() == t
+    lib = _lib.load()
+    assert lib.dmrg_tune_table_load(b"{not json") == 1
+    assert lib.dmrg_tune_table_load(b"{}") == 0

@@ -326,3 +326,33 @@ def test_truncation_with_large_sectors_matches_numpy_svd(ctx):
     th, st = mps.step(M1, True, P.default_opts(dav_max_iter=1))
     assert abs(st["discarded"] - disc) <= 1e-10 * max(disc, 1e-300) + 1e-15
     assert {(a, b): d for a, b, d in mps.bond(j + 1)} == kept
+
+
+def test_autotune_picks_a_configuration_that_gives_the_same_sweeps(ctx):
+    """The autotuner times every candidate launch configuration on real sigma
+    calls; any of them must give the same sigma (same task lists, only the
+    launch shape differs) and the tuned state the same sweep energies."""
+    K, N, M, seed = 8, 8, 24, 52
+    I = chain_integrals(K, n_elec=N, seed=seed)
+    mpo = P.Mpo(ctx, I.h, I.v, N, 0)
+    vals = mps_values(seed, mpo.n_values(M))
+    ref = P.Mps.random(ctx, mpo, M, vals)
+    for _ in range(3):
+        ref.move(True)
+    x = _dev(np.random.default_rng(3).standard_normal(ref.psi_size()))
+    y0 = torch.zeros_like(x)
+    ref.sigma(x, y0)
+    rep = P.autotune(ctx, ref, P.DMRG_FP64, reps=1)
+    _log("autotune", rep["key"], rep["best"])
+    assert len(rep["candidates"]) >= 8 and all(c["ms"] > 0 for c in rep["candidates"])
+    assert P.tune_table()[rep["key"]]["tile1"] == rep["best"]["tile1"]
+    y1 = torch.zeros_like(x)
+    ref.sigma(x, y1)
+    assert torch.allclose(y1, y0, rtol=0, atol=1e-12 * float(y0.abs().max()))
+    a = P.Mps.random(ctx, mpo, M, vals)
+    b = P.Mps.random(ctx, mpo, M, vals)
+    sa, _ = a.sweep(M, 2, P.default_opts(dav_tol=1e-10))
+    P.tune_table_load({k: {"tile1": 32, "tile2": 32, "pieces": 4096, "variant": 0}
+                       for k in ["K8_M32_d0", "K8_M32_d1", "K8_M32_d2"]})
+    sb, _ = b.sweep(M, 2, P.default_opts(dav_tol=1e-10))
+    assert abs(a.energy() - b.energy()) < 1e-10
