@@ -1628,7 +1628,21 @@ bool DavSolver::advance() {
     double* Vp = V();
     double* Wp = W();
     ++napply_;
-    if (first_) {
+    if (rebuild_ > 0) {
+        // FP64 products of the kept Ritz vectors: request the next one, or
+        // rebuild the projected matrix once all are in
+        if (req_ + 1 < rebuild_) {
+            ++req_;
+            return true;
+        }
+        std::fill(G_.begin(), G_.end(), 0.0);
+        for (int b = 0; b < rebuild_; ++b) {
+            const auto& g = dots(Vp, n, rebuild_, Wp + int64_t(b) * n);
+            for (int a = 0; a < rebuild_; ++a) G_[a * ms_ + b] = g[a];
+        }
+        k_ = rebuild_;
+        rebuild_ = 0;
+    } else if (first_) {
         k_ = 1;
         std::fill(G_.begin(), G_.end(), 0.0);
         G_[0] = dots(Vp, 0, 1, Wp)[0];
@@ -1668,13 +1682,22 @@ bool DavSolver::advance() {
     const double u = prec_ == Prec::BF16 ? 0x1p-8 : 0x1p-24;
     if (!refined_ && o_.refine_tol > 0 &&
         (rn <= std::max(o_.refine_tol, 10.0 * u * std::fabs(theta)) || stalled)) {
-        // low-precision phase done: restart from the Ritz vector in FP64
+        // low-precision phase done: continue in FP64 from the `keep` lowest
+        // Ritz vectors (the basis is FP64 already; their H x are recomputed
+        // in FP64 one request at a time before the next Rayleigh-Ritz step)
+        const int kr = std::min(keep_, k);
+        for (int i = 0; i < kr; ++i) {
+            Coefs c{};
+            for (int a = 0; a < k; ++a) c.c[a] = U_[a * k + i];
+            launch_lincomb(scr_.as<double>() + int64_t(i) * n, Vp, n, k, c, n, s_);
+        }
+        for (int i = 0; i < kr; ++i) launch_copy(Vp + int64_t(i) * n, scr_.as<double>() + int64_t(i) * n, n, s_);
         prec_ = Prec::F64;
         refined_ = true;
         iter0_ = napply_;
-        launch_copy(Vp, xr_.as<double>(), n, s_);
+        rebuild_ = kr;
         req_ = 0;
-        first_ = true;
+        first_ = false;
         return true;
     }
     const bool low = !refined_ && o_.refine_tol > 0;

@@ -247,6 +247,7 @@ class DavSolver {
     hipStream_t s_;
     int ms_ = 24, keep_ = 4, k_ = 0, req_ = 0, napply_ = 0;
     int iter0_ = 0;  // applications before the FP64 refinement phase (which gets its own budget)
+    int rebuild_ = 0;  // kept Ritz vectors whose FP64 products are being collected
     bool first_ = true, refined_ = true, done_ = false;
     Prec prec_ = Prec::F64;
     DevBuf V_, W_, r_, t_, xr_, wr_, scr_, part_, dout_;
