@@ -294,6 +294,8 @@ def main():
                     help="instead of middle steps: after the presweeps, solve the middle two-site "
                          "problem from the same start vector in FP64, FP32 and BF16 (with and without "
                          "the FP64 refinement) and compare eigenvalues and sigma time")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the launch autotuner at the middle pair before the timed steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=30)
@@ -348,6 +350,15 @@ def main():
                                                       mpo.bond_dims()[j + 1]))
     if args.precision_check:
         return precision_check(args, P, mps, pre_e)
+    tuned = None
+    if args.autotune:
+        t3 = time.time()
+        rep = P.autotune(ctx, mps, prec, reps=3)
+        tuned = rep["best"]
+        for c in sorted(rep["candidates"], key=lambda c: c["ms"]):
+            log("autotune %s tiles %d/%d pieces %6d variant %d: %.3f ms" % (rep["key"], c["tile1"], c["tile2"],
+                                                                             c["pieces"], c["variant"], c["ms"]))
+        log("autotune %.1fs" % (time.time() - t3))
     if args.sweeps:
         return full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t0)
     fwd = True
@@ -392,7 +403,7 @@ def main():
         "config": {"workload": "chain molecule K=36 N=36 2Sz=0 M=1024 (integral seed 1003), "
                                "two-site steps at the middle bond after %d untimed sweeps" % args.presweeps,
                    "K": K, "M": M, "D_mid": int(mpo.bond_dims()[j + 1]), "psi_elements": mps.psi_size(),
-                   "presweeps": args.presweeps, "presweep_energy": pre_e,
+                   "presweeps": args.presweeps, "presweep_energy": pre_e, "autotuned": tuned,
                    "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
                    "precision": args.prec},
         "sigma_calls": tot["calls"],

@@ -10,13 +10,85 @@
 // device flag array.  This is the parallelism over quantum-number blocks of
 // Sec. 4.3 (ii), extended across molecules, on one GPU.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "engine.h"
 
 namespace dmrg {
 
+OwnCtx::OwnCtx(const Ctx& base) {
+    c.device = base.device;
+    c.max_lds = base.max_lds;
+    DMRG_HIP(hipSetDevice(c.device));
+    DMRG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    c.own_stream = true;
+    DMRG_HIP(hipEventCreate(&c.ev0));
+    DMRG_HIP(hipEventCreate(&c.ev1));
+    DMRG_HIP(hipEventCreate(&c.ev2));
+    DMRG_HIP(hipEventCreate(&c.ev3));
+    if (rocblas_create_handle(&c.blas) != rocblas_status_success) throw Error(E_HIP, "rocblas_create_handle failed");
+    if (rocblas_set_stream(c.blas, c.stream) != rocblas_status_success) throw Error(E_HIP, "rocblas_set_stream failed");
+}
+
+OwnCtx::~OwnCtx() {
+    (void)hipSetDevice(c.device);
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    if (c.blas) rocblas_destroy_handle(c.blas);
+    for (hipEvent_t e : {c.ev0, c.ev1, c.ev2, c.ev3})
+        if (e) (void)hipEventDestroy(e);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+}
+
 namespace {
+
+// f(i) for i < n on up to 16 host threads (the calling thread included);
+// the first exception is rethrown after all threads have joined
+template <class F>
+void parallel_for(int n, int device, F f) {
+    const int nt = std::max(1, std::min({n, 16, int(std::max(1u, std::thread::hardware_concurrency()))}));
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto work = [&]() {
+        (void)hipSetDevice(device);
+        for (int i = next++; i < n; i = next++) {
+            try {
+                f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (std::thread& x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
+// Point every state at its own context for the duration of a batch.
+struct CtxSwap {
+    std::vector<State*> st;
+    std::vector<Ctx*> saved;
+    CtxSwap(const std::vector<State*>& s, const Ctx& base) : st(s) {
+        for (State* x : st) {
+            if (!x->own) x->own = std::make_unique<OwnCtx>(base);
+            saved.push_back(x->ctx);
+            x->ctx = &x->own->c;
+        }
+    }
+    ~CtxSwap() {
+        for (size_t i = 0; i < st.size(); ++i) {
+            (void)hipStreamSynchronize(st[i]->ctx->stream);
+            st[i]->ctx = saved[i];
+        }
+    }
+};
 
 struct BatchSigma {
     hipStream_t s = nullptr;
@@ -105,6 +177,7 @@ struct BatchSigma {
             for (int b = 0; b < nb; ++b) {
                 State& S = *st[b];
                 S.ensure_f32();
+                DMRG_HIP(hipStreamSynchronize(S.ctx->stream));
                 void** t = &htab[1][size_t(8) * b];
                 t[0] = S.Y.buf32.p;
                 t[1] = S.psi32.p;
@@ -204,6 +277,10 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
     stats.assign(nb, std::vector<StepStats>(n_sweeps));
     seconds.assign(nb, std::vector<double>(n_sweeps, 0.0));
     using clk = std::chrono::steady_clock;
+    // the merged sigma launches run on the caller's stream; everything else
+    // of an instance on its own stream, from concurrent host threads
+    CtxSwap swap(st, *ctx);
+    const int dev = ctx->device;
     for (int sw = 0; sw < n_sweeps; ++sw) {
         const auto t0 = clk::now();
         for (int t = 0; t < tmax; ++t) {
@@ -215,17 +292,16 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                     idx.push_back(b);
                 }
             const int na = int(act.size());
-            for (State* S : act) {
-                S->prepare();
-                S->build_diag();
-            }
             std::vector<std::unique_ptr<DavSolver>> ds(na);
             std::vector<DavSolver*> dp(na);
-            for (int a = 0; a < na; ++a) {
+            parallel_for(na, dev, [&](int a) {
+                act[a]->prepare();
+                act[a]->build_diag();
                 ds[a] = std::make_unique<DavSolver>(*act[a], act[a]->psi.as<double>(), act[a]->ts.n, o,
                                                     stats[idx[a]][sw]);
                 dp[a] = ds[a].get();
-            }
+                DMRG_HIP(hipStreamSynchronize(act[a]->ctx->stream));
+            });
             {
                 BatchSigma B;
                 B.build(act, s);
@@ -243,14 +319,23 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                         if (batch_sigma_seconds)
                             *batch_sigma_seconds += std::chrono::duration<double>(clk::now() - tb).count();
                     }
+                    std::vector<int> lv;
                     for (int a = 0; a < na; ++a)
-                        if (live[a] && !dp[a]->advance()) {
+                        if (live[a]) lv.push_back(a);
+                    std::vector<char> more(na, 0);
+                    parallel_for(int(lv.size()), dev, [&](int i) {
+                        const int a = lv[i];
+                        more[a] = dp[a]->advance() ? 1 : 0;
+                        DMRG_HIP(hipStreamSynchronize(act[a]->ctx->stream));
+                    });
+                    for (int a : lv)
+                        if (!more[a]) {
                             live[a] = 0;
                             --nlive;
                         }
                 }
             }
-            for (int a = 0; a < na; ++a) {
+            parallel_for(na, dev, [&](int a) {
                 const int b = idx[a];
                 StepStats& S = stats[b][sw];
                 const DavOut dv = dp[a]->result();
@@ -259,7 +344,8 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                 S.dav_iters += dv.iters;
                 const bool forward = t < nsteps[b] / 2;
                 act[a]->finish_step(M[b], forward, o, S, true, dv, 0, 0, 0, S.sigma_seconds);
-            }
+                DMRG_HIP(hipStreamSynchronize(act[a]->ctx->stream));
+            });
         }
         const double dt = std::chrono::duration<double>(clk::now() - t0).count();
         for (int b = 0; b < nb; ++b) seconds[b][sw] = dt;

@@ -1619,6 +1619,7 @@ void DavSolver::emit_samples() {
     for (int k = 0; k < n_rec_; ++k)
         launch_mlp_targets(psi, urec_.as<double>() + int64_t(k) * n_, c[k], drrec_.as<double>() + size_t(k) * ns_,
                            idx_.as<int>(), ns_, tgt_.as<float>() + size_t(k) * ns_, s_);
+    DMRG_HIP(hipStreamSynchronize(s_));  // the network's stream copies the samples
     stats_.samples += o_.mlp->append(featrec_.as<float>(), tgt_.as<float>(), int64_t(n_rec_) * ns_);
     n_rec_ = 0;
 }

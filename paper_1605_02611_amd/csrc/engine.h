@@ -262,9 +262,21 @@ class DavSolver {
     DevBuf idx_, featrec_, drrec_, urec_, tgt_, featall_, gall_;
 };
 
+// A context of its own (stream, events, library handle) for a state swept
+// in a batch, so that the instances' host-driven phases run concurrently.
+struct OwnCtx {
+    Ctx c;
+    explicit OwnCtx(const Ctx& base);
+    ~OwnCtx();
+    OwnCtx(const OwnCtx&) = delete;
+    OwnCtx& operator=(const OwnCtx&) = delete;
+};
+
 // The MPS with its environments and the current two-site center.
 class State {
   public:
+    // first member: destroyed after every buffer that may live on its stream
+    std::unique_ptr<OwnCtx> own;
     State(Ctx* c, const MPO* m) : ctx(c), mpo(m) {
         // optional override of the sigma tile edges, "t1,t2" with t in {32, 64}
         if (const char* e = std::getenv("DMRG_SIGMA_TILES")) {

@@ -69,6 +69,13 @@ __device__ inline int64_t xcd_task(int64_t b, int64_t g) {
     const int64_t x = b % 8, i = b / 8;
     return x * per + (x < rem ? x : rem) + i;
 }
+// Chunked form: runs of c consecutive tasks stay on one XCD (shared operand
+// rows in its L2) and the runs rotate over the XCDs (balance).  The grid is
+// padded to a multiple of 8c; blocks mapped past the end do nothing.
+__device__ inline int64_t xcd_chunk_task(int64_t b, int64_t c) {
+    const int64_t x = b % 8, slot = b / 8;
+    return (x + 8 * (slot / c)) * c + slot % c;
+}
 
 // One packed K column of a grouped-GEMM step (see grouped_gemm).
 template <class T>
@@ -90,14 +97,20 @@ template <int MODE, int ROLE, int TS, int VAR>
 __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                                            const GemmTerm* __restrict__ terms,
                                                                            void* const* __restrict__ bases,
-                                                                           const int* __restrict__ active, int xcd) {
+                                                                           const int* __restrict__ active, int xcd,
+                                                                           int64_t n_tasks) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
     __shared__ T As[KS][TS + 4];
     __shared__ T Bs[KS][TS + 4];
 
-    const GemmTask task = tasks[xcd ? xcd_task(blockIdx.x, gridDim.x) : int64_t(blockIdx.x)];
+    // xcd: 0 block order, 1 one contiguous run per XCD, c > 1 runs of c tasks
+    const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
+                       : xcd == 1 ? xcd_task(blockIdx.x, gridDim.x)
+                                  : xcd_chunk_task(blockIdx.x, xcd);
+    if (ti >= n_tasks) return;  // padding of the chunked grid (before any barrier)
+    const GemmTask task = tasks[ti];
     if (active && !active[task.inst]) return;  // uniform per workgroup
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -1140,16 +1153,18 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
-        const unsigned g = unsigned(std::min<int64_t>(kMaxGrid, n_tasks - off));
+        const int64_t nt = std::min<int64_t>(kMaxGrid, n_tasks - off);
+        const int64_t step = xcd > 1 ? 8 * int64_t(xcd) : 1;
+        const unsigned g = unsigned((nt + step - 1) / step * step);
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<0, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<1, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd);
+                hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
         }
     }

@@ -77,12 +77,14 @@ void Mlp::adam(double lr) {
 }
 
 int64_t Mlp::append(const float* feat, const float* y, int64_t n) {
+    std::lock_guard<std::mutex> lk(mu);
     const int64_t k = std::min(n, ds_cap - ds_n);
     if (k <= 0) return 0;
     DMRG_HIP(hipMemcpyAsync(ds_x.as<float>() + ds_n * kMlpF, feat, size_t(k) * kMlpF * sizeof(float),
                             hipMemcpyDeviceToDevice, s));
     DMRG_HIP(hipMemcpyAsync(ds_y.as<float>() + ds_n, y, size_t(k) * sizeof(float), hipMemcpyDeviceToDevice, s));
     ds_n += k;
+    DMRG_HIP(hipStreamSynchronize(s));
     return k;
 }
 
@@ -115,6 +117,7 @@ double Mlp::train(int epochs, int batch, double lr, uint64_t perm_seed) {
 }
 
 std::vector<int> Mlp::draw_sample(int64_t n, int count) {
+    std::lock_guard<std::mutex> lk(mu);
     std::vector<int> idx(std::max(0, count));
     uint64_t g = seed ^ (0xd1b54a32d192ed03ULL * (++draws));
     for (int& i : idx) i = int(splitmix64(g) % uint64_t(n));

@@ -17,6 +17,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "core.h"
@@ -74,6 +75,7 @@ struct Mlp {
     DevBuf ds_x, ds_y;      // features (cap x 12) and targets (cap)
     int64_t ds_n = 0, ds_cap = 0;
     uint64_t seed = 0, draws = 0;
+    std::mutex mu;  // append and draw_sample may be called from concurrent instances
 
     // params: host array of kMlpP values, or nullptr for the seeded
     // initialisation (uniform Glorot bounds, output layer scaled by 0.1,
