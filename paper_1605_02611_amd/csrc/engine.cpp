@@ -2117,7 +2117,7 @@ void tune_load(const std::string& js) {
                 expect('}');
                 break;
             }
-            require((c.tile1 == 32 || c.tile1 == 64) && (c.tile2 == 32 || c.tile2 == 64) && c.pieces >= 256 &&
+            require((c.tile1 == 32 || c.tile1 == 64 || c.tile1 == 128) && (c.tile2 == 32 || c.tile2 == 64 || c.tile2 == 128) && c.pieces >= 256 &&
                         c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 3,
                     "tuning table: configuration out of range");
             add[key] = c;

@@ -281,7 +281,8 @@ class State {
         // optional override of the sigma tile edges, "t1,t2" with t in {32, 64}
         if (const char* e = std::getenv("DMRG_SIGMA_TILES")) {
             int a = 0, b = 0;
-            if (std::sscanf(e, "%d,%d", &a, &b) == 2 && (a == 32 || a == 64) && (b == 32 || b == 64)) {
+            auto ok = [](int t) { return t == 32 || t == 64 || t == 128; };
+            if (std::sscanf(e, "%d,%d", &a, &b) == 2 && ok(a) && ok(b)) {
                 cfg.tile1 = a;
                 cfg.tile2 = b;
                 cfg_explicit = true;

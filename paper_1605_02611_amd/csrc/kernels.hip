@@ -88,7 +88,7 @@ struct PackCol {
 
 // ROLE only separates the symbol of the sigma-vector launches (1) from every
 // other use (0) so that profiles report them apart; the code is identical.
-// TS: output tile edge (64: four waves of 32x32, 32: one wave).
+// TS: output tile edge (128: sixteen waves of 32x32, 64: four, 32: one).
 // VAR 0: one staging round per term and K-step; 1: K-steps packed across
 // terms; 2: software pipeline (the next step's operands are loaded into
 // registers while the current step is multiplied).  XCD: task order
@@ -1174,11 +1174,14 @@ template <int ROLE>
 static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                              void* const* b, const int* act, int tile, hipStream_t s, int variant) {
     if (n_tasks <= 0) return;
-    require(tile == 64 || tile == 32, "grouped GEMM: tile must be 64 or 32");
+    require(tile == 128 || tile == 64 || tile == 32, "grouped GEMM: tile must be 128, 64 or 32");
     static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
     const int var = variant >= 0 ? variant : var_env;
     require(var >= 0 && var <= 3, "grouped GEMM: unknown variant");
-    if (tile == 64) {
+    if (tile == 128) {
+        // sixteen waves of 32 x 32; the software-pipelined body
+        launch_gemm_tile<ROLE, 128, 2>(p, tasks, n_tasks, terms, b, act, s, xcd);
+    } else if (tile == 64) {
         if (var == 3) {
             // persistent workgroups: as many as are resident at once
             static int cus = 0;
