@@ -91,14 +91,27 @@ const char* dmrg_last_error(const dmrg_ctx* ctx);
 typedef struct {
     int switch_bond;     /* bonds k <= switch_bond keep normal two-index
                             operators on the left; -1 = floor(K/2) */
-    double compress_tol; /* reserved; must be 0 (exact MPO) */
+    double compress_tol; /* 0: exact MPO.  > 0: Hamiltonian compression
+                            (Sec. "Hamiltonian compression"): at every bond
+                            the integral matrix G coupling each 2-index
+                            channel family (A, B on the left of the switch;
+                            P, Q beyond it) with the pair operators of the
+                            other side is factored per quantum-number block,
+                            G = U lambda V^T; directions with lambda <=
+                            compress_tol (Hartree) are dropped and the site
+                            tensors become Pi^T W Pi with Pi the kept
+                            columns of U (Ad / Pd share the U of A / P).  A
+                            block that keeps every direction is unchanged.
+                            Singular values below about 1e-8 of the largest
+                            in a block are not resolved. */
 } dmrg_mpo_opts;
 
 /* Build the normal/complementary MPO of H for K sites, N electrons and
  * target 2S_z.  h: K*K, v: K^4 (host, FP64, chemists' notation).
  * Errors: DMRG_E_INVAL if K < 1, N outside [0, 2K], parity(2S_z) !=
- * parity(N), |2S_z| > min(N, 2K-N), h not symmetric or v without the
- * 8-fold symmetry (relative tolerance 1e-12). */
+ * parity(N), |2S_z| > min(N, 2K-N), h not symmetric, v without the
+ * 8-fold symmetry (relative tolerance 1e-12), compress_tol negative or not
+ * finite; DMRG_E_NUMERIC if the compression's eigensolver fails. */
 dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
                            int n_elec, int two_sz, const dmrg_mpo_opts* opts,
                            dmrg_mpo** out);
@@ -106,13 +119,22 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D);
 /* Channel labels of bond k: 3*D[k] ints (kind, p, q), kinds
  * 0 I, 1 H, 2 a+_p, 3 a_p, 4 S^L_p, 5 S^L+_p, 6 a+_p a+_q, 7 a_q a_p,
- * 8 a+_p a_q, 9 P^L_pq, 10 P^L+_pq, 11 Q^L_pq (p, q spin orbitals, -1 unused). */
+ * 8 a+_p a_q, 9 P^L_pq, 10 P^L+_pq, 11 Q^L_pq (p, q spin orbitals, -1 unused),
+ * 12 a compressed 2-index channel (p = its family's kind 6..11, q = its
+ * index among that family's compressed channels; unchanged channels keep
+ * their order and precede the compressed ones). */
 dmrg_status dmrg_mpo_channels(const dmrg_mpo* mpo, int bond, int32_t* labels);
 /* Nonzero entries of W[site]: call with xy == NULL to get *n; then xy (2n:
  * left channel, right channel) and mats (16n: 4x4 row-major, row = output
  * state) receive the entries. */
 dmrg_status dmrg_mpo_site_entries(const dmrg_mpo* mpo, int site, int64_t* n,
                                   int32_t* xy, double* mats);
+/* Singular values of the 2-index coupling blocks of bond k of a compressed
+ * MPO (every direction, kept or dropped, one per channel row of the A / B or
+ * P / Q families; descending).  sv == NULL: *n receives the count (0 for an
+ * exact MPO and for bonds 0 and K); otherwise *n is the capacity of sv on
+ * input and the count on output. */
+dmrg_status dmrg_mpo_singular_values(const dmrg_mpo* mpo, int bond, int64_t* n, double* sv);
 void dmrg_mpo_free(dmrg_mpo* mpo);
 
 /* ---- MPS state ----------------------------------------------------------- */

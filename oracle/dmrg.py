@@ -241,10 +241,12 @@ class DMRG:
     """Dense-tensor two-site DMRG on the oracle's MPO."""
 
     def __init__(self, h, v, n_elec, two_sz, M, values, dav_tol=1e-9,
-                 dav_max_iter=200, dav_max_space=24, dav_keep=4):
+                 dav_max_iter=200, dav_max_space=24, dav_keep=4, compress_tol=0.0):
         self.K = K = h.shape[0]
         self.N, self.tsz, self.M = n_elec, two_sz, M
         self.Ws, self.chans = mpo_mod.build_mpo(h, v)
+        if compress_tol > 0.0:
+            self.Ws, self.chans, _ = mpo_mod.compress_mpo(self.Ws, self.chans, h, v, compress_tol)
         self.Wd = [mpo_mod.dense_site(self.Ws[j], len(self.chans[j]), len(self.chans[j + 1]))
                    for j in range(K)]
         A, labels, _ = random_mps(K, n_elec, two_sz, M, values)

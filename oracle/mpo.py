@@ -399,3 +399,119 @@ def apply_mpo(Ws, chans, x):
 
 def bond_dims(K):
     return [len(channels(K, k)) for k in range(K + 1)]
+
+
+# --- Hamiltonian compression (Sec. "Hamiltonian compression") ----------------
+#
+# At bond k the 2-index part of the left-right decomposition couples each
+# 2-index channel with a pair of normal operators on the other side through
+# an integral matrix G (rows: channels of one family and one quantum-number
+# class, in channel order; columns: the pair basis of the other side):
+#   A / P   (v_pqrs - v_pqsr) for the pairs a_r a_s, r < s
+#   B / Q   w_prqs = v_prqs - v_prsq for the pairs a+_r a_s, all (r, s)
+# with (p, q) the channel's own indices.  The paper's scheme takes the SVD
+# G = U lambda V^T per quantum-number block and keeps the directions with
+# lambda > tol; the compressed channels are sum_x U_xi (channel x), and every
+# site tensor is transformed as W[j] -> Pi_j^T W[j] Pi_{j+1}, with Pi_k the
+# isometry (old channels -> kept channels) of bond k: the identity on the
+# other channels, U on the 2-index blocks (the rule A -> V+ A V of the
+# transformed W).  Ad / Pd channels are the conjugates of A / P and use the
+# same U.  A block that keeps every direction is left as it is (Pi = 1 there).
+
+PAIR_BASE = {"A": "A", "Ad": "A", "B": "B", "P": "P", "Pd": "P", "Q": "Q"}
+
+
+def _coupling_row(kind, p, q, other, vs, w):
+    if kind in ("A", "P"):
+        return np.array([vs[p, q, r, s] - vs[p, q, s, r] for r in other for s in other if r < s])
+    return np.array([w[p, r, q, s] for r in other for s in other])
+
+
+def compression_blocks(h, v, K, k):
+    """2-index blocks of bond k: list of (family, row channel indices, G)."""
+    _, vs = spin_orbital_integrals(h, v)
+    w = vs - vs.transpose(0, 1, 3, 2)
+    ch = channels(K, k)
+    normal = k <= switch_bond(K)
+    other = range(2 * k, 2 * K) if normal else range(0, 2 * k)
+    out = []
+    for fam in (("A", "B") if normal else ("P", "Q")):
+        order = []
+        rows = {}
+        for i, c in enumerate(ch):
+            if c[0] != fam:
+                continue
+            dq = channel_qn(c)
+            if dq not in rows:
+                rows[dq] = []
+                order.append(dq)
+            rows[dq].append(i)
+        for dq in order:
+            G = np.array([_coupling_row(fam, ch[i][1], ch[i][2], other, vs, w) for i in rows[dq]])
+            out.append((fam, rows[dq], G.reshape(len(rows[dq]), -1)))
+    return out
+
+
+def compress_mpo(Ws, chans, h, v, tol):
+    """Compressed site tensors, channel labels and, per bond, every
+    singular value of its 2-index blocks (zeros included, one per row)."""
+    K = len(Ws)
+    Pis = [np.ones((1, 1))]
+    new_chans = [chans[0]]
+    svals = [np.zeros(0)]
+    for k in range(1, K):
+        ch = chans[k]
+        D = len(ch)
+        sv = []
+        kept = []  # (family, row indices, U) of the blocks that lose directions
+        full_rows = set()
+        conj_of = {"A": "Ad", "P": "Pd"}
+        for fam, rows, G in compression_blocks(h, v, K, k):
+            if G.shape[1] == 0:
+                U, s = np.zeros((len(rows), 0)), np.zeros(0)
+            else:
+                U, s, _ = np.linalg.svd(G, full_matrices=False)
+            s_all = np.zeros(len(rows))
+            s_all[:len(s)] = s
+            sv.append(s_all)
+            keep = s > tol
+            conj_rows = [ch.index((conj_of[fam], ch[i][1], ch[i][2])) for i in rows] if fam in conj_of else []
+            if keep.sum() == len(rows):
+                full_rows.update(rows)
+                full_rows.update(conj_rows)
+                continue
+            kept.append((fam, rows, U[:, keep]))
+            if conj_rows:
+                kept.append((conj_of[fam], conj_rows, U[:, keep]))
+        # unchanged channels keep their order; compressed ones follow, family
+        # by family (A, Ad, B or P, Pd, Q), block by block
+        cols, labels = [], []
+        for i, c in enumerate(ch):
+            if c[0] not in PAIR_BASE or i in full_rows:
+                e = np.zeros(D)
+                e[i] = 1.0
+                cols.append(e)
+                labels.append(c)
+        for fam in ("A", "Ad", "B", "P", "Pd", "Q"):
+            n_fam = 0
+            for f, rows, U in kept:
+                if f != fam:
+                    continue
+                for a in range(U.shape[1]):
+                    e = np.zeros(D)
+                    e[rows] = U[:, a]
+                    cols.append(e)
+                    labels.append(("X", fam, n_fam))
+                    n_fam += 1
+        Pis.append(np.array(cols).T.reshape(D, len(cols)))
+        new_chans.append(labels)
+        svals.append(np.sort(np.concatenate(sv))[::-1] if sv else np.zeros(0))
+    Pis.append(np.ones((1, 1)))
+    new_chans.append(chans[K])
+    svals.append(np.zeros(0))
+    out = []
+    for j in range(K):
+        Wd = dense_site(Ws[j], len(chans[j]), len(chans[j + 1]))
+        Wc = np.einsum("xi,xyst,yj->ijst", Pis[j], Wd, Pis[j + 1])
+        out.append({(i, jj): Wc[i, jj].copy() for i, jj in zip(*np.nonzero(np.any(Wc != 0.0, axis=(2, 3))))})
+    return out, new_chans, svals

@@ -49,6 +49,7 @@ SIGNATURES = {
                                P(MpoOpts), P(c_void_p)]),
     "dmrg_mpo_bond_dims": (c_int, [c_void_p, P(c_int32)]),
     "dmrg_mpo_channels": (c_int, [c_void_p, c_int, P(c_int32)]),
+    "dmrg_mpo_singular_values": (c_int, [c_void_p, c_int, P(c_int64), P(c_double)]),
     "dmrg_mpo_site_entries": (c_int, [c_void_p, c_int, P(c_int64), P(c_int32), P(c_double)]),
     "dmrg_mpo_free": (None, [c_void_p]),
     "dmrg_mps_n_values": (c_int, [c_void_p, c_int, P(c_int64)]),

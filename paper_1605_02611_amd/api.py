@@ -86,7 +86,7 @@ class Context:
 class Mpo:
     """Normal/complementary MPO of H (dmrg_build_mpo)."""
 
-    def __init__(self, ctx, h, v, n_elec, two_sz=None, switch_bond=-1):
+    def __init__(self, ctx, h, v, n_elec, two_sz=None, switch_bond=-1, compress_tol=0.0):
         self.ctx, self.lib = ctx, ctx.lib
         h = np.asarray(h, dtype=np.float64)
         K = h.shape[0]
@@ -95,7 +95,7 @@ class Mpo:
             two_sz = n_elec % 2
         hh, hp = _dptr(h)
         vv, vp = _dptr(v)
-        opts = L.MpoOpts(switch_bond, 0.0)
+        opts = L.MpoOpts(switch_bond, compress_tol)
         out = C.c_void_p()
         ctx.check(self.lib.dmrg_build_mpo(ctx.h, hp, vp, K, n_elec, two_sz, C.byref(opts),
                                           C.byref(out)))
@@ -112,6 +112,16 @@ class Mpo:
         lab = np.zeros(3 * D, dtype=np.int32)
         self.ctx.check(self.lib.dmrg_mpo_channels(self.h, k, lab.ctypes.data_as(C.POINTER(C.c_int32))))
         return lab.reshape(D, 3)
+
+    def singular_values(self, k):
+        """Singular values of the 2-index coupling blocks of bond k
+        (compressed MPOs only; empty otherwise)."""
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_mpo_singular_values(self.h, k, C.byref(n), None))
+        sv = np.zeros(n.value)
+        self.ctx.check(self.lib.dmrg_mpo_singular_values(
+            self.h, k, C.byref(n), sv.ctypes.data_as(C.POINTER(C.c_double))))
+        return sv
 
     def site_entries(self, j):
         n = C.c_int64()

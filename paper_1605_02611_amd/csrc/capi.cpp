@@ -169,12 +169,15 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
     return guard(ctx, [&] {
         require(h && v && out, "null argument");
         int sw = -1;
+        double tol = 0.0;
         if (opts) {
-            require(opts->compress_tol == 0.0, "MPO compression is not available (compress_tol must be 0)");
+            require(std::isfinite(opts->compress_tol) && opts->compress_tol >= 0.0,
+                    "compress_tol must be finite and >= 0");
             require(opts->switch_bond >= -1 && opts->switch_bond <= K, "switch_bond out of range");
             sw = opts->switch_bond;
+            tol = opts->compress_tol;
         }
-        auto m = build_mpo(h, v, K, n_elec, two_sz, sw);
+        auto m = build_mpo(h, v, K, n_elec, two_sz, sw, tol);
         auto* r = new dmrg_mpo();
         r->m = std::move(m);
         *out = r;
@@ -184,6 +187,20 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D) {
     if (!mpo || !D) return DMRG_E_INVAL;
     for (size_t k = 0; k < mpo->m->chans.size(); ++k) D[k] = int32_t(mpo->m->chans[k].size());
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_mpo_singular_values(const dmrg_mpo* mpo, int bond, int64_t* n, double* sv) {
+    if (!mpo || !n || bond < 0 || bond > mpo->m->K) return DMRG_E_INVAL;
+    const std::vector<double> none;
+    const auto& s = mpo->m->sv.empty() ? none : mpo->m->sv[bond];
+    if (!sv) {
+        *n = int64_t(s.size());
+        return DMRG_OK;
+    }
+    if (*n < int64_t(s.size())) return DMRG_E_INVAL;
+    std::copy(s.begin(), s.end(), sv);
+    *n = int64_t(s.size());
     return DMRG_OK;
 }
 

@@ -108,7 +108,9 @@ struct Mat4 {
 
 // ---------------------------------------------------------------------------
 // MPO: channels per bond and sparse site tensors
-enum ChanKind { CK_I = 0, CK_H, CK_Cd, CK_C, CK_SL, CK_SLd, CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q };
+enum ChanKind { CK_I = 0, CK_H, CK_Cd, CK_C, CK_SL, CK_SLd, CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q, CK_X };
+// CK_X: a compressed 2-index channel (p = its family's kind, q = its index
+// among the compressed channels of that family at the bond)
 struct Chan {
     int kind, p, q;
 };
@@ -141,10 +143,13 @@ struct MPO {
     std::vector<std::vector<QN>> chan_dq;        // per bond
     std::vector<std::vector<std::pair<std::pair<int, int>, Mat4>>> W;  // per site
     std::vector<std::vector<FineW>> fine;        // per site, sorted by (y, sp, s, x)
+    double compress_tol = 0.0;
+    std::vector<std::vector<double>> sv;  // per bond: singular values of its 2-index blocks
     QN target() const { return {n_elec, two_sz}; }
 };
+// compress_tol > 0: SVD compression of the 2-index channel blocks (mpo.cpp)
 std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
-                               int switch_bond);
+                               int switch_bond, double compress_tol = 0.0);
 
 // ---------------------------------------------------------------------------
 // kernels (kernels.hip)
@@ -272,6 +277,10 @@ void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s);
 void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
                          int* rotated, hipStream_t s);
 void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s);
+// block form: slots (job, block-pair index) over blocks of jacobi_block_width() columns
+void launch_jacobi_block(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
+                         int* rotated, hipStream_t s);
+int jacobi_block_width();
 constexpr int kJacobiRoundMin = 160;  // sectors with at least this many columns use the round launches
 
 // ---------------------------------------------------------------------------

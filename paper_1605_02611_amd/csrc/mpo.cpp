@@ -19,7 +19,14 @@
 // Eqs. Sm / norm_complementary; hermitian-conjugate channels use
 // W[xbar, ybar] = eps_x eps_y W[x, y]^T (eps = -1 for odd channels).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <exception>
+#include <functional>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "core.h"
@@ -409,9 +416,439 @@ bool chan_odd(const Chan& c) {
     return c.kind == CK_Cd || c.kind == CK_C || c.kind == CK_SL || c.kind == CK_SLd;
 }
 
+namespace {
+
+// fine entries of W[j] and their groupings for the two blocking directions
+void index_site(MPO& mpo, int j) {
+    auto* m = &mpo;
+    auto& f = m->fine[j];
+    for (auto& [xy, mat] : m->W[j])
+        for (int sp = 0; sp < 4; ++sp)
+            for (int s = 0; s < 4; ++s)
+                if (mat(sp, s) != 0.0)
+                    f.push_back({xy.first, xy.second, int8_t(sp), int8_t(s), mat(sp, s)});
+    // groupings used by the blocking step, sorted once here
+    for (int side = 0; side < 2; ++side) {
+        std::vector<int> idx(f.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = int(i);
+        auto key = [&](const FineW& e) { return side == 0 ? e.y : e.x; };
+        auto other = [&](const FineW& e) { return side == 0 ? e.x : e.y; };
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+            const FineW &p = f[a], &q = f[b];
+            if (key(p) != key(q)) return key(p) < key(q);
+            if (p.sp != q.sp) return p.sp < q.sp;
+            if (p.s != q.s) return p.s < q.s;
+            return other(p) < other(q);
+        });
+        WGroups& G = side == 0 ? m->sys_groups[j] : m->env_groups[j];
+        for (size_t i = 0; i < idx.size();) {
+            const FineW& hd = f[idx[i]];
+            size_t e = i;
+            while (e < idx.size() && key(f[idx[e]]) == key(hd) && f[idx[e]].sp == hd.sp &&
+                   f[idx[e]].s == hd.s)
+                ++e;
+            WGroup g{key(hd), hd.sp, hd.s, int(G.terms.size()), 0};
+            for (size_t k = i; k < e; ++k) G.terms.push_back({other(f[idx[k]]), f[idx[k]].c});
+            g.end = int(G.terms.size());
+            G.groups.push_back(g);
+            i = e;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hamiltonian compression (Sec. "Hamiltonian compression", Eqs.
+// lrdecomp_compression and lrafter_decomp_compression with the transformed
+// W matrices).  At bond k the 2-index part of the left-right decomposition
+// couples every 2-index channel with pair operators on the other side
+// through an integral matrix G (rows: the channels of one family and one
+// quantum-number class, in channel order; columns: the pairs of the other
+// side):
+//   A (k <= switch) / P (k > switch):  v_pqrs - v_pqsr, pairs a_r a_s, r < s
+//   B (k <= switch) / Q (k > switch):  w_prqs = v_prqs - v_prsq, pairs a+_r a_s
+// G = U lambda V^T is truncated to lambda > tol; the kept channels are
+// sum_x U_xi (channel x) and each site tensor becomes Pi_j^T W[j] Pi_{j+1},
+// Pi_k being the isometry old -> kept channels of bond k (identity outside
+// the 2-index blocks).  Ad / Pd are the conjugates of A / P and share their
+// U.  A block that keeps all of its directions is left as it is.
+
+// f(i) for i < n on up to 16 host threads
+template <class F>
+void host_parallel_for(int n, F f) {
+    const int nt = std::max(1, std::min({n, 16, int(std::max(1u, std::thread::hardware_concurrency()))}));
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto work = [&]() {
+        for (int i = next++; i < n; i = next++) {
+            try {
+                f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (std::thread& x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
+// Eigenpairs of the symmetric n x n matrix A (row-major, destroyed):
+// Householder reduction to tridiagonal form, then implicit QR steps with the
+// Wilkinson shift (Golub and Van Loan, Matrix Computations, Secs. 8.3.1 and
+// 8.3.3).  lam[i] is an eigenvalue and column i of Z (row-major) its vector.
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Z) {
+    Z.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[size_t(i) * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j) r += std::fabs(a(i, j));
+        anorm = std::max(anorm, r);
+    }
+    std::vector<double> v(n), p(n), w(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;  // x = A[k+1.., k]
+        double tail = 0.0;
+        for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
+        for (int i = 1; i < m; ++i) tail += v[i] * v[i];
+        if (tail == 0.0) continue;
+        const double alpha = std::sqrt(v[0] * v[0] + tail);
+        const double sgn = v[0] >= 0.0 ? 1.0 : -1.0;
+        v[0] += sgn * alpha;
+        const double beta = 2.0 / (v[0] * v[0] + tail);
+        for (int i = 0; i < m; ++i) {
+            const double* row = &A[size_t(k + 1 + i) * n + k + 1];
+            double t = 0.0;
+            for (int j = 0; j < m; ++j) t += row[j] * v[j];
+            p[i] = beta * t;
+        }
+        double pv = 0.0;
+        for (int i = 0; i < m; ++i) pv += p[i] * v[i];
+        const double kk = 0.5 * beta * pv;
+        for (int i = 0; i < m; ++i) w[i] = p[i] - kk * v[i];
+        for (int i = 0; i < m; ++i) {
+            double* row = &A[size_t(k + 1 + i) * n + k + 1];
+            const double vi = v[i], wi = w[i];
+            for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
+        }
+        a(k + 1, k) = a(k, k + 1) = -sgn * alpha;
+        for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+        for (int r = 0; r < n; ++r) {
+            double* zr = &Z[size_t(r) * n + k + 1];
+            double t = 0.0;
+            for (int j = 0; j < m; ++j) t += zr[j] * v[j];
+            t *= beta;
+            for (int j = 0; j < m; ++j) zr[j] -= t * v[j];
+        }
+    }
+    std::vector<double> d(n), e(std::max(n, 1), 0.0);
+    for (int i = 0; i < n; ++i) d[i] = a(i, i);
+    for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+    const double eps = std::numeric_limits<double>::epsilon();
+    auto small = [&](int i) {  // e[i] negligible
+        return std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1])) + 1e-3 * eps * anorm;
+    };
+    int hi = n - 1, iter = 0;
+    while (hi > 0) {
+        if (small(hi - 1)) {
+            e[hi - 1] = 0.0;
+            --hi;
+            iter = 0;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && !small(lo - 1)) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        if (++iter > 100) throw Error(E_NUMERIC, "MPO compression: eigensolver did not converge");
+        const double dd = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
+        const double mu = d[hi] - eh * eh / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, eh));
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
+            if (k > lo) e[k - 1] = r;
+            const double ak = d[k], ak1 = d[k + 1], bk = e[k];
+            d[k] = c * c * ak + 2.0 * c * sn * bk + sn * sn * ak1;
+            d[k + 1] = sn * sn * ak - 2.0 * c * sn * bk + c * c * ak1;
+            e[k] = c * sn * (ak1 - ak) + (c * c - sn * sn) * bk;
+            if (k + 1 < hi) {
+                z = sn * e[k + 1];
+                e[k + 1] *= c;
+                x = e[k];
+            }
+            for (int r2 = 0; r2 < n; ++r2) {
+                double* zr = &Z[size_t(r2) * n];
+                const double zk = zr[k], zk1 = zr[k + 1];
+                zr[k] = c * zk + sn * zk1;
+                zr[k + 1] = -sn * zk + c * zk1;
+            }
+        }
+    }
+    lam = d;
+}
+
+// Old channels of a bond grouped for the transformation: a group is either
+// one unchanged channel (U = [1]) or a compressed block (U: rows x r).
+struct CGroup {
+    std::vector<int> rows;
+    std::vector<double> U;  // rows.size() x r, row-major
+    int r = 1, first_new = 0;
+};
+struct CBond {
+    std::vector<Chan> chans;
+    std::vector<QN> dq;
+    std::vector<CGroup> groups;
+    std::vector<int> gid, loc;  // per old channel: group and row in it (-1: dropped)
+    std::vector<double> sv;
+};
+
+CBond compress_bond(const MPO& m, const double* h, const double* v, int k, double tol) {
+    (void)h;
+    const int K = m.K;
+    const std::vector<Chan>& ch = m.chans[k];
+    const int D = int(ch.size());
+    auto vs = [&](int P, int Q, int R, int S) {  // (ps|qr) d(sP,sS) d(sQ,sR)
+        if (P % 2 != S % 2 || Q % 2 != R % 2) return 0.0;
+        return v[((int64_t(P / 2) * K + S / 2) * K + Q / 2) * K + R / 2];
+    };
+    const bool normal = k <= m.switch_bond;
+    const int o0 = normal ? 2 * k : 0, o1 = normal ? 2 * K : 2 * k;  // other side's orbitals
+    std::unordered_map<int64_t, int> index;
+    for (int i = 0; i < D; ++i) index[key_of(ch[i])] = i;
+
+    struct Block {
+        int fam, conj;
+        std::vector<int> rows, conj_rows;
+        std::vector<double> U;
+        int r = 0;
+    };
+    std::vector<Block> blocks;
+    for (int fam : {normal ? CK_A : CK_P, normal ? CK_B : CK_Q}) {
+        const int conj = fam == CK_A ? CK_Ad : fam == CK_P ? CK_Pd : -1;
+        std::vector<QN> order;
+        std::vector<std::vector<int>> rows;
+        for (int i = 0; i < D; ++i) {
+            if (ch[i].kind != fam) continue;
+            const QN q = m.chan_dq[k][i];
+            size_t b = 0;
+            while (b < order.size() && !(order[b] == q)) ++b;
+            if (b == order.size()) {
+                order.push_back(q);
+                rows.emplace_back();
+            }
+            rows[b].push_back(i);
+        }
+        for (auto& rw : rows) {
+            Block B;
+            B.fam = fam;
+            B.conj = conj;
+            B.rows = rw;
+            if (conj >= 0)
+                for (int i : rw) {
+                    auto it = index.find(key_of({conj, ch[i].p, ch[i].q}));
+                    require(it != index.end(), "internal: conjugate channel missing");
+                    B.conj_rows.push_back(it->second);
+                }
+            blocks.push_back(std::move(B));
+        }
+    }
+    CBond out;
+    std::vector<char> keep_old(D, 1);
+    for (Block& B : blocks) {
+        const int n = int(B.rows.size());
+        // G (n x ncol)
+        std::vector<double> G;
+        int ncol = 0;
+        for (int i : B.rows) {
+            const int p = ch[i].p, q = ch[i].q;
+            if (B.fam == CK_A || B.fam == CK_P) {
+                for (int r = o0; r < o1; ++r)
+                    for (int s2 = r + 1; s2 < o1; ++s2) G.push_back(vs(p, q, r, s2) - vs(p, q, s2, r));
+            } else {
+                for (int r = o0; r < o1; ++r)
+                    for (int s2 = o0; s2 < o1; ++s2) G.push_back(vs(p, r, q, s2) - vs(p, r, s2, q));
+            }
+        }
+        ncol = n ? int(G.size() / n) : 0;
+        std::vector<double> gram(size_t(n) * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double t = 0.0;
+                const double *gi = &G[size_t(i) * ncol], *gj = &G[size_t(j) * ncol];
+                for (int c = 0; c < ncol; ++c) t += gi[c] * gj[c];
+                gram[size_t(i) * n + j] = gram[size_t(j) * n + i] = t;
+            }
+        std::vector<double> lam, Z;
+        sym_eig(n, gram, lam, Z);
+        // singular values as ||G^T u_i||, which keeps small ones accurate
+        std::vector<double> sig(n);
+        std::vector<double> gu(ncol);
+        for (int a = 0; a < n; ++a) {
+            std::fill(gu.begin(), gu.end(), 0.0);
+            for (int i = 0; i < n; ++i) {
+                const double z = Z[size_t(i) * n + a];
+                if (z == 0.0) continue;
+                const double* gi = &G[size_t(i) * ncol];
+                for (int c = 0; c < ncol; ++c) gu[c] += z * gi[c];
+            }
+            double t = 0.0;
+            for (double x : gu) t += x * x;
+            sig[a] = std::sqrt(t);
+        }
+        std::vector<int> ord(n);
+        for (int a = 0; a < n; ++a) ord[a] = a;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sig[x] > sig[y]; });
+        for (int a : ord) out.sv.push_back(sig[a]);
+        int r = 0;
+        while (r < n && sig[ord[r]] > tol) ++r;
+        B.r = r;
+        if (r == n) continue;  // every direction kept: the block stays as it is
+        B.U.resize(size_t(n) * r);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < r; ++c) B.U[size_t(i) * r + c] = Z[size_t(i) * n + ord[c]];
+        for (int i : B.rows) keep_old[i] = 0;
+        for (int i : B.conj_rows) keep_old[i] = 0;
+    }
+    std::sort(out.sv.begin(), out.sv.end(), std::greater<double>());
+    out.gid.assign(D, -1);
+    out.loc.assign(D, -1);
+    for (int i = 0; i < D; ++i) {
+        if (!keep_old[i]) continue;
+        CGroup g;
+        g.rows = {i};
+        g.U = {1.0};
+        g.first_new = int(out.chans.size());
+        out.gid[i] = int(out.groups.size());
+        out.loc[i] = 0;
+        out.groups.push_back(std::move(g));
+        out.chans.push_back(ch[i]);
+        out.dq.push_back(m.chan_dq[k][i]);
+    }
+    const int fams[6] = {CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q};
+    for (int fam : fams) {
+        int n_fam = 0;
+        for (const Block& B : blocks) {
+            if (B.r == int(B.rows.size())) continue;
+            const bool as_conj = B.conj == fam;
+            if (B.fam != fam && !as_conj) continue;
+            const std::vector<int>& rows = as_conj ? B.conj_rows : B.rows;
+            if (B.r == 0) continue;
+            CGroup g;
+            g.rows = rows;
+            g.U = B.U;
+            g.r = B.r;
+            g.first_new = int(out.chans.size());
+            for (size_t i = 0; i < rows.size(); ++i) {
+                out.gid[rows[i]] = int(out.groups.size());
+                out.loc[rows[i]] = int(i);
+            }
+            for (int c = 0; c < B.r; ++c) {
+                out.chans.push_back({CK_X, fam, n_fam++});
+                out.dq.push_back(m.chan_dq[k][rows[0]]);
+            }
+            out.groups.push_back(std::move(g));
+        }
+    }
+    return out;
+}
+
+// W[j] -> Pi_j^T W[j] Pi_{j+1}, group pair by group pair
+std::vector<std::pair<std::pair<int, int>, Mat4>> transform_site(
+    const std::vector<std::pair<std::pair<int, int>, Mat4>>& W, const CBond& L, const CBond& R) {
+    std::map<std::pair<int, int>, std::vector<int>> buckets;
+    for (size_t e = 0; e < W.size(); ++e) {
+        const int gx = L.gid[W[e].first.first], gy = R.gid[W[e].first.second];
+        if (gx < 0 || gy < 0) continue;  // a 2-index block that keeps nothing
+        buckets[{gx, gy}].push_back(int(e));
+    }
+    std::vector<std::pair<std::pair<int, int>, Mat4>> out;
+    std::vector<double> T, O;
+    for (const auto& [g, ents] : buckets) {
+        const CGroup &GX = L.groups[g.first], &GY = R.groups[g.second];
+        int cs[16], nc = 0;
+        for (int c = 0; c < 16; ++c) {
+            bool any = false;
+            for (int e : ents) any = any || W[e].second.a[c] != 0.0;
+            if (any) cs[nc++] = c;
+        }
+        if (nc == 0) continue;
+        const int nx = int(GX.rows.size()), rx = GX.r, ry = GY.r;
+        const size_t row = size_t(ry) * nc;
+        T.assign(size_t(nx) * row, 0.0);
+        std::vector<char> touched(nx, 0);
+        for (int e : ents) {
+            const int lx = L.loc[W[e].first.first], ly = R.loc[W[e].first.second];
+            touched[lx] = 1;
+            const double* u = &GY.U[size_t(ly) * ry];
+            double* t = &T[size_t(lx) * row];
+            for (int c = 0; c < ry; ++c) {
+                if (u[c] == 0.0) continue;
+                for (int q = 0; q < nc; ++q) t[size_t(c) * nc + q] += u[c] * W[e].second.a[cs[q]];
+            }
+        }
+        O.assign(size_t(rx) * row, 0.0);
+        for (int lx = 0; lx < nx; ++lx) {
+            if (!touched[lx]) continue;
+            const double* t = &T[size_t(lx) * row];
+            for (int a = 0; a < rx; ++a) {
+                const double u = GX.U[size_t(lx) * rx + a];
+                if (u == 0.0) continue;
+                double* o = &O[size_t(a) * row];
+                for (size_t q = 0; q < row; ++q) o[q] += u * t[q];
+            }
+        }
+        for (int a = 0; a < rx; ++a)
+            for (int c = 0; c < ry; ++c) {
+                Mat4 M;
+                for (int q = 0; q < nc; ++q) M.a[cs[q]] = O[size_t(a) * row + size_t(c) * nc + q];
+                if (!M.zero()) out.push_back({{GX.first_new + a, GY.first_new + c}, M});
+            }
+    }
+    std::sort(out.begin(), out.end(), [](const auto& x, const auto& y) {
+        return x.first.second != y.first.second ? x.first.second < y.first.second
+                                                : x.first.first < y.first.first;
+    });
+    return out;
+}
+
+void compress(MPO& m, const double* h, const double* v, double tol) {
+    const int K = m.K;
+    std::vector<CBond> bonds(K + 1);
+    host_parallel_for(K - 1, [&](int i) { bonds[i + 1] = compress_bond(m, h, v, i + 1, tol); });
+    for (int k : {0, K}) {  // single-channel boundary bonds
+        CBond& b = bonds[k];
+        b.chans = m.chans[k];
+        b.dq = m.chan_dq[k];
+        CGroup g;
+        g.rows = {0};
+        g.U = {1.0};
+        b.groups = {g};
+        b.gid = {0};
+        b.loc = {0};
+    }
+    std::vector<std::vector<std::pair<std::pair<int, int>, Mat4>>> W(K);
+    host_parallel_for(K, [&](int j) { W[j] = transform_site(m.W[j], bonds[j], bonds[j + 1]); });
+    m.W = std::move(W);
+    m.sv.assign(K + 1, {});
+    for (int k = 0; k <= K; ++k) {
+        m.chans[k] = bonds[k].chans;
+        m.chan_dq[k] = bonds[k].dq;
+        m.sv[k] = bonds[k].sv;
+    }
+    m.compress_tol = tol;
+}
+
+}  // namespace
+
 std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
-                               int switch_bond) {
+                               int switch_bond, double compress_tol) {
     require(K >= 1 && K <= 1000, "K must be in [1, 1000]");
+    require(std::isfinite(compress_tol) && compress_tol >= 0.0, "compress_tol must be finite and >= 0");
     require(n_elec >= 0 && n_elec <= 2 * K, "N must be in [0, 2K]");
     require(((n_elec - two_sz) % 2 + 2) % 2 == 0, "parity of 2Sz must equal parity of N");
     require(std::abs(two_sz) <= std::min(n_elec, 2 * K - n_elec), "|2Sz| too large for N, K");
@@ -454,40 +891,9 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
     m->env_groups.resize(K);
     for (int j = 0; j < K; ++j) {
         b.site(j, m->chans[j], m->chans[j + 1], m->W[j]);
-        auto& f = m->fine[j];
-        for (auto& [xy, mat] : m->W[j])
-            for (int sp = 0; sp < 4; ++sp)
-                for (int s = 0; s < 4; ++s)
-                    if (mat(sp, s) != 0.0)
-                        f.push_back({xy.first, xy.second, int8_t(sp), int8_t(s), mat(sp, s)});
-        // groupings used by the blocking step, sorted once here
-        for (int side = 0; side < 2; ++side) {
-            std::vector<int> idx(f.size());
-            for (size_t i = 0; i < idx.size(); ++i) idx[i] = int(i);
-            auto key = [&](const FineW& e) { return side == 0 ? e.y : e.x; };
-            auto other = [&](const FineW& e) { return side == 0 ? e.x : e.y; };
-            std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-                const FineW &p = f[a], &q = f[b];
-                if (key(p) != key(q)) return key(p) < key(q);
-                if (p.sp != q.sp) return p.sp < q.sp;
-                if (p.s != q.s) return p.s < q.s;
-                return other(p) < other(q);
-            });
-            WGroups& G = side == 0 ? m->sys_groups[j] : m->env_groups[j];
-            for (size_t i = 0; i < idx.size();) {
-                const FineW& hd = f[idx[i]];
-                size_t e = i;
-                while (e < idx.size() && key(f[idx[e]]) == key(hd) && f[idx[e]].sp == hd.sp &&
-                       f[idx[e]].s == hd.s)
-                    ++e;
-                WGroup g{key(hd), hd.sp, hd.s, int(G.terms.size()), 0};
-                for (size_t k = i; k < e; ++k) G.terms.push_back({other(f[idx[k]]), f[idx[k]].c});
-                g.end = int(G.terms.size());
-                G.groups.push_back(g);
-                i = e;
-            }
-        }
     }
+    if (compress_tol > 0.0) compress(*m, h, v, compress_tol);
+    for (int j = 0; j < K; ++j) index_site(*m, j);
     return m;
 }
 

@@ -122,6 +122,16 @@ def test_gpu_calls_on_host_context_fail_cleanly(hctx):
     with pytest.raises(P.DmrgError) as e:
         P.Mps.random(hctx, m, 8, np.zeros(n))
     assert e.value.status == 6
+    with pytest.raises(P.DmrgError) as e:
+        P.Mlp(hctx)
+    assert e.value.status == 6
+    # null handles are rejected before any device work
+    lib = _lib.load()
+    assert lib.dmrg_solve(hctx.h, None, m.h, None, None, None, None) == 1
+    assert lib.dmrg_psi_import(hctx.h, None, None) == 1
+    assert lib.dmrg_autotune(hctx.h, None, m.h, 0, 1, None, 0) == 1
+    assert lib.dmrg_mlp_forward(hctx.h, None, None, 0, None) == 1
+    assert lib.dmrg_mlp_train(hctx.h, None, 1, 1, 1e-3, 0, None) == 1
 
 
 def test_tuning_table_round_trip_and_validation():

@@ -12,5 +12,7 @@ from .integrals import (  # noqa: F401
     config_integrals,
     batched_instances,
     mps_values,
+    separable_integrals,
+    nearest_neighbour_integrals,
     CONFIGS,
 )

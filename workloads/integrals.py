@@ -128,6 +128,38 @@ def config_integrals(cfg):
     raise ValueError("workload %d is a batch; use batched_instances()" % cfg)
 
 
+def separable_integrals(K, rank, seed):
+    """h (symmetric normal deviates, symmetrised) and (ij|kl) = sum over
+    `rank` vectors x of x_i x_j x_k x_l, x uniform in +-[0.5, 1.5)."""
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((K, K))
+    h = 0.5 * (h + h.T)
+    v = np.zeros((K,) * 4)
+    for _ in range(rank):
+        x = rng.uniform(0.5, 1.5, K) * rng.choice([-1.0, 1.0], K)
+        v += np.einsum("i,j,k,l->ijkl", x, x, x, x)
+    return h, v
+
+
+def nearest_neighbour_integrals(K, seed):
+    """h as above and (ij|kl) nonzero (uniform in [0.1, 1)) only when all
+    four indices lie within one pair of neighbouring orbitals."""
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((K, K))
+    h = 0.5 * (h + h.T)
+    v = np.zeros((K,) * 4)
+    for i in range(K):
+        for j in range(K):
+            for k in range(K):
+                for l in range(K):
+                    idx = (i, j, k, l)
+                    if max(idx) - min(idx) <= 1 and v[idx] == 0.0:
+                        x = rng.uniform(0.1, 1.0)
+                        for a, b, c, d in ((i, j, k, l), (j, i, k, l), (i, j, l, k), (j, i, l, k)):
+                            v[a, b, c, d] = v[c, d, a, b] = x
+    return h, v
+
+
 def mps_values(seed, n):
     """Flat stream of n N(0,1) deviates that fills a random initial MPS.
 
