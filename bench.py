@@ -136,6 +136,7 @@ def full_sweeps(args, P, ctx, mpo, mps, prec, K, M, t_setup):
     fl = sum(r["sigma_flops"] for r in rows)
     ss = sum(r["sigma_seconds"] for r in rows)
     out = {"mode": "sweeps", "precision": args.prec, "K": K, "M": M, "n_sweeps": args.sweeps,
+           "compress_tol": args.compress, "mpo_bond_dims": [int(d) for d in mpo.bond_dims()],
            "energy": e, "sweep_energies": [r["energy"] for r in rows],
            "sweep_seconds": [r["wall"] for r in rows], "sigma_tflops": fl / ss / 1e12,
            "sigma_seconds": ss, "sigma_calls": sum(r["sigma_calls"] for r in rows),
@@ -308,6 +309,8 @@ def main():
                          "the FP64 refinement) and compare eigenvalues and sigma time")
     ap.add_argument("--autotune", action="store_true",
                     help="run the launch autotuner at the middle pair before the timed steps")
+    ap.add_argument("--compress", type=float, default=0.0,
+                    help="MPO compression threshold (Hartree); 0 = exact MPO")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-m", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=30)
@@ -345,7 +348,9 @@ def main():
     ctx = P.Context(0)
     t0 = time.time()
     I = config_integrals(3)
-    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
+    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz, compress_tol=args.compress)
+    if args.compress:
+        log("compressed MPO (tol %g, %.1fs): D %s" % (args.compress, time.time() - t0, list(mpo.bond_dims())))
     n = mpo.n_values(M)
     mps = P.Mps.random(ctx, mpo, M, mps_values(c["seed"], n))
     j = K // 2 - 1
@@ -419,14 +424,15 @@ def main():
                    "K": K, "M": M, "D_mid": int(mpo.bond_dims()[j + 1]), "psi_elements": mps.psi_size(),
                    "presweeps": args.presweeps, "presweep_energy": pre_e, "autotuned": tuned,
                    "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
-                   "precision": args.prec},
+                   "precision": args.prec, "mpo_compress_tol": args.compress},
         "sigma_calls": tot["calls"],
         "sigma_model_flops": tot["flops"],
         "step_tflops_wall": tot["flops"] / wall / 1e12,
         "thetas": thetas,
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK[args.prec],
                      "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec],
-                     "traffic": recorded_traffic(args.prec, args.steps, args.warmup, args.presweeps),
+                     "traffic": (None if args.compress else
+                                 recorded_traffic(args.prec, args.steps, args.warmup, args.presweeps)),
                      "kernel": "grouped_gemm<%d,1>" % prec,
                      "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
                      "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},

@@ -81,6 +81,10 @@ typedef struct dmrg_mlp dmrg_mlp;
  * gives a host-only context that can build and query MPOs; every call that
  * needs the GPU then fails with DMRG_E_STATE. */
 dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out);
+/* Release the caller's handle.  States (dmrg_mps) and networks (dmrg_mlp)
+ * created on ctx keep it alive: its stream, events and BLAS handle are
+ * destroyed once the handle and all of them have been released, in any
+ * order.  No call may use the handle after this one. */
 void dmrg_ctx_destroy(dmrg_ctx* ctx);
 /* Text of the last error on ctx (never NULL; "" after success).  With
  * ctx == NULL: why the last dmrg_ctx_create of this thread failed. */

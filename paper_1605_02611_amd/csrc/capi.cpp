@@ -1,6 +1,7 @@
 // C ABI of the DMRG library (declared in include/dmrg.h).  Every entry point
 // catches internal errors, stores the message on the context and returns a
 // status code.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -10,17 +11,23 @@
 
 using namespace dmrg;
 
+// A context lives until its handle has been destroyed and every state and
+// network created on it has been freed (each of them holds a reference), so
+// the order of the *_free / *_destroy calls does not matter.
 struct dmrg_ctx {
     Ctx c;
+    std::atomic<int> refs{1};
 };
 struct dmrg_mpo {
     std::unique_ptr<MPO> m;
 };
 struct dmrg_mps {
     std::unique_ptr<State> st;
+    dmrg_ctx* owner = nullptr;
 };
 struct dmrg_mlp {
     std::unique_ptr<Mlp> m;
+    dmrg_ctx* owner = nullptr;
 };
 
 namespace dmrg {
@@ -142,7 +149,20 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
     return DMRG_OK;
 }
 
-void dmrg_ctx_destroy(dmrg_ctx* ctx) {
+static void dmrg_ctx_destroy_now(dmrg_ctx* ctx);
+namespace {
+dmrg_ctx* ctx_acquire(dmrg_ctx* ctx) {
+    ctx->refs.fetch_add(1);
+    return ctx;
+}
+void ctx_release(dmrg_ctx* ctx) {
+    if (ctx && ctx->refs.fetch_sub(1) == 1) dmrg_ctx_destroy_now(ctx);
+}
+}  // namespace
+
+void dmrg_ctx_destroy(dmrg_ctx* ctx) { ctx_release(ctx); }
+
+static void dmrg_ctx_destroy_now(dmrg_ctx* ctx) {
     if (!ctx) return;
     if (ctx->c.device < 0) {
         delete ctx;
@@ -256,6 +276,7 @@ dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M, const dou
         st->init_random(M, values, n_values);
         auto* r = new dmrg_mps();
         r->st = std::move(st);
+        r->owner = ctx_acquire(ctx);
         *out = r;
     });
 }
@@ -282,6 +303,7 @@ dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n
         st->import_tensors(b, site_values, center);
         auto* r = new dmrg_mps();
         r->st = std::move(st);
+        r->owner = ctx_acquire(ctx);
         *out = r;
     });
 }
@@ -313,11 +335,13 @@ dmrg_status dmrg_mps_center(const dmrg_mps* mps, int* j) {
 
 void dmrg_mps_free(dmrg_mps* mps) {
     if (!mps) return;
-    if (mps->st && mps->st->ctx) {
+    if (mps->st && mps->st->ctx && mps->st->ctx->device >= 0) {
         (void)hipSetDevice(mps->st->ctx->device);
         (void)hipStreamSynchronize(mps->st->ctx->stream);
     }
+    dmrg_ctx* owner = mps->owner;
     delete mps;
+    ctx_release(owner);
 }
 
 dmrg_status dmrg_psi_size(const dmrg_mps* mps, int64_t* n) {
@@ -661,11 +685,18 @@ dmrg_status dmrg_mlp_create(dmrg_ctx* ctx, const float* params, uint64_t seed, i
         auto h = std::make_unique<dmrg_mlp>();
         h->m = std::make_unique<Mlp>();
         h->m->init(ctx->c.stream, params, seed, capacity);
+        h->owner = ctx_acquire(ctx);
         *out = h.release();
     });
 }
 
-void dmrg_mlp_free(dmrg_mlp* mlp) { delete mlp; }
+void dmrg_mlp_free(dmrg_mlp* mlp) {
+    if (!mlp) return;
+    if (mlp->m && mlp->m->s) (void)hipStreamSynchronize(mlp->m->s);
+    dmrg_ctx* owner = mlp->owner;
+    delete mlp;
+    ctx_release(owner);
+}
 
 dmrg_status dmrg_mlp_params(dmrg_ctx* ctx, const dmrg_mlp* mlp, float* out) {
     if (!ctx) return DMRG_E_INVAL;

@@ -386,9 +386,32 @@ def test_solve_reaches_the_lowest_eigenvalue_of_the_dense_effective_hamiltonian(
     bad[3] = np.nan
     with pytest.raises(P.DmrgError) as e:
         mps.set_psi(bad)
-    assert e.value.status == 1
+    status = e.value.status
+    del e  # the traceback would keep this frame (and the GPU objects) in a cycle
+    assert status == 1
     assert np.array_equal(mps.psi(), psi0)
     th, rn, st = mps.solve(P.default_opts(dav_tol=1e-11, dav_max_iter=300))
     _log("solve theta %.14f dense %.14f |r| %.1e iters %d" % (th, lam, rn, st["dav_iters"]))
     assert abs(th - lam) <= 1e-10 * max(1.0, abs(lam))
     assert mps.center() == c
+
+
+def test_states_and_networks_outlive_their_context_handle():
+    """Freeing a state or a network after the handle of its context has been
+    destroyed is safe: the context lives until the last of them is freed."""
+    import gc
+    c2 = P.Context(0)
+    I = chain_integrals(5, seed=3)
+    mpo = P.Mpo(c2, I.h, I.v, 5, 1)
+    M = 8
+    mps = P.Mps.random(c2, mpo, M, mps_values(3, mpo.n_values(M)))
+    net = P.Mlp(c2, seed=1)
+    e0 = mps.energy()
+    c2.close()
+    del mps, net
+    gc.collect()
+    # the runtime is still healthy: a fresh context computes the same energy
+    c3 = P.Context(0)
+    mpo3 = P.Mpo(c3, I.h, I.v, 5, 1)
+    m3 = P.Mps.random(c3, mpo3, M, mps_values(3, mpo3.n_values(M)))
+    assert m3.energy() == e0
