@@ -277,10 +277,6 @@ void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s);
 void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
                          int* rotated, hipStream_t s);
 void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s);
-// block form: slots (job, block-pair index) over blocks of jacobi_block_width() columns
-void launch_jacobi_block(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
-                         int* rotated, hipStream_t s);
-int jacobi_block_width();
 constexpr int kJacobiRoundMin = 160;  // sectors with at least this many columns use the round launches
 
 // ---------------------------------------------------------------------------

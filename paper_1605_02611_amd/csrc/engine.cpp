@@ -938,15 +938,12 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
         const int nb = int(jobs.size() - n_small);
         if (nb > 0) {
             const SvdJob* big = djobs.as<SvdJob>() + n_small;
-            // block pairs (jacobi_block_width() columns per block) of every large sector
-            const int bw = jacobi_block_width();
             std::vector<int2> slots;
             int rounds = 0;
             for (size_t i = n_small; i < jobs.size(); ++i) {
-                const int n = std::min(jobs[i].rows, jobs[i].cols);
-                const int nbk = (n + bw - 1) / bw, nbe = nbk + (nbk & 1);
-                rounds = std::max(rounds, nbe - 1);
-                for (int pi = 0; pi < nbe / 2; ++pi) slots.push_back(int2{int(i - n_small), pi});
+                const int n = std::min(jobs[i].rows, jobs[i].cols), nn = n + (n & 1);
+                rounds = std::max(rounds, nn - 1);
+                for (int pi = 0; pi < nn / 2; ++pi) slots.push_back(int2{int(i - n_small), pi});
             }
             DevBuf dslots(slots.size() * sizeof(int2), s), dlive(nb * sizeof(int), s), drot(nb * sizeof(int), s),
                 dinfo(nb * sizeof(int), s);
@@ -958,7 +955,7 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
                 DMRG_HIP(hipMemcpyAsync(dlive.p, live.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
                 DMRG_HIP(hipMemsetAsync(drot.p, 0, nb * sizeof(int), s));
                 for (int rd = 0; rd < rounds; ++rd)
-                    launch_jacobi_block(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
+                    launch_jacobi_round(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
                                         drot.as<int>(), s);
                 DMRG_HIP(hipMemcpyAsync(rot.data(), drot.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
                 DMRG_HIP(hipStreamSynchronize(s));

@@ -1120,155 +1120,6 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const SvdJob* __restr
     if (jacobi_rotate(A, V, d.m, d.n, p, q, threadIdx.x & 63) && (threadIdx.x & 63) == 0) rotated[sl.x] = 1;
 }
 
-// Block form for large sectors: columns in blocks of kJB; one workgroup
-// per pair of blocks (P, Q) of a round of the round-robin schedule over
-// blocks.  The workgroup forms the Gram matrix G of the (up to 2 kJB)
-// columns, diagonalises it in LDS by parallel two-sided Jacobi (the same
-// rotation as the column version, G' = J^T G J), and applies the
-// accumulated rotation W to the columns of A and V (A <- A W, V <- V W).
-constexpr int kJB = 16;
-constexpr int kJW = 2 * kJB;
-__global__ __launch_bounds__(256) void jacobi_block_kernel(const SvdJob* __restrict__ jobs,
-                                                           const int2* __restrict__ slots, int64_t n_slots,
-                                                           int rd, const int* __restrict__ live,
-                                                           int* __restrict__ rotated) {
-    __shared__ double G[kJW][kJW + 1];
-    __shared__ double W[kJW][kJW + 1];
-    __shared__ double P[64][kJW + 1];  // a chunk of panel rows
-    __shared__ double cs[kJW / 2], sn[kJW / 2];
-    __shared__ int col[kJW];
-    __shared__ int any, w_sh;
-    const int tid = threadIdx.x;
-    const int64_t slot = blockIdx.x;
-    if (slot >= n_slots) return;
-    const int2 sl = slots[slot];
-    if (!live[sl.x]) return;
-    const SvdJob job = jobs[sl.x];
-    const JacobiDims d = jacobi_dims(job);
-    const int m = d.m, n = d.n;
-    const int nbk = (n + kJB - 1) / kJB, nbe = nbk + (nbk & 1);
-    if (rd >= nbe - 1) return;
-    int bp, bq;
-    jacobi_pair_of(nbe, rd, sl.y, bp, bq);
-    if (bp >= nbk || bq >= nbk) return;
-    double* A = job.work;
-    double* V = job.work + int64_t(m) * n;
-    if (tid == 0) {
-        int w = 0;
-        for (int c = bp * kJB; c < min(n, (bp + 1) * kJB); ++c) col[w++] = c;
-        for (int c = bq * kJB; c < min(n, (bq + 1) * kJB); ++c) col[w++] = c;
-        w_sh = w;
-        any = 0;
-    }
-    __syncthreads();
-    const int w = w_sh;
-    // G = panel^T panel over row chunks of 64
-    double g[4] = {0, 0, 0, 0};  // entries tid, tid + 256, ... of the w x w matrix
-    for (int r0 = 0; r0 < m; r0 += 64) {
-        for (int e = tid; e < 64 * kJW; e += 256) {
-            const int r = e / kJW, c = e % kJW;
-            P[r][c] = (r0 + r < m && c < w) ? A[int64_t(col[c]) * m + r0 + r] : 0.0;
-        }
-        __syncthreads();
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int a = e / kJW, b = e % kJW;
-            double acc = g[i];
-            for (int r = 0; r < 64; ++r) acc += P[r][a] * P[r][b];
-            g[i] = acc;
-        }
-        __syncthreads();
-    }
-    for (int i = 0; i < 4; ++i) {
-        const int e = tid + 256 * i;
-        G[e / kJW][e % kJW] = g[i];
-        W[e / kJW][e % kJW] = (e / kJW == e % kJW) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // two-sided parallel Jacobi on G (w' = w rounded up to even columns)
-    const int we = w + (w & 1);
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        __shared__ int off;
-        if (tid == 0) off = 0;
-        __syncthreads();
-        for (int e = tid; e < w * w; e += 256) {
-            const int a = e / w, b = e % w;
-            if (a < b && G[a][b] != 0.0 && fabs(G[a][b]) > 1e-15 * sqrt(G[a][a] * G[b][b])) off = 1;
-        }
-        __syncthreads();
-        if (!off) break;
-        if (tid == 0) any = 1;
-        for (int r = 0; r < we - 1; ++r) {
-            if (tid < we / 2) {
-                int p, q;
-                jacobi_pair_of(we, r, tid, p, q);
-                double c = 1.0, s = 0.0;
-                if (p < w && q < w) {
-                    const double al = G[p][p], be = G[q][q], ga = G[p][q];
-                    if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = c * t;
-                    }
-                }
-                cs[tid] = c;
-                sn[tid] = s;
-            }
-            __syncthreads();
-            // columns: G <- G J, W <- W J
-            for (int e = tid; e < (we / 2) * w; e += 256) {
-                const int k = e / w, i = e % w;
-                int p, q;
-                jacobi_pair_of(we, r, k, p, q);
-                if (p >= w || q >= w) continue;
-                const double c = cs[k], s = sn[k];
-                const double gp = G[i][p], gq = G[i][q];
-                G[i][p] = c * gp - s * gq;
-                G[i][q] = s * gp + c * gq;
-                const double wp = W[i][p], wq = W[i][q];
-                W[i][p] = c * wp - s * wq;
-                W[i][q] = s * wp + c * wq;
-            }
-            __syncthreads();
-            // rows: G <- J^T G
-            for (int e = tid; e < (we / 2) * w; e += 256) {
-                const int k = e / w, i = e % w;
-                int p, q;
-                jacobi_pair_of(we, r, k, p, q);
-                if (p >= w || q >= w) continue;
-                const double c = cs[k], s = sn[k];
-                const double gp = G[p][i], gq = G[q][i];
-                G[p][i] = c * gp - s * gq;
-                G[q][i] = s * gp + c * gq;
-            }
-            __syncthreads();
-        }
-    }
-    if (!any) return;  // the block pair was orthogonal already (uniform)
-    if (tid == 0) rotated[sl.x] = 1;
-    // A panel <- A panel W and V panel <- V panel W, chunks of 64 rows
-    for (int part = 0; part < 2; ++part) {
-        double* X = part == 0 ? A : V;
-        const int rows = part == 0 ? m : n;
-        for (int r0 = 0; r0 < rows; r0 += 64) {
-            for (int e = tid; e < 64 * kJW; e += 256) {
-                const int r = e / kJW, c = e % kJW;
-                P[r][c] = (r0 + r < rows && c < w) ? X[int64_t(col[c]) * rows + r0 + r] : 0.0;
-            }
-            __syncthreads();
-            for (int e = tid; e < 64 * kJW; e += 256) {
-                const int r = e % 64, c = e / 64;  // consecutive threads: consecutive rows of one column
-                if (r0 + r >= rows || c >= w) continue;
-                double acc = 0.0;
-                for (int a = 0; a < w; ++a) acc += P[r][a] * W[a][c];
-                X[int64_t(col[c]) * rows + r0 + r] = acc;
-            }
-            __syncthreads();
-        }
-    }
-}
-
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_finish_kernel(const SvdJob* __restrict__ jobs,
                                                                       const int* __restrict__ info) {
     const SvdJob job = jobs[blockIdx.x];
@@ -1507,14 +1358,6 @@ void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s) {
     hipLaunchKernelGGL(jacobi_init_kernel, dim3(n_jobs), dim3(kJacobiThreads), 0, s, jobs);
     DMRG_HIP(hipGetLastError());
 }
-void launch_jacobi_block(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
-                         int* rotated, hipStream_t s) {
-    if (n_slots <= 0) return;
-    hipLaunchKernelGGL(jacobi_block_kernel, dim3(unsigned(n_slots)), dim3(256), 0, s, jobs, slots, n_slots, rd,
-                       live, rotated);
-    DMRG_HIP(hipGetLastError());
-}
-int jacobi_block_width() { return kJB; }
 void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
                          int* rotated, hipStream_t s) {
     if (n_slots <= 0) return;
