@@ -1792,7 +1792,7 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool
     auto sec = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
     const auto t0 = clk::now();
     DavOut dv{0, 0, 0};
-    double sig0 = stt.sigma_seconds;
+    const double sig0 = stt.sigma_seconds, pass1_0 = stt.pass1_seconds;
     auto t1 = t0, t2 = t0;
     if (solve) {
         prepare();
@@ -1808,13 +1808,13 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool
         t1 = t2 = t0;
     }
     const auto t3 = clk::now();
-    return finish_step(M, forward, o, stt, solve, dv, sec(t0, t1), sec(t1, t2), sec(t2, t3), sig0);
+    return finish_step(M, forward, o, stt, solve, dv, sec(t0, t1), sec(t1, t2), sec(t2, t3), sig0, pass1_0);
 }
 
 // Truncation (sector SVD), new site tensors, environment update and the next
 // two-site guess, after the two-site vector has been solved for.
 double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool solve,
-                          const DavOut& dv, double tb, double td, double tv, double sig0) {
+                          const DavOut& dv, double tb, double td, double tv, double sig0, double pass1_0) {
     const int K = mpo->K;
     const int j = center;
     hipStream_t s = ctx->stream;
@@ -2011,7 +2011,8 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
                 "update+next %.3fs total %.3fs\n",
                 j, forward ? "fwd" : "bwd", (long long)ts_n_at_solve, ts_nq_at_solve, dv.iters,
                 dv.theta, dv.rnorm, bonds[j + 1].total, stt.discarded, tb, td, tv,
-                stt.sigma_seconds - sig0, stt.pass1_seconds, sec(t3, t4), sec(t4, t5),
+                stt.sigma_seconds - sig0, pass1_0 >= 0.0 ? stt.pass1_seconds - pass1_0 : 0.0, sec(t3, t4),
+                sec(t4, t5),
                 tb + td + tv + sec(t3, t5));
     }
     return dv.theta;

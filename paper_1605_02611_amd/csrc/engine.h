@@ -347,7 +347,7 @@ class State {
     // of the effective Hamiltonian; no truncation, the center stays
     DavOut solve(const SweepOpts& o, StepStats& st);
     double finish_step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve,
-                       const DavOut& dv, double tb, double td, double tv, double sig0);
+                       const DavOut& dv, double tb, double td, double tv, double sig0, double pass1_0 = -1.0);
     double energy();
     void env_dense(int side, int bond, std::vector<double>& out);
 

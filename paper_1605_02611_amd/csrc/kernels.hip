@@ -77,6 +77,17 @@ __device__ inline int64_t xcd_chunk_task(int64_t b, int64_t c) {
     return (x + 8 * (slot / c)) * c + slot % c;
 }
 
+// Row pitch of the LDS operand tiles As[KS][pitch], Bs[KS][pitch].  A
+// K-major operand is staged with 16 lanes writing one column at rows 0..15,
+// so the pitch decides the bank of every row: 64-bit rows 81 elements apart
+// (TS + 17) put those 16 writes in 16 distinct bank pairs and keep the MFMA
+// reads of 16 consecutive elements per row conflict-free (a pitch of TS + 4
+// = 68 made the writes 4-way conflicts).  32-bit tiles keep TS + 4.
+template <int MODE>
+__host__ __device__ constexpr int lds_pitch(int ts) {
+    return MODE == 0 ? ts + 17 : ts + 4;
+}
+
 // One packed K column of a grouped-GEMM step (see grouped_gemm).
 template <class T>
 struct PackCol {
@@ -102,8 +113,8 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
     constexpr int NT = (TS / 32) * (TS / 32) * 64;
-    __shared__ T As[KS][TS + 4];
-    __shared__ T Bs[KS][TS + 4];
+    __shared__ T As[KS][lds_pitch<MODE>(TS)];
+    __shared__ T Bs[KS][lds_pitch<MODE>(TS)];
 
     // xcd: 0 block order, 1 one contiguous run per XCD, c > 1 runs of c tasks
     const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
@@ -497,8 +508,8 @@ __global__ __launch_bounds__(256) void persistent_gemm(const GemmTask* __restric
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
     constexpr int TS = 64, NT = 256, PER = TS * KS / NT;
-    __shared__ T As[KS][TS + 4];
-    __shared__ T Bs[KS][TS + 4];
+    __shared__ T As[KS][lds_pitch<MODE>(TS)];
+    __shared__ T Bs[KS][lds_pitch<MODE>(TS)];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
