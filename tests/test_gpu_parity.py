@@ -16,6 +16,7 @@ torch = pytest.importorskip("torch")
 
 import paper_1605_02611_amd as P  # noqa: E402
 from oracle import dmrg as od  # noqa: E402
+from oracle import fermions as fm  # noqa: E402
 from tests import helpers as H  # noqa: E402
 from workloads import (CONFIGS, chain_integrals, config_integrals, mps_values,  # noqa: E402
                        random_integrals_cfg1)
@@ -415,3 +416,42 @@ def test_states_and_networks_outlive_their_context_handle():
     mpo3 = P.Mpo(c3, I.h, I.v, 5, 1)
     m3 = P.Mps.random(c3, mpo3, M, mps_values(3, mpo3.n_values(M)))
     assert m3.energy() == e0
+
+
+@pytest.mark.parametrize("K,N,tsz,M", [
+    (2, 2, 0, 16),   # one pair: the whole system is the two-site block
+    (2, 1, -1, 4),   # one electron, spin down
+    (4, 0, 0, 8),    # vacuum: one state, E = 0
+    (4, 8, 0, 8),    # completely filled: one state
+    (5, 1, 1, 16),   # one electron: the lowest eigenvalue of h
+    (5, 5, 5, 16),   # fully polarised: spinless fermions
+    (4, 4, 0, 1),    # bond dimension 1: product states
+    (3, 3, 1, 64),   # M above every sector's full dimension
+])
+def test_degenerate_systems_match_oracle(ctx, K, N, tsz, M):
+    _log("degenerate case K=%d N=%d 2Sz=%d M=%d" % (K, N, tsz, M))
+    I = chain_integrals(K, n_elec=max(N, 1), seed=50 + K)
+    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(7, od.n_mps_values(K, N, tsz, M)))
+    thetas = []
+    for _ in range(2):
+        d.sweep()
+        thetas.append(d.log[-2]["theta"])  # the sweep's last two-site eigenvalue
+    mpo = P.Mpo(ctx, I.h, I.v, N, tsz)
+    mps = P.Mps.random(ctx, mpo, M, mps_values(7, mpo.n_values(M)))
+    stats, _ = mps.sweep(M, 2)
+    assert abs(mps.energy() - d.energy()) < 1e-8
+    assert np.abs(np.array([s["energy"] for s in stats]) - thetas).max() < 1e-8
+    for k in range(K + 1):
+        got = [tuple(t) for t in mps.bond(k)]
+        ref = [tuple(q) + (dd,) for q, dd in d.bond_sectors(k)]
+        if M == 1:
+            # sectors (N, 2S_z) and (N, -2S_z) tie exactly at 2S_z = 0: either
+            # is a correct choice, so compare up to the sign of 2S_z
+            got = sorted((n, abs(sz), dd) for n, sz, dd in got)
+            ref = sorted((n, abs(sz), dd) for n, sz, dd in ref)
+        assert got == ref, k
+    if N == 1:  # one electron: the lowest eigenvalue of the one-body matrix
+        assert abs(mps.energy() - np.linalg.eigvalsh(I.h)[0]) < 1e-8
+    if N in (0, 2 * K):
+        e_fci = fm.fci_energy(I.h, I.v, N, tsz)
+        assert abs(mps.energy() - e_fci) < 1e-10
