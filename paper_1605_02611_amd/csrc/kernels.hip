@@ -105,7 +105,7 @@ struct PackCol {
 // registers while the current step is multiplied).  XCD: task order
 // remapped per XCD (see xcd_task).
 template <int MODE, int ROLE, int TS, int VAR>
-__global__ __launch_bounds__((TS / 32) * (TS / 32) * 64) void grouped_gemm(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void grouped_gemm(const GemmTask* __restrict__ tasks,
                                                                            const GemmTerm* __restrict__ terms,
                                                                            void* const* __restrict__ bases,
                                                                            const int* __restrict__ active, int xcd,
