@@ -360,9 +360,10 @@ def main():
     if not args.sweeps and args.presweeps:
         # untimed: bring the random state close to the ground state first, so
         # that the timed steps see the sector structure of a production sweep
-        st, _ = mps.sweep(M, args.presweeps, opts)
-        pre_e = st[-1]["energy"]
-        log("presweeps %d: E %.10f (%.1fs)" % (args.presweeps, pre_e, time.time() - t0))
+        for i in range(args.presweeps):  # one at a time, a progress line each
+            st, _ = mps.sweep(M, 1, opts)
+            pre_e = st[-1]["energy"]
+            log("presweep %d: E %.10f (%.1fs)" % (i, pre_e, time.time() - t0))
     for _ in range(0 if args.sweeps else j):
         mps.move(True)
     log("setup %.1fs: center %d, psi %d, D_mid %d" % (time.time() - t0, mps.center(), mps.psi_size(),
