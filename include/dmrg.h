@@ -60,7 +60,9 @@ typedef enum {
     DMRG_E_HIP = 3,     /* a HIP / rocSOLVER call failed */
     DMRG_E_NOCONV = 4,  /* an eigensolver hit its iteration limit (result kept) */
     DMRG_E_NUMERIC = 5, /* NaN or Inf in a vector or an SVD failure */
-    DMRG_E_STATE = 6    /* call made on an object in the wrong state */
+    DMRG_E_STATE = 6,   /* call made on an object in the wrong state */
+    DMRG_E_IO = 7       /* a file could not be opened, read or written, or is not
+                           an MPS file of the format below */
 } dmrg_status;
 
 typedef enum {
@@ -167,6 +169,24 @@ dmrg_status dmrg_mps_bond(const dmrg_mps* mps, int bond, int32_t* n, int32_t* se
 /* Current center pair j (the two-site vector lives on sites j, j+1). */
 dmrg_status dmrg_mps_center(const dmrg_mps* mps, int* j);
 void dmrg_mps_free(dmrg_mps* mps);
+
+/* Checkpoint and resume of a state (its bonds, site tensors, center pair and
+ * two-site vector; environments are rebuilt on load).  File layout,
+ * little-endian, no padding:
+ *   8 bytes  "DMRGMPS" followed by the version byte 1
+ *   int32    K, N, 2S_z, center pair j
+ *   per bond k = 0..K: int32 n, then n x (int32 N, int32 2S_z, int32 dim),
+ *            sectors sorted by (N, 2S_z)
+ *   int64    n_site, then n_site doubles: the site tensors of sites 0..K-1 in
+ *            the fine-block layout above
+ *   int64    n_psi, then n_psi doubles: the two-site vector at (j, j+1) in
+ *            the merged sector layout above
+ * A loaded state continues bit for bit as the saved one would.  Errors:
+ * DMRG_E_IO (open, read or write failure, wrong magic, truncated file, sizes
+ * inconsistent with the bonds), DMRG_E_INVAL (K, N or 2S_z differ from the
+ * MPO's, non-finite values, bonds that break the import rules). */
+dmrg_status dmrg_mps_save(dmrg_ctx* ctx, const dmrg_mps* mps, const char* path);
+dmrg_status dmrg_mps_load(dmrg_ctx* ctx, const dmrg_mpo* mpo, const char* path, dmrg_mps** out);
 
 /* ---- sigma (Eq. Hpartition at the center bond) --------------------------- */
 

@@ -19,7 +19,7 @@ P = C.POINTER
 
 DMRG_FP64, DMRG_FP32, DMRG_BF16 = 0, 1, 2
 STATUS = {0: "DMRG_OK", 1: "DMRG_E_INVAL", 2: "DMRG_E_NOMEM", 3: "DMRG_E_HIP",
-          4: "DMRG_E_NOCONV", 5: "DMRG_E_NUMERIC", 6: "DMRG_E_STATE"}
+          4: "DMRG_E_NOCONV", 5: "DMRG_E_NUMERIC", 6: "DMRG_E_STATE", 7: "DMRG_E_IO"}
 
 
 class MpoOpts(C.Structure):
@@ -59,6 +59,8 @@ SIGNATURES = {
     "dmrg_mps_bond": (c_int, [c_void_p, c_int, P(c_int32), P(c_int32)]),
     "dmrg_mps_center": (c_int, [c_void_p, P(c_int)]),
     "dmrg_mps_free": (None, [c_void_p]),
+    "dmrg_mps_save": (c_int, [c_void_p, c_void_p, c_char_p]),
+    "dmrg_mps_load": (c_int, [c_void_p, c_void_p, c_char_p, P(c_void_p)]),
     "dmrg_psi_size": (c_int, [c_void_p, P(c_int64)]),
     "dmrg_psi_export": (c_int, [c_void_p, c_void_p, P(c_double)]),
     "dmrg_sigma": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, P(c_double)]),

@@ -179,6 +179,17 @@ class Mps:
         ctx.check(ctx.lib.dmrg_mps_import(ctx.h, mpo.h, np_, sp, vp, center, C.byref(out)))
         return cls(ctx, mpo, out)
 
+    def save(self, path):
+        """Checkpoint (dmrg_mps_save)."""
+        self.ctx.check(self.lib.dmrg_mps_save(self.ctx.h, self.h, str(path).encode()))
+
+    @classmethod
+    def load(cls, ctx, mpo, path):
+        """Resume a checkpoint (dmrg_mps_load)."""
+        out = C.c_void_p()
+        ctx.check(ctx.lib.dmrg_mps_load(ctx.h, mpo.h, str(path).encode(), C.byref(out)))
+        return cls(ctx, mpo, out)
+
     def bond(self, k):
         n = C.c_int32()
         self.ctx.check(self.lib.dmrg_mps_bond(self.h, k, C.byref(n), None))

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "../../include/dmrg.h"
@@ -301,6 +302,137 @@ dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n
         }
         auto st = std::make_unique<State>(&ctx->c, mpo->m.get());
         st->import_tensors(b, site_values, center);
+        auto* r = new dmrg_mps();
+        r->st = std::move(st);
+        r->owner = ctx_acquire(ctx);
+        *out = r;
+    });
+}
+
+namespace {
+
+// MPS file: little-endian, no padding.
+//   8 bytes  magic "DMRGMPS" + version byte 1
+//   int32    K, N, 2S_z, center pair j
+//   per bond k = 0..K: int32 n; n x (int32 N, int32 2S_z, int32 dim), sorted
+//   int64    n_site, then n_site doubles: the site tensors in the fine-block
+//            layout (sites 0..K-1)
+//   int64    n_psi, then n_psi doubles: the two-site vector at (j, j+1) in
+//            the merged sector layout
+constexpr char kMpsMagic[8] = {'D', 'M', 'R', 'G', 'M', 'P', 'S', 1};
+
+struct File {
+    FILE* f = nullptr;
+    File(const char* path, const char* mode) : f(std::fopen(path, mode)) {
+        if (!f) throw Error(E_IO, std::string("cannot open ") + path);
+    }
+    ~File() {
+        if (f) std::fclose(f);
+    }
+    void put(const void* p, size_t n) {
+        if (n && std::fwrite(p, 1, n, f) != n) throw Error(E_IO, "write failed");
+    }
+    void get(void* p, size_t n) {
+        if (n && std::fread(p, 1, n, f) != n) throw Error(E_IO, "file truncated");
+    }
+    int32_t get_i32() {
+        int32_t x;
+        get(&x, sizeof(x));
+        return x;
+    }
+    int64_t get_i64() {
+        int64_t x;
+        get(&x, sizeof(x));
+        return x;
+    }
+};
+
+}  // namespace
+
+dmrg_status dmrg_mps_save(dmrg_ctx* ctx, const dmrg_mps* mps, const char* path) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && path, "null argument");
+        use_device(ctx->c);
+        const State& st = *mps->st;
+        const int K = st.mpo->K;
+        std::vector<double> sites, psi(static_cast<size_t>(std::max<int64_t>(0, st.ts.n)));
+        st.export_tensors(sites);
+        if (st.ts.n > 0)
+            DMRG_HIP(hipMemcpyAsync(psi.data(), st.psi.p, st.ts.n * sizeof(double), hipMemcpyDeviceToHost,
+                                    ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
+        File F(path, "wb");
+        F.put(kMpsMagic, 8);
+        const int32_t head[4] = {K, st.mpo->n_elec, st.mpo->two_sz, st.center};
+        F.put(head, sizeof(head));
+        for (int k = 0; k <= K; ++k) {
+            const Bond& b = st.bonds[k];
+            const int32_t n = int32_t(b.q.size());
+            F.put(&n, 4);
+            for (int i = 0; i < n; ++i) {
+                const int32_t t[3] = {b.q[i].n, b.q[i].sz, b.dim[i]};
+                F.put(t, sizeof(t));
+            }
+        }
+        const int64_t ns = int64_t(sites.size()), np = int64_t(psi.size());
+        F.put(&ns, 8);
+        F.put(sites.data(), sites.size() * sizeof(double));
+        F.put(&np, 8);
+        F.put(psi.data(), psi.size() * sizeof(double));
+        if (std::fflush(F.f) != 0) throw Error(E_IO, "write failed");
+    });
+}
+
+dmrg_status dmrg_mps_load(dmrg_ctx* ctx, const dmrg_mpo* mpo, const char* path, dmrg_mps** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mpo && path && out, "null argument");
+        const MPO& m = *mpo->m;
+        File F(path, "rb");
+        char magic[8];
+        F.get(magic, 8);
+        if (std::memcmp(magic, kMpsMagic, 8) != 0) throw Error(E_IO, "not an MPS file of this format");
+        int32_t head[4];
+        F.get(head, sizeof(head));
+        require(head[0] == m.K && head[1] == m.n_elec && head[2] == m.two_sz,
+                "the file's K, N or 2S_z differ from the MPO's");
+        std::vector<std::vector<std::pair<QN, int>>> b(m.K + 1);
+        int64_t expect = 0;
+        for (int k = 0; k <= m.K; ++k) {
+            const int32_t n = F.get_i32();
+            if (n < 1 || n > (1 << 20)) throw Error(E_IO, "bad sector count");
+            for (int i = 0; i < n; ++i) {
+                int32_t t[3];
+                F.get(t, sizeof(t));
+                require(t[2] >= 1, "sector dimensions must be >= 1");
+                b[k].push_back({QN{t[0], t[1]}, t[2]});
+            }
+        }
+        for (int j = 0; j < m.K; ++j)
+            for (const auto& [ql, ml] : b[j])
+                for (int s = 0; s < 4; ++s)
+                    for (const auto& [qr, mr] : b[j + 1])
+                        if (qr == ql + kSiteQN[s]) expect += int64_t(ml) * mr;
+        const int64_t ns = F.get_i64();
+        if (ns != expect) throw Error(E_IO, "site tensor size does not match the bonds");
+        std::vector<double> sites(static_cast<size_t>(ns));
+        F.get(sites.data(), sites.size() * sizeof(double));
+        const int64_t np = F.get_i64();
+        if (np < 0 || np > (int64_t(1) << 34)) throw Error(E_IO, "bad two-site vector size");
+        std::vector<double> psi(static_cast<size_t>(np));
+        F.get(psi.data(), psi.size() * sizeof(double));
+        for (double x : sites) require(std::isfinite(x), "non-finite site tensor value");
+        for (double x : psi) require(std::isfinite(x), "non-finite two-site vector value");
+        require(m.K >= 2, "two-site DMRG needs K >= 2");
+        use_device(ctx->c);  // the file is checked first, also on a host-only context
+        auto st = std::make_unique<State>(&ctx->c, mpo->m.get());
+        st->import_tensors(b, sites.data(), head[3]);
+        require(st->ts.n == np, "two-site vector size does not match the bonds");
+        if (np > 0)
+            DMRG_HIP(hipMemcpyAsync(st->psi.p, psi.data(), np * sizeof(double), hipMemcpyHostToDevice,
+                                    ctx->c.stream));
+        DMRG_HIP(hipStreamSynchronize(ctx->c.stream));
         auto* r = new dmrg_mps();
         r->st = std::move(st);
         r->owner = ctx_acquire(ctx);

@@ -20,7 +20,7 @@ struct Error : std::runtime_error {
     int code;
     Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
-enum { E_INVAL = 1, E_NOMEM = 2, E_HIP = 3, E_NOCONV = 4, E_NUMERIC = 5, E_STATE = 6 };
+enum { E_INVAL = 1, E_NOMEM = 2, E_HIP = 3, E_NOCONV = 4, E_NUMERIC = 5, E_STATE = 6, E_IO = 7 };
 
 #define DMRG_HIP(call)                                                             \
     do {                                                                           \

@@ -855,6 +855,35 @@ static void merge_site(const BondL& bl, const BondL& br, int form, const double*
         }
 }
 
+// inverse of merge_site: the fine blocks of one site appended to vals
+static void unmerge_site(const BondL& bl, const BondL& br, const Merged& Mg, const std::vector<double>& host,
+                         std::vector<double>& vals) {
+    for (size_t il = 0; il < bl.q.size(); ++il)
+        for (int s = 0; s < 4; ++s) {
+            const QN qr = bl.q[il] + kSiteQN[s];
+            const int ir = br.find(qr);
+            if (ir < 0) continue;
+            const int ml = bl.dim[il], mr = br.dim[ir];
+            if (Mg.form == 1) {
+                const int iq = Mg.find(qr);
+                require(iq >= 0, "internal: site sector missing");
+                const Space sp = sys_space(bl, qr);
+                const Seg& sg = sp.segs[sp.seg_of[s]];
+                for (int a = 0; a < ml; ++a)
+                    for (int b = 0; b < mr; ++b)
+                        vals.push_back(host[Mg.off[iq] + int64_t(sg.off + a) * Mg.cols[iq] + b]);
+            } else {
+                const int iq = Mg.find(bl.q[il]);
+                require(iq >= 0, "internal: site sector missing");
+                const Space sp = env_space(br, bl.q[il]);
+                const Seg& sg = sp.segs[sp.seg_of[s]];
+                for (int a = 0; a < ml; ++a)
+                    for (int b = 0; b < mr; ++b)
+                        vals.push_back(host[Mg.off[iq] + int64_t(a) * Mg.cols[iq] + sg.off + b]);
+            }
+        }
+}
+
 static void upload(Merged& Mg, const std::vector<double>& host, hipStream_t s) {
     Mg.buf.alloc(std::max<int64_t>(1, Mg.size) * sizeof(double), s);
     DMRG_HIP(hipMemcpyAsync(Mg.buf.p, host.data(), std::max<int64_t>(1, Mg.size) * sizeof(double),
@@ -1160,6 +1189,21 @@ void State::import_tensors(const std::vector<std::vector<std::pair<QN, int>>>& b
         R[k] = decimate_right(Zb, k, site[k]);
     }
     prepared = false;
+}
+
+void State::export_tensors(std::vector<double>& values) const {
+    hipStream_t s = ctx->stream;
+    values.clear();
+    std::vector<double> host;
+    for (int j = 0; j < mpo->K; ++j) {
+        const Merged& Mg = site[j];
+        require(Mg.form == 1 || Mg.form == 2, "internal: site tensor without a layout");
+        host.assign(std::max<int64_t>(1, Mg.size), 0.0);
+        if (Mg.size > 0)
+            DMRG_HIP(hipMemcpyAsync(host.data(), Mg.buf.p, Mg.size * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipStreamSynchronize(s));
+        unmerge_site(bonds[j], bonds[j + 1], Mg, host, values);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -335,6 +335,8 @@ class State {
 
     // setup
     void init_random(int M, const double* values, int64_t n_values);
+    // site tensors of all sites in the fine-block layout of import_tensors
+    void export_tensors(std::vector<double>& values) const;
     void import_tensors(const std::vector<std::vector<std::pair<QN, int>>>& bonds_in,
                         const double* values, int center_j);
     // operations

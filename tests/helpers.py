@@ -86,3 +86,52 @@ def merged_to_dense(vec, lab_l, lab_r):
     out = np.zeros(int(np.prod(shape)))
     out[idx] = vec
     return out.reshape(shape)
+
+
+# --- MPS checkpoint files (the layout documented with dmrg_mps_save) ------------------
+
+MPS_MAGIC = b"DMRGMPS\x01"
+
+
+def write_mps_file(path, K, N, two_sz, center, bonds, site_values, psi):
+    """bonds: per k a list of (N, 2Sz, dim); site_values, psi: flat FP64."""
+    import struct
+    with open(path, "wb") as f:
+        f.write(MPS_MAGIC)
+        f.write(struct.pack("<4i", K, N, two_sz, center))
+        for b in bonds:
+            f.write(struct.pack("<i", len(b)))
+            for t in b:
+                f.write(struct.pack("<3i", *t))
+        sv = np.ascontiguousarray(site_values, dtype="<f8")
+        f.write(struct.pack("<q", sv.size))
+        f.write(sv.tobytes())
+        pv = np.ascontiguousarray(psi, dtype="<f8")
+        f.write(struct.pack("<q", pv.size))
+        f.write(pv.tobytes())
+
+
+def read_mps_file(path):
+    import struct
+    with open(path, "rb") as f:
+        data = f.read()
+    assert data[:8] == MPS_MAGIC
+    pos = 8
+    K, N, tsz, center = struct.unpack_from("<4i", data, pos)
+    pos += 16
+    bonds = []
+    for _ in range(K + 1):
+        (n,) = struct.unpack_from("<i", data, pos)
+        pos += 4
+        bonds.append([tuple(struct.unpack_from("<3i", data, pos + 12 * i)) for i in range(n)])
+        pos += 12 * n
+    (ns,) = struct.unpack_from("<q", data, pos)
+    pos += 8
+    sites = np.frombuffer(data, dtype="<f8", count=ns, offset=pos).copy()
+    pos += 8 * ns
+    (npsi,) = struct.unpack_from("<q", data, pos)
+    pos += 8
+    psi = np.frombuffer(data, dtype="<f8", count=npsi, offset=pos).copy()
+    pos += 8 * npsi
+    assert pos == len(data)
+    return dict(K=K, N=N, two_sz=tsz, center=center, bonds=bonds, sites=sites, psi=psi)

@@ -455,3 +455,60 @@ def test_degenerate_systems_match_oracle(ctx, K, N, tsz, M):
     if N in (0, 2 * K):
         e_fci = fm.fci_energy(I.h, I.v, N, tsz)
         assert abs(mps.energy() - e_fci) < 1e-10
+
+
+def test_checkpoint_resumes_bit_for_bit(ctx, tmp_path):
+    """dmrg_mps_save / dmrg_mps_load in the middle of a sweep: the loaded state
+    has the same bonds, vector and energy, and the next steps give the same
+    eigenvalues to the last bit."""
+    K, N, M = 8, 8, 24
+    I = chain_integrals(K, n_elec=N, seed=12)
+    mpo = P.Mpo(ctx, I.h, I.v, N, 0)
+    a = P.Mps.random(ctx, mpo, M, mps_values(12, mpo.n_values(M)))
+    a.sweep(M, 1)
+    for _ in range(3):
+        a.step(M, True)
+    path = tmp_path / "mid.mps"
+    a.save(path)
+    b = P.Mps.load(ctx, mpo, path)
+    assert b.center() == a.center() == 3
+    for k in range(K + 1):
+        assert b.bond(k) == a.bond(k)
+    assert np.array_equal(b.psi(), a.psi())
+    assert b.energy() == a.energy()
+    for fwd in (True, True, False):
+        ta, _ = a.step(M, fwd)
+        tb, _ = b.step(M, fwd)
+        assert ta == tb
+    assert np.array_equal(b.psi(), a.psi())
+
+
+def test_checkpoint_format_is_shared_with_the_oracle(ctx, tmp_path):
+    """A file written from the oracle's tensors (test writer) loads into the
+    oracle's vector, energy and environments; a state imported from the same
+    tensors saves exactly those tensors (test reader)."""
+    K, N, tsz, M, c = 6, 6, 0, 12, 2
+    I, d = _oracle_case(K, N, tsz, M, 61, "chain")
+    for j in range(c):
+        d.step(j, True, False)
+    mpo = P.Mpo(ctx, I.h, I.v, N, tsz)
+    bonds = [H.sectors(l) for l in d.labels]
+    fine = np.concatenate([H.site_fine_blocks(d.A[j], d.labels[j], d.labels[j + 1]) for j in range(K)])
+    psi = H.dense_to_merged(d.psi, d.labels[c], d.labels[c + 2])
+    path = tmp_path / "oracle.mps"
+    H.write_mps_file(path, K, N, tsz, c, bonds, fine, psi)
+    m = P.Mps.load(ctx, mpo, path)
+    assert np.array_equal(m.psi(), psi)
+    for k in range(c + 2, K + 1):
+        assert np.abs(m.env(1, k) - d.Renv[k]).max() < 1e-11
+    x = d.psi  # <psi|H|psi> / <psi|psi> with the oracle's effective Hamiltonian at pair c
+    e_ref = float(np.vdot(x, d.sigma(c, x)) / np.vdot(x, x))
+    assert abs(m.energy() - e_ref) < 1e-11 * max(1.0, abs(e_ref))
+    imp = P.Mps.from_tensors(ctx, mpo, bonds, fine, c)
+    out = tmp_path / "lib.mps"
+    imp.save(out)
+    r = H.read_mps_file(out)
+    assert (r["K"], r["N"], r["two_sz"], r["center"]) == (K, N, tsz, c)
+    assert [list(map(tuple, b)) for b in r["bonds"]] == bonds
+    assert np.array_equal(r["sites"], fine)
+    assert np.abs(r["psi"] - psi).max() < 1e-12
