@@ -510,13 +510,29 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vecto
         for (int j = 0; j < n; ++j) r += std::fabs(a(i, j));
         anorm = std::max(anorm, r);
     }
+    // work on A / ||A|| (eigenvectors unchanged, eigenvalues rescaled at the
+    // end) so that no intermediate under- or overflows
+    const double unscale = anorm > 0.0 ? anorm : 1.0;
+    for (double& x : A) x /= unscale;
+    anorm = anorm > 0.0 ? 1.0 : 0.0;
     std::vector<double> v(n), p(n), w(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;  // x = A[k+1.., k]
+        double tmax = 0.0, scale = 0.0;
+        for (int i = 0; i < m; ++i) {
+            v[i] = a(k + 1 + i, k);
+            if (i > 0) tmax = std::max(tmax, std::fabs(v[i]));
+        }
+        if (tmax <= 1e-3 * std::numeric_limits<double>::epsilon() * anorm) {
+            // a negligible sub-column (below the rounding level of A): drop it
+            // rather than build a reflector from underflowing squares
+            for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+            continue;
+        }
+        scale = std::max(tmax, std::fabs(v[0]));
         double tail = 0.0;
-        for (int i = 0; i < m; ++i) v[i] = a(k + 1 + i, k);
+        for (int i = 0; i < m; ++i) v[i] /= scale;  // the reflector is scale-free
         for (int i = 1; i < m; ++i) tail += v[i] * v[i];
-        if (tail == 0.0) continue;
         const double alpha = std::sqrt(v[0] * v[0] + tail);
         const double sgn = v[0] >= 0.0 ? 1.0 : -1.0;
         v[0] += sgn * alpha;
@@ -536,7 +552,7 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vecto
             const double vi = v[i], wi = w[i];
             for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
         }
-        a(k + 1, k) = a(k, k + 1) = -sgn * alpha;
+        a(k + 1, k) = a(k, k + 1) = -sgn * alpha * scale;
         for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
         for (int r = 0; r < n; ++r) {
             double* zr = &Z[size_t(r) * n + k + 1];
@@ -589,6 +605,7 @@ void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vecto
             }
         }
     }
+    for (double& x : d) x *= unscale;
     lam = d;
 }
 

@@ -12,7 +12,8 @@ import pytest
 
 import paper_1605_02611_amd as P
 from oracle import fermions as fm, mpo as omp
-from workloads import chain_integrals, nearest_neighbour_integrals, separable_integrals
+from workloads import (chain_integrals, exponential_density_integrals, nearest_neighbour_integrals,
+                       separable_integrals)
 
 NAMES = ["I", "H", "Cd", "C", "SL", "SLd", "A", "Ad", "B", "P", "Pd", "Q"]
 
@@ -53,6 +54,18 @@ def test_separable_integrals_match_oracle_and_fock_hamiltonian(hctx, K, rank):
     H = omp.contract_full(_sites(m, K), labs)
     Hf = fm.fock_hamiltonian(h, v)
     assert np.abs(H - Hf).max() < 1e-11 * np.abs(Hf).max()
+
+
+@pytest.mark.parametrize("K", [4, 6, 8, 16])
+def test_exponential_interaction_keeps_one_pair_channel(hctx, K):
+    h, v = exponential_density_integrals(K)
+    m = P.Mpo(hctx, h, v, K, 0, compress_tol=1e-10)
+    D = m.bond_dims()
+    assert all(D[k] == 2 + 4 * K + 1 for k in range(1, K))
+    if K <= 6:
+        H = omp.contract_full(_sites(m, K), _labels(m, K))
+        Hf = fm.fock_hamiltonian(h, v)
+        assert np.abs(H - Hf).max() < 1e-11 * np.abs(Hf).max()
 
 
 def test_nearest_neighbour_integrals_match_oracle(hctx):

@@ -18,7 +18,8 @@ import numpy as np
 import pytest
 
 from oracle import dmrg, fermions as fm, mpo
-from workloads import chain_integrals, mps_values, nearest_neighbour_integrals, separable_integrals
+from workloads import (chain_integrals, exponential_density_integrals, mps_values, nearest_neighbour_integrals,
+                       separable_integrals)
 
 PAIR = ("A", "Ad", "B", "P", "Pd", "Q")
 
@@ -49,6 +50,24 @@ def test_separable_integrals_compress_to_the_rank_of_the_spin_blocks(K, rank):
     H = mpo.contract_full(Wc, chc)
     Hf = fm.fock_hamiltonian(h, v)
     assert np.abs(H - Hf).max() < 1e-11 * np.abs(Hf).max()
+
+
+@pytest.mark.parametrize("K", [4, 6, 8])
+def test_exponential_interaction_compresses_to_one_pair_channel(K):
+    """A density-density interaction that is one exponential in the distance
+    compresses exactly to a bond dimension independent of K (the paper's
+    sum-of-exponentials example): coupling e^{-(r-p)/xi} between p in L and
+    r in R factorises, so one 2-index channel per bond remains."""
+    h, v = exponential_density_integrals(K)
+    Ws, ch = mpo.build_mpo(h, v)
+    Wc, chc, _ = mpo.compress_mpo(Ws, ch, h, v, 1e-10)
+    for k in range(1, K):
+        assert n_pair(chc[k]) + sum(1 for c in chc[k] if c[0] == "X") == 1, k
+        assert len(chc[k]) == 2 + 4 * K + 1
+    if K <= 6:
+        H = mpo.contract_full(Wc, chc)
+        Hf = fm.fock_hamiltonian(h, v)
+        assert np.abs(H - Hf).max() < 1e-11 * np.abs(Hf).max()
 
 
 def test_nearest_neighbour_integrals_drop_uncoupled_pairs_exactly():

@@ -14,5 +14,6 @@ from .integrals import (  # noqa: F401
     mps_values,
     separable_integrals,
     nearest_neighbour_integrals,
+    exponential_density_integrals,
     CONFIGS,
 )

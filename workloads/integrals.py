@@ -160,6 +160,20 @@ def nearest_neighbour_integrals(K, seed):
     return h, v
 
 
+def exponential_density_integrals(K, xi=1.5):
+    """Nearest-neighbour hopping h_{i,i+1} = -1 and the density-density
+    interaction (ii|jj) = exp(-|i-j| / xi), every other (ij|kl) zero (no
+    random numbers)."""
+    h = np.zeros((K, K))
+    for i in range(K - 1):
+        h[i, i + 1] = h[i + 1, i] = -1.0
+    v = np.zeros((K,) * 4)
+    for i in range(K):
+        for j in range(K):
+            v[i, i, j, j] = np.exp(-abs(i - j) / xi)
+    return h, v
+
+
 def mps_values(seed, n):
     """Flat stream of n N(0,1) deviates that fills a random initial MPS.
 
