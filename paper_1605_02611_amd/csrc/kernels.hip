@@ -1152,7 +1152,9 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 // Kernel variant switches (environment, read once): DMRG_GEMM_VARIANT
 // (0 plain, 1 packed K-steps, 2 software pipeline, 3 persistent software
-// pipeline) and DMRG_GEMM_XCD=1 for the per-XCD task order.
+// pipeline) and DMRG_GEMM_XCD, the task order over the XCDs (0 block order,
+// 1 one contiguous run per XCD, c > 1 runs of c consecutive tasks per XCD:
+// the tiles of one operand panel then share an L2; default 4).
 static int gemm_env(const char* name, int dflt) {
     const char* e = std::getenv(name);
     return e ? std::atoi(e) : dflt;
@@ -1186,7 +1188,7 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
                              void* const* b, const int* act, int tile, hipStream_t s, int variant) {
     if (n_tasks <= 0) return;
     require(tile == 128 || tile == 64 || tile == 32, "grouped GEMM: tile must be 128, 64 or 32");
-    static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 0);
+    static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 4);
     const int var = variant >= 0 ? variant : var_env;
     require(var >= 0 && var <= 3, "grouped GEMM: unknown variant");
     if (tile == 128) {
