@@ -37,6 +37,7 @@ OwnCtx::OwnCtx(const Ctx& base) {
 OwnCtx::~OwnCtx() {
     (void)hipSetDevice(c.device);
     if (c.stream) (void)hipStreamSynchronize(c.stream);
+    destroy_side(c);
     if (c.blas) rocblas_destroy_handle(c.blas);
     for (hipEvent_t e : {c.ev0, c.ev1, c.ev2, c.ev3})
         if (e) (void)hipEventDestroy(e);

@@ -171,6 +171,7 @@ static void dmrg_ctx_destroy_now(dmrg_ctx* ctx) {
     }
     (void)hipSetDevice(ctx->c.device);
     if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    destroy_side(ctx->c);
     if (ctx->c.blas) rocblas_destroy_handle(ctx->c.blas);
     if (ctx->c.ev0) (void)hipEventDestroy(ctx->c.ev0);
     if (ctx->c.ev1) (void)hipEventDestroy(ctx->c.ev1);

@@ -898,6 +898,31 @@ struct SvdOut {
     int64_t a_off, u_off, v_off, s_off, e_off;
 };
 
+void ensure_side(Ctx& c) {
+    if (c.side) return;
+    DMRG_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    DMRG_HIP(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+    DMRG_HIP(hipEventCreateWithFlags(&c.join, hipEventDisableTiming));
+}
+void destroy_side(Ctx& c) {
+    if (c.side) (void)hipStreamSynchronize(c.side);
+    if (c.fork) (void)hipEventDestroy(c.fork);
+    if (c.join) (void)hipEventDestroy(c.join);
+    if (c.side) (void)hipStreamDestroy(c.side);
+    c.side = nullptr;
+    c.fork = c.join = nullptr;
+}
+
+// the main stream waits for the side stream's work (also when an exception
+// leaves the scope, before the buffers that work uses are released)
+struct SideJoin {
+    Ctx* c = nullptr;
+    bool on = false;
+    ~SideJoin() {
+        if (on) (void)hipStreamWaitEvent(c->stream, c->join, 0);
+    }
+};
+
 static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::pair<int, int>>>& mats,
                       std::vector<SvdOut>& outs, DevBuf& work, DevBuf& info) {
     hipStream_t s = ctx->stream;
@@ -934,6 +959,7 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
             jtot += svd_work_elems(outs[i].rows, outs[i].cols);
         }
     DevBuf jscr, djobs;
+    SideJoin sj{ctx};  // declared after the buffers: joins before they are released
     if (jtot > 0) {
         jscr.alloc(jtot * sizeof(double), s);
         int64_t pos = 0;
@@ -962,7 +988,19 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
                 need = std::max(need, mm * nn + nn * nn);
             }
             const int64_t cap = std::min<int64_t>(kJacobiLds, (ctx->max_lds - 64) / int64_t(sizeof(double)));
-            launch_jacobi_svd(djobs.as<SvdJob>(), int(n_small), int(std::max<int64_t>(0, std::min(need, cap))), s);
+            const int lds = int(std::max<int64_t>(0, std::min(need, cap)));
+            if (n_small < jobs.size()) {
+                // the small sectors run on the side stream, concurrently with
+                // the round launches of the large ones on the main stream
+                ensure_side(*ctx);
+                DMRG_HIP(hipEventRecord(ctx->fork, s));
+                DMRG_HIP(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+                launch_jacobi_svd(djobs.as<SvdJob>(), int(n_small), lds, ctx->side);
+                DMRG_HIP(hipEventRecord(ctx->join, ctx->side));
+                sj.on = true;
+            } else {
+                launch_jacobi_svd(djobs.as<SvdJob>(), int(n_small), lds, s);
+            }
         }
         const int nb = int(jobs.size() - n_small);
         if (nb > 0) {
@@ -998,6 +1036,10 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
             DMRG_HIP(hipMemcpyAsync(dinfo.p, sweeps.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
             launch_jacobi_finish(big, nb, dinfo.as<int>(), s);
             DMRG_HIP(hipStreamSynchronize(s));
+        }
+        if (sj.on) {
+            DMRG_HIP(hipStreamWaitEvent(s, ctx->join, 0));
+            sj.on = false;
         }
     }
     for (size_t i = 0; i < mats.size(); ++i) {

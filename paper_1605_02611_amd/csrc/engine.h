@@ -183,7 +183,13 @@ struct Ctx {
     std::string err;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     int max_lds = 0;  // bytes of LDS one workgroup may allocate on this device
+    // second stream (default priority) for work that overlaps the main
+    // stream, and its fork / join events; created on first use
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
+void ensure_side(Ctx& c);
+void destroy_side(Ctx& c);
 
 struct SweepOpts {
     Prec prec = Prec::F64;
