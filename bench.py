@@ -63,12 +63,12 @@ def cpu_baseline(P, ctx, m_sample, seed):
     from oracle import dmrg as od
     from oracle import mpo as omp
     from oracle.fermions import spin_orbital_integrals
-    from workloads import CONFIGS, config_integrals, mps_values
+    from workloads import WORKLOADS, workload_integrals, mps_values
 
-    c = CONFIGS[3]
+    c = WORKLOADS["chain_k36_m1024"]
     K = c["K"]
     j = K // 2 - 1
-    I = config_integrals(3)
+    I = workload_integrals("chain_k36_m1024")
     # model flops of this shape from the library
     mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
     n = mpo.n_values(m_sample)
@@ -226,19 +226,20 @@ def learned(args, P, torch):
     same random state; the learned run collects samples during the first
     sweeps (diagonal preconditioner), trains, then continues with the learned
     correction; the reference continues with the diagonal one."""
-    from workloads import CONFIGS, config_integrals, mps_values
-    cfg, n_col, n_cmp = (int(x) for x in args.learned.split(","))
-    c = CONFIGS[cfg]
+    from workloads import WORKLOADS, workload_integrals, mps_values
+    name, n_col, n_cmp = args.learned.split(",")
+    n_col, n_cmp = int(n_col), int(n_cmp)
+    c = WORKLOADS[name]
     K, M = c["K"], c["M"]
     prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
     ctx = P.Context(0)
-    I = config_integrals(cfg)
+    I = workload_integrals(name)
     mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
     vals = mps_values(c["seed"], mpo.n_values(M))
     net = P.Mlp(ctx, seed=7, capacity=1 << 22)
     kw = dict(prec=prec, dav_tol=args.dav_tol, dav_max_iter=args.dav_iter,
               refine_tol=1e-4 if prec != P.DMRG_FP64 else 0.0)
-    out = {"mode": "learned", "workload": cfg, "K": K, "M": M, "precision": args.prec,
+    out = {"mode": "learned", "workload": name, "K": K, "M": M, "precision": args.prec,
            "collect_sweeps": n_col, "compare_sweeps": n_cmp}
     runs = {}
 
@@ -300,7 +301,7 @@ def main():
                          "(K 12-24, M 128-512), --sweeps sweeps (default 1) sequential FP64, sequential "
                          "FP32 and batched FP32; energies and speedups")
     ap.add_argument("--learned", default="",
-                    help="instead of middle steps: 'cfg,collect,compare' e.g. '2,3,3': sweeps with the "
+                    help="instead of middle steps: 'workload,collect,compare' e.g. 'chain_k24_m512,3,3': sweeps with the "
                          "diagonal preconditioner collecting training samples, training, then "
                          "`compare` sweeps learned vs diagonal from the same state")
     ap.add_argument("--precision-check", action="store_true",
@@ -329,7 +330,7 @@ def main():
     import torch
 
     import paper_1605_02611_amd as P
-    from workloads import CONFIGS, config_integrals, mps_values
+    from workloads import WORKLOADS, workload_integrals, mps_values
 
     prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
     if args.calib:
@@ -343,11 +344,11 @@ def main():
         return batched(args, P, torch)
     if args.learned:
         return learned(args, P, torch)
-    c = CONFIGS[3]
+    c = WORKLOADS["chain_k36_m1024"]
     K, M = c["K"], c["M"]
     ctx = P.Context(0)
     t0 = time.time()
-    I = config_integrals(3)
+    I = workload_integrals("chain_k36_m1024")
     mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz, compress_tol=args.compress)
     if args.compress:
         log("compressed MPO (tol %g, %.1fs): D %s" % (args.compress, time.time() - t0, list(mpo.bond_dims())))

@@ -14,13 +14,13 @@ sys.path.insert(0, ROOT)
 
 from oracle import dmrg as od  # noqa: E402
 from oracle import fermions as fm  # noqa: E402
-from workloads import CONFIGS, chain_integrals, config_integrals, mps_values  # noqa: E402
+from workloads import WORKLOADS, chain_integrals, mps_values, workload_integrals  # noqa: E402
 
 CASES = {
-    # first workload: random molecule K=8, N=8, M=64, 6 sweeps
-    "config1": dict(kind="config", cfg=1, M=64, sweeps=6),
+    # random molecule K=8, N=8, M=64, 6 sweeps
+    "random_k8": dict(kind="workload", name="random_k8", M=64, sweeps=6),
     # the same molecule at M=256, where the two-site space is exact
-    "config1_exact": dict(kind="config", cfg=1, M=256, sweeps=2),
+    "random_k8_exact": dict(kind="workload", name="random_k8", M=256, sweeps=2),
     # chain K=8, N=8, M=16 (truncating), 3 sweeps
     "chain8": dict(kind="chain", K=8, N=8, seed=77, M=16, sweeps=3),
     # odd electron count: K=7, N=7, 2Sz=1
@@ -33,9 +33,9 @@ CASES = {
 
 
 def run(name, c):
-    if c["kind"] == "config":
-        I = config_integrals(c["cfg"])
-        seed = CONFIGS[c["cfg"]]["seed"]
+    if c["kind"] == "workload":
+        I = workload_integrals(c["name"])
+        seed = WORKLOADS[c["name"]]["seed"]
     else:
         I = chain_integrals(c["K"], n_elec=c["N"], seed=c["seed"])
         seed = c["seed"]

@@ -13,7 +13,7 @@ import pytest
 import paper_1605_02611_amd as P
 from paper_1605_02611_amd import _lib
 from oracle import dmrg as od, fermions as fm, mpo as omp
-from workloads import chain_integrals, random_integrals_cfg1
+from workloads import chain_integrals, random_molecule_integrals
 
 NAMES = ["I", "H", "Cd", "C", "SL", "SLd", "A", "Ad", "B", "P", "Pd", "Q"]
 
@@ -40,7 +40,7 @@ def test_library_exports_every_declared_function(repo_root):
 
 @pytest.mark.parametrize("K", [2, 3, 4, 5, 6])
 def test_host_mpo_equals_oracle_mpo(hctx, K):
-    I = random_integrals_cfg1(K=K, n_elec=K, seed=40 + K, rank=4)
+    I = random_molecule_integrals(K=K, n_elec=K, seed=40 + K, rank=4)
     m = P.Mpo(hctx, I.h, I.v, K, K % 2)
     Ws, ch = omp.build_mpo(I.h, I.v)
     assert list(m.bond_dims()) == omp.bond_dims(K)
@@ -70,7 +70,7 @@ def test_host_mpo_contracts_to_fock_hamiltonian(hctx, K):
 
 def test_switch_bond_option_changes_only_the_recursion(hctx):
     K = 4
-    I = random_integrals_cfg1(K=K, n_elec=K, seed=3, rank=3)
+    I = random_molecule_integrals(K=K, n_elec=K, seed=3, rank=3)
     Hf = fm.fock_hamiltonian(I.h, I.v)
     for sw in (0, 1, 3, 4):
         m = P.Mpo(hctx, I.h, I.v, K, 0, switch_bond=sw)
@@ -94,7 +94,7 @@ def test_initial_value_count_matches_oracle_rule(hctx, K, N, tsz, M):
 
 def test_invalid_inputs_are_rejected(hctx):
     K = 3
-    I = random_integrals_cfg1(K=K, n_elec=K, seed=1, rank=2)
+    I = random_molecule_integrals(K=K, n_elec=K, seed=1, rank=2)
     h = I.h.copy()
     h[0, 1] += 1e-6
     with pytest.raises(P.DmrgError) as e:
@@ -116,7 +116,7 @@ def test_invalid_inputs_are_rejected(hctx):
 
 
 def test_gpu_calls_on_host_context_fail_cleanly(hctx):
-    I = random_integrals_cfg1(K=4, n_elec=4, seed=1, rank=2)
+    I = random_molecule_integrals(K=4, n_elec=4, seed=1, rank=2)
     m = P.Mpo(hctx, I.h, I.v, 4, 0)
     n = m.n_values(8)
     with pytest.raises(P.DmrgError) as e:

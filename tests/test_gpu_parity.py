@@ -18,8 +18,8 @@ import paper_1605_02611_amd as P  # noqa: E402
 from oracle import dmrg as od  # noqa: E402
 from oracle import fermions as fm  # noqa: E402
 from tests import helpers as H  # noqa: E402
-from workloads import (CONFIGS, chain_integrals, config_integrals, mps_values,  # noqa: E402
-                       random_integrals_cfg1)
+from workloads import (WORKLOADS, chain_integrals, mps_values, random_molecule_integrals,  # noqa: E402
+                       workload_integrals)
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_dmrg.json")
@@ -73,7 +73,7 @@ def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
 # --- environments, sigma and diagonal on imported tensors -----------------------------
 
 def _oracle_case(K, N, tsz, M, seed, kind="random"):
-    I = (random_integrals_cfg1(K=K, n_elec=N, seed=seed, rank=4) if kind == "random"
+    I = (random_molecule_integrals(K=K, n_elec=N, seed=seed, rank=4) if kind == "random"
          else chain_integrals(K, n_elec=N, seed=seed))
     n = od.n_mps_values(K, N, tsz, M)
     return I, od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n))
@@ -146,12 +146,12 @@ def _golden():
     return json.load(open(GOLD))
 
 
-@pytest.mark.parametrize("name", ["chain7_odd", "chain8", "chain8_compressed", "config1_exact", "config1"])
+@pytest.mark.parametrize("name", ["chain7_odd", "chain8", "chain8_compressed", "random_k8_exact", "random_k8"])
 def test_sweeps_match_oracle_energies(ctx, name):
     g = _golden()[name]
     _log("sweeps", name)
     if g["kind"] == "random":
-        I = config_integrals(1)
+        I = workload_integrals("random_k8")
     else:
         I = chain_integrals(g["K"], n_elec=g["N"], seed=g["seed"])
     mpo = P.Mpo(ctx, I.h, I.v, g["N"], g["two_sz"], compress_tol=g.get("compress_tol", 0.0))
@@ -169,7 +169,7 @@ def test_sweeps_match_oracle_energies(ctx, name):
         assert [list(t) for t in mps.bond(k)] == g["bonds"][k]
     if "fci" in g and not g.get("compress_tol"):  # the bound holds for the exact H only
         assert mps.energy() >= g["fci"] - 1e-10
-        if name == "config1_exact":
+        if name == "random_k8_exact":
             assert abs(mps.energy() - g["fci"]) < 1e-10
 
 
@@ -191,8 +191,8 @@ def test_mixed_precision_refinement_reaches_fp64_energy(ctx):
 
 @pytest.fixture(scope="module")
 def big(ctx):
-    c = CONFIGS[3]
-    I = config_integrals(3)
+    c = WORKLOADS["chain_k36_m1024"]
+    I = workload_integrals("chain_k36_m1024")
     mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
     n = mpo.n_values(c["M"])
     mps = P.Mps.random(ctx, mpo, c["M"], mps_values(c["seed"], n))
@@ -251,7 +251,7 @@ def _batch_instances():
     for K, N, M, seed, kind in [(6, 6, 12, 201, "chain"), (7, 7, 16, 202, "chain"),
                                 (5, 4, 8, 203, "random"), (8, 8, 24, 204, "chain")]:
         I = (chain_integrals(K, n_elec=N, seed=seed) if kind == "chain"
-             else random_integrals_cfg1(K=K, n_elec=N, seed=seed, rank=3))
+             else random_molecule_integrals(K=K, n_elec=N, seed=seed, rank=3))
         out.append((I, M, seed))
     return out
 

@@ -13,13 +13,13 @@ import numpy as np
 import pytest
 
 from oracle import dmrg, fermions as fm, mpo, proj
-from workloads import chain_integrals, mps_values, random_integrals_cfg1
+from workloads import chain_integrals, mps_values, random_molecule_integrals
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _rand_ints(K, seed, rank=4):
-    return random_integrals_cfg1(K=K, n_elec=K, seed=seed, rank=rank)
+    return random_molecule_integrals(K=K, n_elec=K, seed=seed, rank=rank)
 
 
 # --- FCI -------------------------------------------------------------------------
@@ -61,7 +61,7 @@ def test_fci_orbital_rotation_invariance():
 
 
 def test_fci_sector_dimension_and_lanczos():
-    I = random_integrals_cfg1()
+    I = random_molecule_integrals()
     dets = fm.sector_determinants(8, 8, 0)
     assert len(dets) == comb(8, 4) ** 2 == 4900
     H = fm.hamiltonian_on_determinants(I.h, I.v, dets)

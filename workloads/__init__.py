@@ -7,13 +7,13 @@ the CPU oracle and the HIP library consume exactly these arrays.
 
 from .integrals import (  # noqa: F401
     Integrals,
-    random_integrals_cfg1,
+    random_molecule_integrals,
     chain_integrals,
-    config_integrals,
+    workload_integrals,
     batched_instances,
     mps_values,
     separable_integrals,
     nearest_neighbour_integrals,
     exponential_density_integrals,
-    CONFIGS,
+    WORKLOADS,
 )

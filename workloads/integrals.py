@@ -57,7 +57,7 @@ def _v_from_cholesky(vecs):
     return np.einsum("qij,qkl->ijkl", Lq, Lq)
 
 
-def random_integrals_cfg1(K=8, n_elec=8, seed=1001, rank=8):
+def random_molecule_integrals(K=8, n_elec=8, seed=1001, rank=8):
     """Dense random molecule (first workload).
 
     h_ij = N(0,1) exp(-|i-j|/3) for i <= j, mirrored, then h_ii += 0.5 i
@@ -109,23 +109,23 @@ def batched_instances(n=64, seed=4999, base_seed=4000):
     return out
 
 
-CONFIGS = {
-    1: dict(kind="random", K=8, n_elec=8, M=64, sweeps=6, seed=1001),
-    2: dict(kind="chain", K=24, n_elec=24, M=512, sweeps=8, seed=1002),
-    3: dict(kind="chain", K=36, n_elec=36, M=1024, sweeps=8, seed=1003),
-    4: dict(kind="batched", n=64, sweeps=8, seed=4999),
-    5: dict(kind="chain", K=48, n_elec=48, M=1024, sweeps=6, seed=1005),
+WORKLOADS = {
+    "random_k8": dict(kind="random", K=8, n_elec=8, M=64, sweeps=6, seed=1001),
+    "chain_k24_m512": dict(kind="chain", K=24, n_elec=24, M=512, sweeps=8, seed=1002),
+    "chain_k36_m1024": dict(kind="chain", K=36, n_elec=36, M=1024, sweeps=8, seed=1003),
+    "batch64_k12_24": dict(kind="batched", n=64, sweeps=8, seed=4999),
+    "chain_k48_m1024": dict(kind="chain", K=48, n_elec=48, M=1024, sweeps=6, seed=1005),
 }
 
 
-def config_integrals(cfg):
-    """Integrals of workload ``cfg`` (1, 2, 3 or 5)."""
-    c = CONFIGS[cfg]
+def workload_integrals(name):
+    """Integrals of a single-molecule workload of WORKLOADS."""
+    c = WORKLOADS[name]
     if c["kind"] == "random":
-        return random_integrals_cfg1(c["K"], c["n_elec"], c["seed"])
+        return random_molecule_integrals(c["K"], c["n_elec"], c["seed"])
     if c["kind"] == "chain":
         return chain_integrals(c["K"], c["n_elec"], c["seed"], rank=c["K"])
-    raise ValueError("workload %d is a batch; use batched_instances()" % cfg)
+    raise ValueError("workload %s is a batch; use batched_instances()" % name)
 
 
 def separable_integrals(K, rank, seed):
