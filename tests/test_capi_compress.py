@@ -130,3 +130,19 @@ def test_compression_at_the_largest_test_size_is_quick(hctx):
     D, D0 = m.bond_dims(), omp.bond_dims(K)
     assert all(a <= b for a, b in zip(D, D0)) and D[K // 2] < D0[K // 2]
     assert dt < 30.0
+
+
+@pytest.mark.parametrize("scale", [1e-100, 1e100])
+def test_compression_is_scale_invariant(hctx, scale):
+    """Integrals scaled by a huge or tiny factor compress to the same bond
+    dimensions with the threshold scaled alike, and the singular values scale
+    with them (the host eigensolver works on A / ||A||, so nothing under- or
+    overflows)."""
+    K = 6
+    h, v = exponential_density_integrals(K)
+    ref = P.Mpo(hctx, h, v, K, 0, compress_tol=1e-10)
+    m = P.Mpo(hctx, h * scale, v * scale, K, 0, compress_tol=1e-10 * scale)
+    assert list(m.bond_dims()) == list(ref.bond_dims())
+    for k in range(1, K):
+        s0, s1 = ref.singular_values(k), m.singular_values(k)
+        assert np.allclose(s1, s0 * scale, rtol=1e-10, atol=1e-12 * scale * s0.max())
