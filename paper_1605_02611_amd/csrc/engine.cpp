@@ -1871,9 +1871,6 @@ DavOut State::solve(const SweepOpts& o, StepStats& stt) {
 }
 
 double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool solve) {
-    const int K = mpo->K;
-    const int j = center;
-    hipStream_t s = ctx->stream;
     using clk = std::chrono::steady_clock;
     auto sec = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
     const auto t0 = clk::now();
