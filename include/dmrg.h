@@ -147,6 +147,16 @@ void dmrg_mpo_free(dmrg_mpo* mpo);
 
 /* Number of FP64 values a random initial MPS of bond dimension M consumes. */
 dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n);
+/* Integer block index of the two-site vector (host only, no context): left
+ * = sectors of bond j and right = sectors of bond j+2 as (N, 2S_z, dim)
+ * triples sorted by (N, 2S_z).  The middle sectors q of the merged layout
+ * above, in storage order, as rows of 5 int64: N, 2S_z, rows (left state,
+ * s) with Q_l + q_s = q, columns (t, right state) with Q_r = q + q_t, and
+ * the sector's element offset.  out == NULL: *n receives the row count;
+ * otherwise *n is the capacity in rows on input and the count on output.
+ * DMRG_E_INVAL for unsorted or repeated sectors or dimensions below 1. */
+dmrg_status dmrg_two_site_index(const int32_t* left, int n_left, const int32_t* right, int n_right,
+                                int64_t* n, int64_t* out);
 /* Random initial MPS: sector dimensions from the fixed integer rule (full
  * dimension min(left count, right count); M apportioned in proportion to it
  * by largest remainders when the total exceeds M; then made consistent

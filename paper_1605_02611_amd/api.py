@@ -144,6 +144,26 @@ class Mpo:
             self.h = None
 
 
+def two_site_index(left, right):
+    """dmrg_two_site_index: rows (N, 2Sz, d_sys, d_env, offset) of the two-site
+    vector between bond sectors left (bond j) and right (bond j+2)."""
+    lib = L.load()
+    lt = np.ascontiguousarray(np.asarray(left, dtype=np.int32).reshape(-1))
+    rt = np.ascontiguousarray(np.asarray(right, dtype=np.int32).reshape(-1))
+    n = C.c_int64()
+    ip = C.POINTER(C.c_int32)
+    st = lib.dmrg_two_site_index(lt.ctypes.data_as(ip), lt.size // 3, rt.ctypes.data_as(ip), rt.size // 3,
+                                 C.byref(n), None)
+    if st:
+        raise DmrgError(st, "two-site index")
+    out = np.zeros(5 * n.value, dtype=np.int64)
+    st = lib.dmrg_two_site_index(lt.ctypes.data_as(ip), lt.size // 3, rt.ctypes.data_as(ip), rt.size // 3,
+                                 C.byref(n), out.ctypes.data_as(C.POINTER(C.c_int64)))
+    if st:
+        raise DmrgError(st, "two-site index")
+    return out.reshape(-1, 5)
+
+
 def default_opts(**kw):
     o = L.SweepOpts()
     L.load().dmrg_sweep_opts_default(C.byref(o))

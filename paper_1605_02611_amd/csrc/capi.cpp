@@ -267,6 +267,44 @@ dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n) {
     return DMRG_OK;
 }
 
+dmrg_status dmrg_two_site_index(const int32_t* left, int n_left, const int32_t* right, int n_right,
+                                int64_t* n, int64_t* out) {
+    if (!left || !right || !n || n_left < 1 || n_right < 1) return DMRG_E_INVAL;
+    try {
+        auto bond = [](const int32_t* t, int cnt) {
+            Bond b;
+            for (int i = 0; i < cnt; ++i) {
+                require(t[3 * i + 2] >= 1, "sector dimensions must be >= 1");
+                const QN q{t[3 * i], t[3 * i + 1]};
+                require(b.q.empty() || b.q.back() < q, "sectors must be sorted and unique");
+                b.q.push_back(q);
+                b.dim.push_back(t[3 * i + 2]);
+            }
+            b.finalize();
+            return b;
+        };
+        const Bond bl = bond(left, n_left), br = bond(right, n_right);
+        const TwoSite ts = make_two_site(bl, br);
+        const int64_t cnt = int64_t(ts.q.size());
+        if (!out) {
+            *n = cnt;
+            return DMRG_OK;
+        }
+        if (*n < cnt) return DMRG_E_INVAL;
+        for (int64_t i = 0; i < cnt; ++i) {
+            out[5 * i] = ts.q[i].n;
+            out[5 * i + 1] = ts.q[i].sz;
+            out[5 * i + 2] = ts.sys[i].dim;
+            out[5 * i + 3] = ts.env[i].dim;
+            out[5 * i + 4] = ts.off[i];
+        }
+        *n = cnt;
+    } catch (...) {
+        return DMRG_E_INVAL;
+    }
+    return DMRG_OK;
+}
+
 dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M, const double* values,
                             int64_t n_values, dmrg_mps** out) {
     if (!ctx) return DMRG_E_INVAL;

@@ -13,7 +13,8 @@ import pytest
 import paper_1605_02611_amd as P
 from paper_1605_02611_amd import _lib
 from oracle import dmrg as od, fermions as fm, mpo as omp
-from workloads import chain_integrals, random_molecule_integrals
+from tests import helpers as H
+from workloads import chain_integrals, mps_values, random_molecule_integrals
 
 NAMES = ["I", "H", "Cd", "C", "SL", "SLd", "A", "Ad", "B", "P", "Pd", "Q"]
 
@@ -153,3 +154,41 @@ def test_tuning_table_round_trip_and_validation():
     lib = _lib.load()
     assert lib.dmrg_tune_table_load(b"{not json") == 1
     assert lib.dmrg_tune_table_load(b"{}") == 0
+
+
+def _brute_two_site(lab_l, lab_r):
+    """(N, 2Sz, d_sys, d_env, offset) rows by counting label rows one by one."""
+    site = [(0, 0), (1, 1), (1, -1), (2, 0)]
+    ll = [tuple(int(v) for v in x) for x in np.asarray(lab_l).reshape(-1, 2)]
+    lr = [tuple(int(v) for v in x) for x in np.asarray(lab_r).reshape(-1, 2)]
+    qs = sorted({(a[0] + s[0], a[1] + s[1]) for a in ll for s in site})
+    rows, off = [], 0
+    for q in qs:
+        ds = sum(1 for a in ll for s in site if (a[0] + s[0], a[1] + s[1]) == q)
+        de = sum(1 for b in lr for t in site if b == (q[0] + t[0], q[1] + t[1]))
+        if ds and de:
+            rows.append((q[0], q[1], ds, de, off))
+            off += ds * de
+    return rows
+
+
+@pytest.mark.parametrize("K,N,tsz,M,steps", [(6, 6, 0, 12, 2), (7, 8, 2, 20, 3), (8, 8, 0, 24, 4), (5, 5, 1, 6, 1)])
+def test_two_site_block_index_is_bit_exact(K, N, tsz, M, steps):
+    I = chain_integrals(K, n_elec=N, seed=K + steps)
+    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(K, od.n_mps_values(K, N, tsz, M)))
+    for j in range(steps):
+        d.step(j, True, False)
+    for c in range(K - 1):
+        lab_l, lab_r = d.labels[c], d.labels[c + 2]
+        got = P.two_site_index(H.sectors(lab_l), H.sectors(lab_r))
+        want = _brute_two_site(lab_l, lab_r)
+        assert [tuple(int(v) for v in r) for r in got] == want, c
+        n = int(got[-1, 2] * got[-1, 3] + got[-1, 4]) if len(got) else 0
+        assert n == len(H.merged_index(lab_l, lab_r)[0])
+
+
+def test_two_site_block_index_rejects_bad_sectors():
+    with pytest.raises(P.DmrgError):
+        P.two_site_index([(1, 1, 2), (0, 0, 1)], [(0, 0, 1)])  # unsorted
+    with pytest.raises(P.DmrgError):
+        P.two_site_index([(0, 0, 0)], [(0, 0, 1)])  # empty sector
