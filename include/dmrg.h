@@ -157,6 +157,23 @@ dmrg_status dmrg_mps_n_values(const dmrg_mpo* mpo, int M, int64_t* n);
  * DMRG_E_INVAL for unsorted or repeated sectors or dimensions below 1. */
 dmrg_status dmrg_two_site_index(const int32_t* left, int n_left, const int32_t* right, int n_right,
                                 int64_t* n, int64_t* out);
+/* Model flops of one sigma-vector application (dmrg_sigma) at the pair
+ * (j, j+1) of a state whose bond j has the sectors `left` and bond j+2 the
+ * sectors `right` (triples (N, 2S_z, dim) sorted by (N, 2S_z)); host only,
+ * no context.  The count is the integer cost of Eq. Hpartition evaluated
+ * with the blocked operators of Eq. prenormmatrix (the M^3 K^3 term of the
+ * Sec. 2.5 cost): for every middle-bond channel y whose system and
+ * environment operators are both nonzero,
+ *   flops[0] (system side): sum over the fine blocks (Q'_l, s') <- (Q_l, s)
+ *            of O^sys_y of 2 m(Q'_l) m(Q_l) C(Q_l + q_s), C(q) the number
+ *            of two-site columns (t, Q_r) of middle sector q;
+ *   flops[1] (environment side): sum over the fine blocks (t', Q'_r) <-
+ *            (t, Q_r) of O^env_y of 2 m(Q'_r) m(Q_r) R(q'), R(q') the
+ *            number of two-site rows (Q'_l, s') of the destination sector;
+ * the identity operator of the channels 1 (x) H^R and H^L (x) 1 costs
+ * nothing.  DMRG_E_INVAL for a pair outside the MPO or malformed sectors. */
+dmrg_status dmrg_sigma_model_flops(const dmrg_mpo* mpo, int j, const int32_t* left, int n_left,
+                                   const int32_t* right, int n_right, double* flops);
 /* Random initial MPS: sector dimensions from the fixed integer rule (full
  * dimension min(left count, right count); M apportioned in proportion to it
  * by largest remainders when the total exceeds M; then made consistent

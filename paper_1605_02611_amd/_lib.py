@@ -54,6 +54,8 @@ SIGNATURES = {
     "dmrg_mpo_free": (None, [c_void_p]),
     "dmrg_mps_n_values": (c_int, [c_void_p, c_int, P(c_int64)]),
     "dmrg_two_site_index": (c_int, [P(c_int32), c_int, P(c_int32), c_int, P(c_int64), P(c_int64)]),
+    "dmrg_sigma_model_flops": (c_int, [c_void_p, c_int, P(c_int32), c_int, P(c_int32), c_int,
+                                       P(c_double)]),
     "dmrg_mps_random": (c_int, [c_void_p, c_void_p, c_int, P(c_double), c_int64, P(c_void_p)]),
     "dmrg_mps_import": (c_int, [c_void_p, c_void_p, P(c_int32), P(c_int32), P(c_double), c_int,
                                 P(c_void_p)]),

@@ -164,6 +164,22 @@ def two_site_index(left, right):
     return out.reshape(-1, 5)
 
 
+def sigma_model_flops(mpo, j, left, right):
+    """dmrg_sigma_model_flops: (system-side, environment-side) model flops of
+    one sigma at the pair (j, j+1) for bond-j sectors `left` and bond-(j+2)
+    sectors `right` (lists of (N, 2Sz, dim), sorted)."""
+    lib = L.load()
+    lt = np.ascontiguousarray(np.asarray(left, dtype=np.int32).reshape(-1))
+    rt = np.ascontiguousarray(np.asarray(right, dtype=np.int32).reshape(-1))
+    out = np.zeros(2)
+    ip = C.POINTER(C.c_int32)
+    st = lib.dmrg_sigma_model_flops(mpo.h, j, lt.ctypes.data_as(ip), lt.size // 3, rt.ctypes.data_as(ip),
+                                    rt.size // 3, out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st:
+        raise DmrgError(st, "sigma model flops")
+    return float(out[0]), float(out[1])
+
+
 def default_opts(**kw):
     o = L.SweepOpts()
     L.load().dmrg_sweep_opts_default(C.byref(o))

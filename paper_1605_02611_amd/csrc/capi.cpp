@@ -305,6 +305,36 @@ dmrg_status dmrg_two_site_index(const int32_t* left, int n_left, const int32_t* 
     return DMRG_OK;
 }
 
+namespace {
+Bond bond_from_triples(const int32_t* t, int cnt) {
+    Bond b;
+    for (int i = 0; i < cnt; ++i) {
+        require(t[3 * i + 2] >= 1, "sector dimensions must be >= 1");
+        const QN q{t[3 * i], t[3 * i + 1]};
+        require(b.q.empty() || b.q.back() < q, "sectors must be sorted and unique");
+        b.q.push_back(q);
+        b.dim.push_back(t[3 * i + 2]);
+    }
+    b.finalize();
+    return b;
+}
+}  // namespace
+
+dmrg_status dmrg_sigma_model_flops(const dmrg_mpo* mpo, int j, const int32_t* left, int n_left,
+                                   const int32_t* right, int n_right, double* flops) {
+    if (!mpo || !left || !right || !flops || n_left < 1 || n_right < 1) return DMRG_E_INVAL;
+    if (j < 0 || j + 2 > mpo->m->K) return DMRG_E_INVAL;
+    try {
+        const Bond bl = bond_from_triples(left, n_left), br = bond_from_triples(right, n_right);
+        sigma_model_flops(*mpo->m, j, bl, br, &flops[0], &flops[1]);
+    } catch (const std::bad_alloc&) {
+        return DMRG_E_NOMEM;
+    } catch (...) {
+        return DMRG_E_INVAL;
+    }
+    return DMRG_OK;
+}
+
 dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M, const double* values,
                             int64_t n_values, dmrg_mps** out) {
     if (!ctx) return DMRG_E_INVAL;

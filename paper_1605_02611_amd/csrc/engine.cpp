@@ -1275,15 +1275,15 @@ void State::release_workspace() {
     prepared = false;
 }
 
-void State::prepare() {
-    if (prepared) return;
-    const int j = center;
-    hipStream_t s = ctx->stream;
-    const auto tp0 = std::chrono::steady_clock::now();
-    Y = block_sys(j, *L[j]);
-    Z = block_env(j + 1, *R[j + 2]);
-    const auto tp1 = std::chrono::steady_clock::now();
-    const int nch = int(mpo->chans[j + 1].size());
+// Task lists of the two sigma passes at the pair (j, j+1) (host only; Eq.
+// Hpartition): pass 1 forms T_y(q) = O^sys_y psi_q for every middle-bond
+// channel y, pass 2 sums T_y(q) (O^env_y)^T into sigma.  Their model flops
+// (identity operators excluded) are the library's count of the work of one
+// sigma.
+void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& Y, const Blocked& Z,
+                       const SigmaConfig& cfg, GemmList& pass1, GemmList& pass2,
+                       std::vector<int64_t>& t_off, int64_t& t_total, int& splits) {
+    const int nch = int(mpo.chans[j + 1].size());
     const int nq = int(ts.q.size());
     // destination sector of every sector for each distinct shift
     std::map<QN, std::vector<int>> dest;
@@ -1302,7 +1302,7 @@ void State::prepare() {
     t_total = 0;
     for (int y = 0; y < nch; ++y) {
         if (!hy[y] || !hz[y]) continue;
-        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
+        const std::vector<int>& dv = dest_of(mpo.chan_dq[j + 1][y]);
         for (int iq = 0; iq < nq; ++iq) {
             const int iq2 = dv[iq];
             if (iq2 < 0) continue;
@@ -1311,12 +1311,11 @@ void State::prepare() {
         }
     }
     pass1.clear();
-    if (!cfg_explicit) tune_lookup(tune_key(), cfg);
     pass1.tile = cfg.tile1;
     pass1.variant = cfg.variant;
     std::vector<UTerm> terms;
     for (int y = 0; y < nch; ++y) {
-        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
+        const std::vector<int>& dv = dest_of(mpo.chan_dq[j + 1][y]);
         for (int iq = 0; iq < nq; ++iq) {
             const int64_t to = t_off[size_t(y) * nq + iq];
             if (to < 0) continue;
@@ -1352,7 +1351,7 @@ void State::prepare() {
     std::vector<std::vector<UTerm>> uterms(unit_base[nq]);
     for (int y = 0; y < nch; ++y) {
         if (!hy[y] || !hz[y]) continue;
-        const std::vector<int>& dv = dest_of(mpo->chan_dq[j + 1][y]);
+        const std::vector<int>& dv = dest_of(mpo.chan_dq[j + 1][y]);
         for (int iq = 0; iq < nq; ++iq) {
             const int64_t to = t_off[size_t(y) * nq + iq];
             if (to < 0) continue;
@@ -1409,14 +1408,48 @@ void State::prepare() {
             add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[u], su[u], ts.n);
         }
     }
-    const BondL& br = bonds[j + 2];
-    (void)br;
     {
         int64_t sz1[kMaxBufs] = {Y.total, ts.n, t_total};
         validate_list(pass1, sz1);
         int64_t sz2[kMaxBufs] = {t_total, Z.total, splits > 1 ? int64_t(splits) * ts.n : ts.n};
         validate_list(pass2, sz2);
     }
+}
+
+void sigma_model_flops(const MPO& mpo, int j, const Bond& left, const Bond& right, double* pass1_flops,
+                       double* pass2_flops) {
+    require(j >= 0 && j + 2 <= mpo.K, "pair out of range");
+    BondL bl, br;
+    static_cast<Bond&>(bl) = left;
+    static_cast<Bond&>(br) = right;
+    bl.finalize();
+    br.finalize();
+    Env Lj, Rj;
+    Lj.lay_out(bl, mpo.chan_dq[j]);
+    Rj.lay_out(br, mpo.chan_dq[j + 2]);
+    const int nch = int(mpo.chans[j + 1].size());
+    const Blocked Y = make_blocked(bl, mpo.sys_groups[j], Lj, nch, CK_I, mpo.chans[j + 1]);
+    const Blocked Z = make_blocked(br, mpo.env_groups[j + 1], Rj, nch, CK_H, mpo.chans[j + 1]);
+    const TwoSite ts = make_two_site(bl, br);
+    GemmList p1, p2;
+    std::vector<int64_t> t_off;
+    int64_t t_total = 0;
+    int splits = 1;
+    build_sigma_lists(mpo, j, ts, Y, Z, SigmaConfig{}, p1, p2, t_off, t_total, splits);
+    *pass1_flops = p1.model_flops;
+    *pass2_flops = p2.model_flops;
+}
+
+void State::prepare() {
+    if (prepared) return;
+    const int j = center;
+    hipStream_t s = ctx->stream;
+    const auto tp0 = std::chrono::steady_clock::now();
+    Y = block_sys(j, *L[j]);
+    Z = block_env(j + 1, *R[j + 2]);
+    const auto tp1 = std::chrono::steady_clock::now();
+    if (!cfg_explicit) tune_lookup(tune_key(), cfg);
+    build_sigma_lists(*mpo, j, ts, Y, Z, cfg, pass1, pass2, t_off, t_total, splits);
     pass1.sigma_role = pass2.sigma_role = true;
     const auto tp2 = std::chrono::steady_clock::now();
     pass1.upload(s);

@@ -156,6 +156,12 @@ struct GemmList {
 // buffers it addresses (throws instead of letting a kernel fault).
 void validate_list(const GemmList& L, const int64_t* sizes);
 
+// Model flops of one sigma at the pair (j, j+1) of a state whose bonds j and
+// j+2 hold the sectors of `left` and `right` (host only): the same task
+// lists as State::prepare, split into the two passes.
+void sigma_model_flops(const MPO& mpo, int j, const Bond& left, const Bond& right, double* pass1_flops,
+                       double* pass2_flops);
+
 struct UTerm {
     int a_buf;
     int64_t a_off;
