@@ -21,7 +21,10 @@
  *   - Every function returns dmrg_status; DMRG_OK is 0.  On error no output
  *     argument is written and dmrg_last_error(ctx) describes the failure
  *     until the next call on that context.  No exception or abort crosses
- *     the ABI.
+ *     the ABI.  The one exception is DMRG_E_NOCONV, a warning: the call
+ *     completed and wrote its outputs, but at least one Davidson solve
+ *     stopped at its iteration limit with the residual above the requested
+ *     tolerance (the statistics say how many and how far).
  *   - Host arrays passed in are borrowed for the duration of the call;
  *     handles are owned by the library and released with the *_free /
  *     *_destroy functions; arrays written by the library are caller-owned.
@@ -76,13 +79,33 @@ typedef struct dmrg_mpo dmrg_mpo;
 typedef struct dmrg_mps dmrg_mps;
 typedef struct dmrg_mlp dmrg_mlp;
 
+/* Device-memory allocator of a context.  alloc(bytes, user) returns device
+ * memory of the context's GPU, or NULL when it has none to give (the call
+ * that needed it then fails with DMRG_E_NOMEM); free(p, user) takes back a
+ * pointer alloc returned.  The library calls free only after the device has
+ * finished every queued use of the memory, so the allocator may hand it out
+ * again at once.  Both may be called from the library's host threads
+ * (batched sweeps), never concurrently for one context unless the caller
+ * runs two calls at once, which the context does not allow. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* p, void* user);
+    void* user;
+} dmrg_allocator;
+
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
- * order all work on, or NULL for a stream owned by the context.  device = -1
- * gives a host-only context that can build and query MPOs; every call that
- * needs the GPU then fails with DMRG_E_STATE. */
-dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out);
+ * order all work on, or NULL for a stream owned by the context.
+ * `allocator` (copied; may be NULL) supplies all device memory of the
+ * states and networks created on the context; NULL: the library allocates
+ * stream-ordered memory itself (hipMallocAsync on the context's stream,
+ * cached in the device's default pool).  device = -1 gives a host-only
+ * context that can build and query MPOs; every call that needs the GPU then
+ * fails with DMRG_E_STATE.  DMRG_E_INVAL for an allocator without both
+ * functions. */
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, const dmrg_allocator* allocator,
+                            dmrg_ctx** out);
 /* Release the caller's handle.  States (dmrg_mps) and networks (dmrg_mlp)
  * created on ctx keep it alive: its stream, events and BLAS handle are
  * destroyed once the handle and all of them have been released, in any
@@ -184,12 +207,15 @@ dmrg_status dmrg_sigma_model_flops(const dmrg_mpo* mpo, int j, const int32_t* le
 dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M,
                             const double* values, int64_t n_values, dmrg_mps** out);
 /* MPS from explicit site tensors (test hook).  sectors: for bonds 0..K in
- * order, n_sectors[k] triples (N, 2S_z, dim), sorted.  site_values: the K
- * site tensors concatenated, each in fine-block layout.  Sites < center are
- * taken as left-canonical, sites > center+1 as right-canonical; the center
- * pair is contracted into the two-site vector and environments are built. */
+ * order, n_sectors[k] triples (N, 2S_z, dim), sorted (at most 2^20 sectors
+ * of at most 2^24 states each).  site_values: the K site tensors
+ * concatenated, each in fine-block layout, n_values of them -- exactly the
+ * count the bonds imply (at most 2^34), else DMRG_E_INVAL.  Sites < center
+ * are taken as left-canonical, sites > center+1 as right-canonical; the
+ * center pair is contracted into the two-site vector and environments are
+ * built. */
 dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n_sectors,
-                            const int32_t* sectors, const double* site_values,
+                            const int32_t* sectors, const double* site_values, int64_t n_values,
                             int center, dmrg_mps** out);
 /* Sectors of bond k: call with sectors == NULL to get *n; then 3n ints. */
 dmrg_status dmrg_mps_bond(const dmrg_mps* mps, int bond, int32_t* n, int32_t* sectors);
@@ -210,7 +236,9 @@ void dmrg_mps_free(dmrg_mps* mps);
  *            the merged sector layout above
  * A loaded state continues bit for bit as the saved one would.  Errors:
  * DMRG_E_IO (open, read or write failure, wrong magic, truncated file, sizes
- * inconsistent with the bonds), DMRG_E_INVAL (K, N or 2S_z differ from the
+ * inconsistent with the bonds, more than 2^20 sectors in a bond or 2^24
+ * states in a sector, more than 2^34 site-tensor values), DMRG_E_INVAL (K,
+ * N or 2S_z differ from the
  * MPO's, non-finite values, bonds that break the import rules). */
 dmrg_status dmrg_mps_save(dmrg_ctx* ctx, const dmrg_mps* mps, const char* path);
 dmrg_status dmrg_mps_load(dmrg_ctx* ctx, const dmrg_mpo* mpo, const char* path, dmrg_mps** out);
@@ -238,6 +266,21 @@ dmrg_status dmrg_sigma_diag(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, d
  * out receives D[bond] x m x m FP64 (m = bond dimension), row-major. */
 dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bond,
                             double* out);
+
+/* Environment operators in block form (test hook).  Side 0 = the left
+ * block at bond `bond` (stored for bonds <= center), 1 = the right block
+ * (bonds >= center+2).  The values are channel-major: for each channel x of
+ * the bond (dmrg_mpo_channels order) with shift dq_x = (dN, d2S_z) of its
+ * left operator, the blocks (Q + dq_x <- Q) for Q over the bond's sorted
+ * sectors with Q + dq_x also a sector, each m(Q + dq_x) x m(Q) row-major
+ * (the right block's operators use the same bond labels and shifts).
+ * dmrg_env_size gives the count.  dmrg_env_import replaces the stored
+ * operators (host array of exactly that count, finite, else DMRG_E_INVAL);
+ * the blocked operators and the diagonal of the center are rebuilt from
+ * them by the next call that needs them. */
+dmrg_status dmrg_env_size(const dmrg_mps* mps, int side, int bond, int64_t* n);
+dmrg_status dmrg_env_import(dmrg_ctx* ctx, dmrg_mps* mps, int side, int bond, const double* values,
+                            int64_t n_values);
 
 /* Test hook for the grouped GEMM kernel: C = alpha op(A) op(B) (+ C when
  * accumulate != 0).  A, B, C are DEVICE FP64 pointers, row-major with leading
@@ -281,6 +324,10 @@ typedef struct {
     int32_t n_steps;
     int64_t precond_fallbacks; /* steps whose learned correction fell back to the diagonal one */
     int64_t samples;        /* training samples appended to the network */
+    double max_residual;    /* largest final Davidson residual norm ||H x - theta x|| */
+    int64_t unconverged;    /* Davidson solves that stopped at dav_max_iter with the
+                               residual above dav_tol (then the call returns
+                               DMRG_E_NOCONV, its results kept) */
 } dmrg_sweep_stat;
 
 /* Default options (FP64, tol 1e-9, 200 iterations, subspace 24, keep 4). */

@@ -37,12 +37,21 @@ class SweepStat(C.Structure):
                 ("sigma_flops", c_double), ("sigma_seconds", c_double),
                 ("sigma_calls", c_int64), ("gemm_seconds", c_double), ("gemm_launches", c_int64),
                 ("dav_iters", c_int64), ("max_bond", c_int32),
-                ("n_steps", c_int32), ("precond_fallbacks", c_int64), ("samples", c_int64)]
+                ("n_steps", c_int32), ("precond_fallbacks", c_int64), ("samples", c_int64),
+                ("max_residual", c_double), ("unconverged", c_int64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(c_void_p, C.c_size_t, c_void_p)
+FREE_FN = C.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p)]
 
 
 # name -> (restype, argtypes)
 SIGNATURES = {
-    "dmrg_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "dmrg_ctx_create": (c_int, [c_int, c_void_p, P(Allocator), P(c_void_p)]),
     "dmrg_ctx_destroy": (None, [c_void_p]),
     "dmrg_last_error": (c_char_p, [c_void_p]),
     "dmrg_build_mpo": (c_int, [c_void_p, P(c_double), P(c_double), c_int, c_int, c_int,
@@ -57,8 +66,8 @@ SIGNATURES = {
     "dmrg_sigma_model_flops": (c_int, [c_void_p, c_int, P(c_int32), c_int, P(c_int32), c_int,
                                        P(c_double)]),
     "dmrg_mps_random": (c_int, [c_void_p, c_void_p, c_int, P(c_double), c_int64, P(c_void_p)]),
-    "dmrg_mps_import": (c_int, [c_void_p, c_void_p, P(c_int32), P(c_int32), P(c_double), c_int,
-                                P(c_void_p)]),
+    "dmrg_mps_import": (c_int, [c_void_p, c_void_p, P(c_int32), P(c_int32), P(c_double), c_int64,
+                                c_int, P(c_void_p)]),
     "dmrg_mps_bond": (c_int, [c_void_p, c_int, P(c_int32), P(c_int32)]),
     "dmrg_mps_center": (c_int, [c_void_p, P(c_int)]),
     "dmrg_mps_free": (None, [c_void_p]),
@@ -69,6 +78,8 @@ SIGNATURES = {
     "dmrg_sigma": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, P(c_double)]),
     "dmrg_sigma_diag": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_env_export": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double)]),
+    "dmrg_env_size": (c_int, [c_void_p, c_int, c_int, P(c_int64)]),
+    "dmrg_env_import": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double), c_int64]),
     "dmrg_debug_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
                                 c_void_p, c_int, c_void_p, c_int, c_void_p, c_int, c_int, c_int]),
     "dmrg_sweep_opts_default": (None, [P(SweepOpts)]),

@@ -39,18 +39,64 @@ def _torch_sync():
     torch.cuda.current_stream().synchronize()
 
 
+NOCONV = 4  # DMRG_E_NOCONV: completed, outputs written, some solve hit its iteration limit
+
+
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator on the context's
+    stream (alloc / free of the dmrg_allocator callbacks)."""
+
+    def __init__(self, device, stream):
+        import torch
+        self.torch, self.device, self.stream = torch, device, stream
+
+    def alloc(self, nbytes):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(nbytes, self.device, self.stream)
+        except RuntimeError:  # out of memory
+            return None
+
+    def free(self, ptr):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
 class Context:
-    def __init__(self, device=0, stream=None):
+    """A library context on one GPU (device -1: host only).
+
+    allocator: None (the library's own stream-ordered allocations), "torch"
+    (PyTorch's caching allocator) or an object with alloc(nbytes) -> int
+    device pointer or None, and free(ptr)."""
+
+    def __init__(self, device=0, stream=None, allocator=None):
         self.lib = L.load()
+        torch_stream = None
         if stream is None and device >= 0:
             try:
                 import torch
                 if torch.cuda.is_available():
-                    stream = torch.cuda.current_stream(device).cuda_stream or None
+                    torch_stream = torch.cuda.current_stream(device)
+                    stream = torch_stream.cuda_stream or None
             except ImportError:
                 pass
+        self._alloc = None
+        al = None
+        if allocator is not None:
+            if allocator == "torch":
+                allocator = TorchAllocator(device, torch_stream)
+            self._pyalloc = allocator
+
+            def _a(nbytes, user):
+                p = allocator.alloc(int(nbytes))
+                return int(p) if p else None
+
+            def _f(ptr, user):
+                allocator.free(int(ptr))
+
+            # the callbacks must outlive every state created on the context
+            self._alloc = L.Allocator(L.ALLOC_FN(_a), L.FREE_FN(_f), None)
+            al = C.byref(self._alloc)
         h = C.c_void_p()
-        st = self.lib.dmrg_ctx_create(device, stream, C.byref(h))
+        st = self.lib.dmrg_ctx_create(device, stream, al, C.byref(h))
         if st != 0:
             raise DmrgError(st, "dmrg_ctx_create: " + self.lib.dmrg_last_error(None).decode())
         self.h = h
@@ -67,9 +113,13 @@ class Context:
             self.h, prec, m, n, k, int(ta), int(tb), alpha, C_void(A), A.stride(0), C_void(B),
             B.stride(0), C_void(C), C.stride(0), int(accumulate), int(tile)))
 
-    def check(self, st):
-        if st != 0:
+    def check(self, st, allow_noconv=False):
+        """Raise DmrgError for a failed call; DMRG_E_NOCONV (the call completed
+        and its statistics count the unconverged solves) passes when
+        allow_noconv is set."""
+        if st != 0 and not (allow_noconv and st == NOCONV):
             raise DmrgError(st, self.lib.dmrg_last_error(self.h).decode())
+        return st
 
     def close(self):
         if getattr(self, "h", None):
@@ -212,7 +262,7 @@ class Mps:
         ss, sp = _iptr(secs)
         vv, vp = _dptr(site_values)
         out = C.c_void_p()
-        ctx.check(ctx.lib.dmrg_mps_import(ctx.h, mpo.h, np_, sp, vp, center, C.byref(out)))
+        ctx.check(ctx.lib.dmrg_mps_import(ctx.h, mpo.h, np_, sp, vp, vv.size, center, C.byref(out)))
         return cls(ctx, mpo, out)
 
     def save(self, path):
@@ -275,12 +325,27 @@ class Mps:
                                                 out.ctypes.data_as(C.POINTER(C.c_double))))
         return out.reshape(D, m, m)
 
+    def env_size(self, side, bond):
+        n = C.c_int64()
+        self.ctx.check(self.lib.dmrg_env_size(self.h, side, bond, C.byref(n)))
+        return n.value
+
+    def env_import(self, side, bond, values):
+        """Replace the environment at (side, bond) with channel-major block
+        values (the format of dmrg_env_import)."""
+        vv, vp = _dptr(values)
+        self.ctx.check(self.lib.dmrg_env_import(self.ctx.h, self.h, side, bond, vp, vv.size))
+
     def sweep(self, M, n_sweeps, opts=None):
+        """n_sweeps sweeps; per-sweep statistics (their "unconverged" field
+        counts solves that hit the iteration limit) and the last sweep's
+        thetas."""
         opts = opts or default_opts()
         st = (L.SweepStat * max(1, n_sweeps))()
         th = np.zeros(2 * (self.mpo.K - 1))
         self.ctx.check(self.lib.dmrg_sweep(self.ctx.h, self.h, self.mpo.h, M, n_sweeps,
-                                           C.byref(opts), st, th.ctypes.data_as(C.POINTER(C.c_double))))
+                                           C.byref(opts), st, th.ctypes.data_as(C.POINTER(C.c_double))),
+                       allow_noconv=True)
         stats = [{f: getattr(st[i], f) for f, _ in L.SweepStat._fields_} for i in range(n_sweeps)]
         return stats, th
 
@@ -289,7 +354,7 @@ class Mps:
         st = L.SweepStat()
         th = C.c_double()
         self.ctx.check(self.lib.dmrg_step(self.ctx.h, self.h, self.mpo.h, M, int(bool(forward)),
-                                          C.byref(opts), C.byref(th), C.byref(st)))
+                                          C.byref(opts), C.byref(th), C.byref(st)), allow_noconv=True)
         return th.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
 
     def set_psi(self, psi):
@@ -302,7 +367,7 @@ class Mps:
         opts = opts or default_opts()
         th, rn, st = C.c_double(), C.c_double(), L.SweepStat()
         self.ctx.check(self.lib.dmrg_solve(self.ctx.h, self.h, self.mpo.h, C.byref(opts), C.byref(th),
-                                           C.byref(rn), C.byref(st)))
+                                           C.byref(rn), C.byref(st)), allow_noconv=True)
         return th.value, rn.value, {f: getattr(st, f) for f, _ in L.SweepStat._fields_}
 
     def move(self, forward=True):
@@ -435,7 +500,7 @@ def sweep_batched(ctx, states, Ms, n_sweeps, opts=None):
     st = (L.SweepStat * max(1, n * n_sweeps))()
     bs = C.c_double()
     ctx.check(ctx.lib.dmrg_sweep_batched(ctx.h, n, hm, hp, Mv, n_sweeps, C.byref(opts), st,
-                                         C.byref(bs)))
+                                         C.byref(bs)), allow_noconv=True)
     out = [[{f: getattr(st[b * n_sweeps + i], f) for f, _ in L.SweepStat._fields_}
             for i in range(n_sweeps)] for b in range(n)]
     return out, bs.value

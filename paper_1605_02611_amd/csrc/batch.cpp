@@ -23,6 +23,7 @@ namespace dmrg {
 OwnCtx::OwnCtx(const Ctx& base) {
     c.device = base.device;
     c.max_lds = base.max_lds;
+    c.alloc = base.alloc;
     DMRG_HIP(hipSetDevice(c.device));
     DMRG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     c.own_stream = true;
@@ -54,8 +55,10 @@ void parallel_for(int n, int device, F f) {
     std::atomic<int> next{0};
     std::exception_ptr err;
     std::mutex mu;
+    const DevAllocator* al = tl_alloc;  // the caller's allocator, in every thread
     auto work = [&]() {
         (void)hipSetDevice(device);
+        AllocScope scope(al);
         for (int i = next++; i < n; i = next++) {
             try {
                 f(i);
@@ -342,7 +345,7 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                 const DavOut dv = dp[a]->result();
                 ds[a].reset();
                 S.theta = dv.theta;
-                S.dav_iters += dv.iters;
+                note_davidson(S, dv);
                 const bool forward = t < nsteps[b] / 2;
                 act[a]->finish_step(M[b], forward, o, S, true, dv, 0, 0, 0, S.sigma_seconds);
                 DMRG_HIP(hipStreamSynchronize(act[a]->ctx->stream));

@@ -1,6 +1,7 @@
 // C ABI of the DMRG library (declared in include/dmrg.h).  Every entry point
 // catches internal errors, stores the message on the context and returns a
 // status code.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -17,6 +18,7 @@ using namespace dmrg;
 // the order of the *_free / *_destroy calls does not matter.
 struct dmrg_ctx {
     Ctx c;
+    DevAllocator alloc;  // the caller's allocator (c.alloc points here when set)
     std::atomic<int> refs{1};
 };
 struct dmrg_mpo {
@@ -41,6 +43,7 @@ template <class F>
 dmrg_status guard(dmrg_ctx* ctx, F&& f) {
     try {
         if (ctx) ctx->c.err.clear();
+        AllocScope scope(ctx ? ctx->c.alloc : nullptr);
         f();
         return DMRG_OK;
     } catch (const Error& e) {
@@ -92,6 +95,21 @@ void fill_stat(dmrg_sweep_stat& d, const StepStats& x, double energy, double sec
     d.n_steps = n_steps;
     d.precond_fallbacks = x.precond_fallbacks;
     d.samples = x.samples;
+    d.max_residual = x.max_rnorm;
+    d.unconverged = x.unconverged;
+}
+
+// DMRG_E_NOCONV after a call that completed and wrote its outputs but in
+// which some Davidson solve stopped at its iteration limit.
+dmrg_status noconv_status(dmrg_ctx* ctx, dmrg_status st, int64_t unconverged, double max_rnorm) {
+    if (st != DMRG_OK || unconverged == 0) return st;
+    char buf[160];
+    std::snprintf(buf, sizeof buf,
+                  "%lld Davidson solve(s) stopped at the iteration limit (largest final residual %.3e); "
+                  "results kept",
+                  (long long)unconverged, max_rnorm);
+    ctx->c.err = buf;
+    return DMRG_E_NOCONV;
 }
 
 void use_device(const Ctx& c) {
@@ -105,10 +123,20 @@ static thread_local std::string g_create_err;
 
 extern "C" {
 
-dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx** out) {
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, const dmrg_allocator* allocator, dmrg_ctx** out) {
     if (!out) return DMRG_E_INVAL;
+    if (allocator && (!allocator->alloc || !allocator->free)) {
+        g_create_err = "an allocator needs both alloc and free";
+        return DMRG_E_INVAL;
+    }
     auto* ctx = new (std::nothrow) dmrg_ctx();
     if (!ctx) return DMRG_E_NOMEM;
+    if (allocator) {
+        ctx->alloc.alloc = allocator->alloc;
+        ctx->alloc.free = allocator->free;
+        ctx->alloc.user = allocator->user;
+        ctx->c.alloc = &ctx->alloc;
+    }
     dmrg_status st = guard(ctx, [&] {
         if (device == -1) {  // host-only context: MPO construction and queries
             ctx->c.device = -1;
@@ -306,6 +334,25 @@ dmrg_status dmrg_two_site_index(const int32_t* left, int n_left, const int32_t* 
 }
 
 namespace {
+constexpr int kMaxSectors = 1 << 20;     // sectors per bond
+constexpr int kMaxSectorDim = 1 << 24;   // states per sector
+constexpr int64_t kMaxSiteValues = int64_t(1) << 34;
+
+// Number of site-tensor values the bonds imply (fine blocks of every site);
+// DMRG_E_INVAL past kMaxSiteValues.
+int64_t site_value_count(const std::vector<std::vector<std::pair<QN, int>>>& b) {
+    int64_t n = 0;
+    for (size_t j = 0; j + 1 < b.size(); ++j)
+        for (const auto& [ql, ml] : b[j])
+            for (int s = 0; s < 4; ++s)
+                for (const auto& [qr, mr] : b[j + 1])
+                    if (qr == ql + kSiteQN[s]) {
+                        n += int64_t(ml) * mr;
+                        require(n <= kMaxSiteValues, "site tensors too large");
+                    }
+    return n;
+}
+
 Bond bond_from_triples(const int32_t* t, int cnt) {
     Bond b;
     for (int i = 0; i < cnt; ++i) {
@@ -352,8 +399,8 @@ dmrg_status dmrg_mps_random(dmrg_ctx* ctx, const dmrg_mpo* mpo, int M, const dou
 }
 
 dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n_sectors,
-                            const int32_t* sectors, const double* site_values, int center,
-                            dmrg_mps** out) {
+                            const int32_t* sectors, const double* site_values, int64_t n_values,
+                            int center, dmrg_mps** out) {
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(mpo && n_sectors && sectors && site_values && out, "null argument");
@@ -363,12 +410,13 @@ dmrg_status dmrg_mps_import(dmrg_ctx* ctx, const dmrg_mpo* mpo, const int32_t* n
         std::vector<std::vector<std::pair<QN, int>>> b(K + 1);
         int64_t p = 0;
         for (int k = 0; k <= K; ++k) {
-            require(n_sectors[k] >= 1, "every bond needs a sector");
+            require(n_sectors[k] >= 1 && n_sectors[k] <= kMaxSectors, "sector count out of range");
             for (int i = 0; i < n_sectors[k]; ++i, p += 3) {
-                require(sectors[p + 2] >= 1, "sector dimensions must be >= 1");
+                require(sectors[p + 2] >= 1 && sectors[p + 2] <= kMaxSectorDim, "sector dimension out of range");
                 b[k].push_back({QN{sectors[p], sectors[p + 1]}, sectors[p + 2]});
             }
         }
+        require(n_values == site_value_count(b), "n_values does not match the site tensors the bonds imply");
         auto st = std::make_unique<State>(&ctx->c, mpo->m.get());
         st->import_tensors(b, site_values, center);
         auto* r = new dmrg_mps();
@@ -470,19 +518,19 @@ dmrg_status dmrg_mps_load(dmrg_ctx* ctx, const dmrg_mpo* mpo, const char* path, 
         int64_t expect = 0;
         for (int k = 0; k <= m.K; ++k) {
             const int32_t n = F.get_i32();
-            if (n < 1 || n > (1 << 20)) throw Error(E_IO, "bad sector count");
+            if (n < 1 || n > kMaxSectors) throw Error(E_IO, "bad sector count");
             for (int i = 0; i < n; ++i) {
                 int32_t t[3];
                 F.get(t, sizeof(t));
-                require(t[2] >= 1, "sector dimensions must be >= 1");
+                if (t[2] < 1 || t[2] > kMaxSectorDim) throw Error(E_IO, "bad sector dimension");
                 b[k].push_back({QN{t[0], t[1]}, t[2]});
             }
         }
-        for (int j = 0; j < m.K; ++j)
-            for (const auto& [ql, ml] : b[j])
-                for (int s = 0; s < 4; ++s)
-                    for (const auto& [qr, mr] : b[j + 1])
-                        if (qr == ql + kSiteQN[s]) expect += int64_t(ml) * mr;
+        try {
+            expect = site_value_count(b);
+        } catch (const Error&) {
+            throw Error(E_IO, "site tensors of the file's bonds are too large");
+        }
         const int64_t ns = F.get_i64();
         if (ns != expect) throw Error(E_IO, "site tensor size does not match the bonds");
         std::vector<double> sites(static_cast<size_t>(ns));
@@ -578,7 +626,9 @@ dmrg_status dmrg_psi_import(dmrg_ctx* ctx, dmrg_mps* mps, const double* psi_host
 dmrg_status dmrg_solve(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const dmrg_sweep_opts* opts,
                        double* theta, double* rnorm, dmrg_sweep_stat* stat) {
     if (!ctx) return DMRG_E_INVAL;
-    return guard(ctx, [&] {
+    int64_t unconv = 0;
+    double maxr = 0;
+    const dmrg_status st = guard(ctx, [&] {
         require(mps && mpo, "null argument");
         require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
         use_device(ctx->c);
@@ -590,7 +640,10 @@ dmrg_status dmrg_solve(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const 
         if (theta) *theta = dv.theta;
         if (rnorm) *rnorm = dv.rnorm;
         if (stat) fill_stat(*stat, s, dv.theta, std::chrono::duration<double>(t1 - t0).count(), 0);
+        unconv = s.unconverged;
+        maxr = s.max_rnorm;
     });
+    return noconv_status(ctx, st, unconv, maxr);
 }
 
 dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
@@ -630,6 +683,26 @@ dmrg_status dmrg_env_export(dmrg_ctx* ctx, const dmrg_mps* mps, int side, int bo
         std::vector<double> h;
         mps->st->env_dense(side, bond, h);
         std::memcpy(out, h.data(), h.size() * sizeof(double));
+    });
+}
+
+dmrg_status dmrg_env_size(const dmrg_mps* mps, int side, int bond, int64_t* n) {
+    if (!mps || !n || (side != 0 && side != 1)) return DMRG_E_INVAL;
+    try {
+        *n = mps->st->env_size(side, bond);
+    } catch (const Error& e) {
+        return dmrg_status(e.code);
+    }
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_env_import(dmrg_ctx* ctx, dmrg_mps* mps, int side, int bond, const double* values,
+                            int64_t n_values) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && values && (side == 0 || side == 1), "bad argument");
+        use_device(ctx->c);
+        mps->st->env_import(side, bond, values, n_values);
     });
 }
 
@@ -694,7 +767,9 @@ void dmrg_sweep_opts_default(dmrg_sweep_opts* o) {
 dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int forward,
                       const dmrg_sweep_opts* opts, double* theta, dmrg_sweep_stat* stat) {
     if (!ctx) return DMRG_E_INVAL;
-    return guard(ctx, [&] {
+    int64_t unconv = 0;
+    double maxr = 0;
+    const dmrg_status status = guard(ctx, [&] {
         require(mps && mpo, "null argument");
         require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
         require(M >= 1, "M must be >= 1");
@@ -706,13 +781,18 @@ dmrg_status dmrg_step(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, 
         auto t1 = std::chrono::steady_clock::now();
         if (theta) *theta = th;
         if (stat) fill_stat(*stat, s, th, std::chrono::duration<double>(t1 - t0).count(), 1);
+        unconv = s.unconverged;
+        maxr = s.max_rnorm;
     });
+    return noconv_status(ctx, status, unconv, maxr);
 }
 
 dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M, int n_sweeps,
                        const dmrg_sweep_opts* opts, dmrg_sweep_stat* stats, double* thetas) {
     if (!ctx) return DMRG_E_INVAL;
-    return guard(ctx, [&] {
+    int64_t unconv = 0;
+    double maxr = 0;
+    const dmrg_status status = guard(ctx, [&] {
         require(mps && mpo, "null argument");
         require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
         require(M >= 1 && n_sweeps >= 0, "bad M or n_sweeps");
@@ -736,8 +816,11 @@ dmrg_status dmrg_sweep(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int M,
             }
             auto t1 = std::chrono::steady_clock::now();
             if (stats) fill_stat(stats[sw], s, th, std::chrono::duration<double>(t1 - t0).count(), step);
+            unconv += s.unconverged;
+            maxr = std::max(maxr, s.max_rnorm);
         }
     });
+    return noconv_status(ctx, status, unconv, maxr);
 }
 
 dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward) {
@@ -760,7 +843,9 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps, const
                                const int* M, int n_sweeps, const dmrg_sweep_opts* opts,
                                dmrg_sweep_stat* stats, double* batch_sigma_seconds) {
     if (!ctx) return DMRG_E_INVAL;
-    return guard(ctx, [&] {
+    int64_t unconv = 0;
+    double maxr = 0;
+    const dmrg_status status = guard(ctx, [&] {
         require(n >= 1 && mps && mpo && M && n_sweeps >= 0, "bad batched arguments");
         use_device(ctx->c);
         std::vector<State*> st(n);
@@ -779,13 +864,15 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps, const
         double bs = 0;
         sweep_batched(&ctx->c, st, Mv, n_sweeps, o, S, secs, &bs);
         if (batch_sigma_seconds) *batch_sigma_seconds = bs;
-        if (stats)
-            for (int b = 0; b < n; ++b)
-                for (int sw = 0; sw < n_sweeps; ++sw) {
-                    const StepStats& x = S[b][sw];
-                    fill_stat(stats[size_t(b) * n_sweeps + sw], x, x.theta, secs[b][sw], 2 * (mpo[b]->m->K - 1));
-                }
+        for (int b = 0; b < n; ++b)
+            for (int sw = 0; sw < n_sweeps; ++sw) {
+                const StepStats& x = S[b][sw];
+                if (stats) fill_stat(stats[size_t(b) * n_sweeps + sw], x, x.theta, secs[b][sw], 2 * (mpo[b]->m->K - 1));
+                unconv += x.unconverged;
+                maxr = std::max(maxr, x.max_rnorm);
+            }
     });
+    return noconv_status(ctx, status, unconv, maxr);
 }
 
 // ---- autotuner -------------------------------------------------------------------

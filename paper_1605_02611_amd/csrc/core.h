@@ -280,11 +280,32 @@ void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipSt
 constexpr int kJacobiRoundMin = 160;  // sectors with at least this many columns use the round launches
 
 // ---------------------------------------------------------------------------
-// device memory: stream-ordered allocations
+// device memory: stream-ordered allocations, or a caller's allocator
+
+// Device allocator supplied by the caller of a context (alloc returns NULL
+// on failure).  Memory from it is released with free after the device has
+// finished every queued use of it.
+struct DevAllocator {
+    void* (*alloc)(size_t bytes, void* user) = nullptr;
+    void (*free)(void* p, void* user) = nullptr;
+    void* user = nullptr;
+};
+// Allocator of the library call running on this thread (nullptr:
+// hipMallocAsync on the buffer's stream).
+extern thread_local const DevAllocator* tl_alloc;
+struct AllocScope {
+    const DevAllocator* prev;
+    explicit AllocScope(const DevAllocator* a) : prev(tl_alloc) { tl_alloc = a; }
+    ~AllocScope() { tl_alloc = prev; }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t s = nullptr;
+    const DevAllocator* al = nullptr;  // allocator p came from (nullptr: hipMallocAsync)
     DevBuf() = default;
     DevBuf(size_t b, hipStream_t st) { alloc(b, st); }
     void alloc(size_t b, hipStream_t st);
@@ -299,6 +320,7 @@ struct DevBuf {
             p = o.p;
             bytes = o.bytes;
             s = o.s;
+            al = o.al;
             o.p = nullptr;
             o.bytes = 0;
         }

@@ -376,7 +376,7 @@ void State::run_blocking(Blocked& B, const Env& src, int plan_key) {
     }
     BlockPlan& P = plans[plan_key];
     if (P.key != key) {
-        P.key = key;
+        P.key.clear();  // set again once the plan is uploaded
         P.gemm.clear();
         P.dense.assign(nc, 0);
         std::vector<int64_t> cm_off(nc, -1);
@@ -416,6 +416,7 @@ void State::run_blocking(Blocked& B, const Env& src, int plan_key) {
         int64_t sz[kMaxBufs] = {int64_t(cm.size()), src.total, B.total};
         validate_list(P.gemm, sz);
         P.gemm.upload(s);
+        P.key = key;
     }
     if (!P.gemm.tasks.empty()) {
         Bases b{};
@@ -1473,7 +1474,7 @@ void State::prepare() {
 }
 
 void State::ensure_f32() {
-    if (Y.buf32.p) return;
+    if (Y.buf32.p && Z.buf32.p && psi32.p && sig32.p && tbuf32.p && (splits <= 1 || part32.p)) return;
     hipStream_t s = ctx->stream;
     Y.buf32.alloc(std::max<int64_t>(1, Y.total) * sizeof(float), s);
     launch_to_f32(Y.buf32.as<float>(), Y.buf.as<double>(), Y.total, s);
@@ -1822,6 +1823,7 @@ bool DavSolver::advance() {
     }
     const bool low = !refined_ && o_.refine_tol > 0;
     if ((rn <= o_.dav_tol && !low) || napply_ - iter0_ >= o_.dav_max_iter) {
+        res_.converged = rn <= o_.dav_tol && !low;
         finish();
         return false;
     }
@@ -1871,7 +1873,7 @@ bool DavSolver::advance() {
     }
     const double nt = std::sqrt(dots(t, 0, 1, t)[0]);
     check_finite(nt, "Davidson correction");
-    if (nt < 1e-14) {
+    if (nt < 1e-14) {  // no new direction: the subspace holds the eigenvector
         finish();
         return false;
     }
@@ -1894,12 +1896,18 @@ DavOut davidson(State& st, double* x, int64_t n, const SweepOpts& o, StepStats& 
 
 }  // namespace
 
+void note_davidson(StepStats& st, const DavOut& dv) {
+    st.dav_iters += dv.iters;
+    st.max_rnorm = std::max(st.max_rnorm, dv.rnorm);
+    if (!dv.converged) st.unconverged += 1;
+}
+
 DavOut State::solve(const SweepOpts& o, StepStats& stt) {
     prepare();
     build_diag();
     const DavOut dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
     stt.theta = dv.theta;
-    stt.dav_iters += dv.iters;
+    note_davidson(stt, dv);
     return dv;
 }
 
@@ -1917,7 +1925,7 @@ double State::step(int M, bool forward, const SweepOpts& o, StepStats& stt, bool
         t2 = clk::now();
         dv = davidson(*this, psi.as<double>(), ts.n, o, stt);
         stt.theta = dv.theta;
-        stt.dav_iters += dv.iters;
+        note_davidson(stt, dv);
     } else {
         // gauge move: split the current vector exactly
         M = std::numeric_limits<int>::max();
@@ -2284,6 +2292,36 @@ void State::env_dense(int side, int bond, std::vector<double>& out) {
                     out[(x * m + b.off[blk.out] + r) * m + b.off[blk.in] + c] =
                         h[e->off[x] + blk.off + int64_t(r) * blk.cols + c];
     }
+}
+
+int64_t State::env_size(int side, int bond) const {
+    require(bond >= 0 && bond <= mpo->K, "bond out of range");
+    const Env* e = side == 0 ? L[bond].get() : R[bond].get();
+    require(e != nullptr, "environment not stored at that bond", E_STATE);
+    return e->total;
+}
+
+void State::env_import(int side, int bond, const double* vals, int64_t n) {
+    hipStream_t s = ctx->stream;
+    require(bond >= 0 && bond <= mpo->K, "bond out of range");
+    Env* e = side == 0 ? L[bond].get() : R[bond].get();
+    require(e != nullptr, "environment not stored at that bond", E_STATE);
+    require(n == e->total, "value count does not match the environment's blocks");
+    for (int64_t i = 0; i < n; ++i) require(std::isfinite(vals[i]), "non-finite environment value");
+    // channel-major input (each channel's blocks in layout order) -> the
+    // storage grouped by shift
+    std::vector<double> h(std::max<int64_t>(1, e->total));
+    const BondL& b = bonds[bond];
+    int64_t pos = 0;
+    for (size_t x = 0; x < mpo->chans[bond].size(); ++x) {
+        const int64_t sz = b.layout(mpo->chan_dq[bond][x]).size;
+        std::copy(vals + pos, vals + pos + sz, h.begin() + e->off[x]);
+        pos += sz;
+    }
+    require(pos == n, "internal: environment layout", E_STATE);
+    DMRG_HIP(hipMemcpyAsync(e->buf.p, h.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    release_workspace();  // blocked operators and the diagonal depend on it
 }
 
 }  // namespace dmrg

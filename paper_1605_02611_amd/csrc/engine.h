@@ -193,6 +193,8 @@ struct Ctx {
     // stream, and its fork / join events; created on first use
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // the caller's device allocator (nullptr: hipMallocAsync)
+    const DevAllocator* alloc = nullptr;
 };
 void ensure_side(Ctx& c);
 void destroy_side(Ctx& c);
@@ -220,12 +222,17 @@ struct StepStats {
     int64_t precond_fallbacks = 0;  // steps whose learned correction was dropped for the diagonal one
     int64_t samples = 0;            // training samples collected
     int max_bond = 0;
+    double max_rnorm = 0;           // largest final Davidson residual norm
+    int64_t unconverged = 0;        // solves that stopped at the iteration limit
 };
 
 struct DavOut {
     double theta = 0, rnorm = 0;
     int iters = 0;
+    bool converged = true;  // false: stopped at the iteration limit with ||r|| > tol
 };
+// Record a Davidson result in the step statistics.
+void note_davidson(StepStats& st, const DavOut& dv);
 
 class State;
 
@@ -364,6 +371,9 @@ class State {
                        const DavOut& dv, double tb, double td, double tv, double sig0, double pass1_0 = -1.0);
     double energy();
     void env_dense(int side, int bond, std::vector<double>& out);
+    // environment values in the channel-major block format of dmrg_env_import
+    int64_t env_size(int side, int bond) const;
+    void env_import(int side, int bond, const double* vals, int64_t n);
 
   private:
     void set_bond(int k, const std::vector<std::pair<QN, int>>& secs);

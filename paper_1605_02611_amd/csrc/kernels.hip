@@ -1391,11 +1391,23 @@ void launch_jacobi_svd(const SvdJob* jobs, int n_jobs, int lds_elems, hipStream_
     DMRG_HIP(hipGetLastError());
 }
 
+thread_local const DevAllocator* tl_alloc = nullptr;
+
 void DevBuf::alloc(size_t b, hipStream_t st) {
     free();
     s = st;
     bytes = b;
+    al = nullptr;
     if (b == 0) return;
+    if (tl_alloc && tl_alloc->alloc) {
+        p = tl_alloc->alloc(b, tl_alloc->user);
+        if (!p) {
+            bytes = 0;
+            throw Error(E_NOMEM, "the caller's allocator returned no memory for " + std::to_string(b) + " bytes");
+        }
+        al = tl_alloc;
+        return;
+    }
     hipError_t e = hipMallocAsync(&p, b, st);
     if (e != hipSuccess) {
         p = nullptr;
@@ -1406,9 +1418,19 @@ void DevBuf::alloc(size_t b, hipStream_t st) {
     }
 }
 void DevBuf::free() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) {
+        if (al) {
+            // the allocator may hand the memory out again at once: let every
+            // queued use of it finish first
+            (void)hipDeviceSynchronize();
+            al->free(p, al->user);
+        } else {
+            (void)hipFreeAsync(p, s);
+        }
+    }
     p = nullptr;
     bytes = 0;
+    al = nullptr;
 }
 
 }  // namespace dmrg

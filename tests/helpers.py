@@ -88,6 +88,38 @@ def merged_to_dense(vec, lab_l, lab_r):
     return out.reshape(shape)
 
 
+# --- environment operators in the channel-major block format of dmrg_env_import ----
+
+def env_block_shapes(sectors_list, shifts):
+    """Per channel the blocks (Q + dq <- Q) of a bond with sectors
+    [(N, 2Sz, dim)] (sorted): list over channels of [(out, in, rows, cols)]
+    with sector indices, in the documented order."""
+    idx = {(n, s): i for i, (n, s, _) in enumerate(sectors_list)}
+    out = []
+    for dq in shifts:
+        blocks = []
+        for i, (n, s, d) in enumerate(sectors_list):
+            o = idx.get((n + dq[0], s + dq[1]))
+            if o is not None:
+                blocks.append((o, i, sectors_list[o][2], d))
+        out.append(blocks)
+    return out
+
+
+def env_blocks_to_dense(values, sectors_list, shifts):
+    """Block values -> dense (D, m, m) with states in sector order."""
+    offs = np.cumsum([0] + [d for _, _, d in sectors_list])
+    m = int(offs[-1])
+    dense = np.zeros((len(shifts), m, m))
+    pos = 0
+    for x, blocks in enumerate(env_block_shapes(sectors_list, shifts)):
+        for o, i, r, c in blocks:
+            dense[x, offs[o]:offs[o] + r, offs[i]:offs[i] + c] = np.asarray(values[pos:pos + r * c]).reshape(r, c)
+            pos += r * c
+    assert pos == len(values)
+    return dense
+
+
 # --- MPS checkpoint files (the layout documented with dmrg_mps_save) ------------------
 
 MPS_MAGIC = b"DMRGMPS\x01"
