@@ -64,11 +64,14 @@ def _patterns(W, side, chans_outer):
     return pat
 
 
-def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right):
+def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_sectors=None):
     """Model flops (system side, environment side) of one sigma at the pair
     (j, j+1).  Wj, Wj1: sparse site tensors {(x, y): 4x4} of the oracle MPO;
     chans_*: channel labels of bonds j, j+1, j+2; left, right: {(N, 2Sz):
-    dim} of bonds j and j+2.  Integers only."""
+    dim} of bonds j and j+2.  out_sectors (optional): count only the work
+    whose result lands in these middle sectors of sigma (both sides: the
+    system-side product of channel y feeds sector q + dq_y).  Integers
+    only."""
     def cols(q):  # C(q): columns (t, Q_r) of middle sector q
         return sum(right.get(_shift(q, SITE_QN[t]), 0) for t in range(4))
 
@@ -90,6 +93,7 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right):
         if not (nonzero(ps, left) and nonzero(pe, right)):
             continue
         dq_y = channel_qn(ch)
+        keep = (lambda q2: True) if out_sectors is None else (lambda q2: q2 in out_sectors)
         if ch[0] != "I":
             for sp, s, dqx in ps:
                 for Ql, ml in left.items():
@@ -97,7 +101,7 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right):
                     if Qo not in left:
                         continue
                     q = _shift(Ql, SITE_QN[s])
-                    if middle(q) and middle(_shift(q, dq_y)):
+                    if middle(q) and middle(_shift(q, dq_y)) and keep(_shift(q, dq_y)):
                         f_sys += 2 * left[Qo] * ml * cols(q)
         if ch[0] != "H":
             for tp, t, dqz in pe:
@@ -107,7 +111,7 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right):
                         continue
                     q = _shift(Qr, SITE_QN[t], -1)
                     q2 = _shift(q, dq_y)
-                    if middle(q) and middle(q2):
+                    if middle(q) and middle(q2) and keep(q2):
                         f_env += 2 * right[Qo] * mr * rows(q2)
     return f_sys, f_env
 

@@ -143,11 +143,14 @@ struct BatchSigma {
         htab[0].assign(size_t(8) * nb, nullptr);
         p1.tile = st[0]->pass1.tile;
         p2.tile = st[0]->pass2.tile;
+        p1.tile_n = st[0]->pass1.tile_n;
+        p2.tile_n = st[0]->pass2.tile_n;
         p1.variant = st[0]->pass1.variant;
         p2.variant = st[0]->pass2.variant;
         for (int b = 0; b < nb; ++b) {
             State& S = *st[b];
-            require(S.pass1.tile == p1.tile && S.pass2.tile == p2.tile && S.pass1.variant == p1.variant &&
+            require(S.pass1.tile == p1.tile && S.pass2.tile == p2.tile && S.pass1.tile_n == p1.tile_n &&
+                        S.pass2.tile_n == p2.tile_n && S.pass1.variant == p1.variant &&
                         S.pass2.variant == p2.variant,
                     "batched sigma: instances with different launch configurations", E_STATE);
             merge(p1, S.pass1, b, r1);
@@ -272,7 +275,8 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
         if (!st[0]->cfg_explicit) tune_lookup(st[0]->tune_key(), common);
         for (State* S : st) {
             if (S->cfg.tile1 != common.tile1 || S->cfg.tile2 != common.tile2 || S->cfg.variant != common.variant ||
-                S->cfg.pieces != common.pieces)
+                S->cfg.pieces != common.pieces || S->cfg.wide1 != common.wide1 || S->cfg.wide2 != common.wide2 ||
+                S->cfg.rows2 != common.rows2 || S->cfg.order1 != common.order1 || S->cfg.order2 != common.order2)
                 S->invalidate();
             S->cfg = common;
             S->cfg_explicit = true;

@@ -712,7 +712,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
-        require(tile == 64 || tile == 32, "tile must be 64 or 32");
+        require(tile == 64 || tile == 32 || tile == 128 || tile == 256, "tile must be 32, 64, 128 or 256");
         require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
         require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
         use_device(ctx->c);
@@ -721,7 +721,8 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
         const int64_t nb = tb ? int64_t(n - 1) * ldb + k : int64_t(k - 1) * ldb + n;
         const int64_t nc = int64_t(m - 1) * ldc + n;
         GemmList L;
-        L.tile = tile;
+        L.tile = tile > 64 ? 64 : tile;
+        L.tile_n = tile > 64 ? tile : 0;
         std::vector<UTerm> terms = {{0, 0, lda, ta != 0, 1, 0, ldb, tb != 0, k, alpha, true}};
         add_unit(L, 2, 0, ldc, m, n, accumulate ? 1 : 0, terms);
         int64_t sz[kMaxBufs] = {na, nb, nc};
@@ -888,18 +889,39 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
         State& st = *mps->st;
         hipStream_t s = ctx->c.stream;
         std::vector<SigmaConfig> cand;
+        // square tiles of 64 or 32 in either pass, two split-K targets
         for (int t1 : {64, 32})
             for (int t2 : {64, 32})
-                for (double pc : {4096.0, 16384.0, 65536.0})
-                    for (int v : {0, 2}) {
-                        if (t1 == 32 && t2 == 32 && v != 0) continue;  // the variant applies to tile-64 passes
-                        SigmaConfig c;
-                        c.tile1 = t1;
-                        c.tile2 = t2;
-                        c.pieces = pc;
-                        c.variant = v;
-                        cand.push_back(c);
-                    }
+                for (double pc : {16384.0, 65536.0}) {
+                    SigmaConfig c;
+                    c.tile1 = t1;
+                    c.tile2 = t2;
+                    c.pieces = pc;
+                    c.variant = t1 == 32 && t2 == 32 ? 0 : 2;
+                    cand.push_back(c);
+                }
+        // sector-major pass-1 order and aligned pass-2 pieces
+        for (int o1 : {0, 1})
+            for (int o2 : {0, 1}) {
+                if (o1 == 0 && o2 == 0) continue;  // above
+                SigmaConfig c;
+                c.order1 = o1;
+                c.order2 = o2;
+                c.variant = 2;
+                cand.push_back(c);
+            }
+        // 64 x 128 tiles in pass 1; 64 x 128 / 128 x 64 / 128 x 128 tiles in pass 2
+        const int p2[4][2] = {{64, 0}, {64, 128}, {128, 64}, {128, 128}};  // (rows, cols), cols 0: square 64
+        for (int w1 : {0, 128})
+            for (const auto& r2 : p2) {
+                if (w1 == 0 && r2[1] == 0) continue;  // square in both passes: above
+                SigmaConfig c;
+                c.wide1 = w1;
+                c.rows2 = r2[0];
+                c.wide2 = r2[1];
+                c.variant = 2;
+                cand.push_back(c);
+            }
         st.prepare();
         const int64_t n = st.ts.n;
         DevBuf y(std::max<int64_t>(1, n) * sizeof(double), s);
@@ -916,18 +938,26 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
             StepStats ss;
             for (int r = 0; r < reps; ++r) st.sigma(x, y.as<double>(), Prec(prec), &ss);
             const double t = ss.sigma_seconds / reps;
-            char buf[200];
-            std::snprintf(buf, sizeof buf, "%s{\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"ms\": %.4f}",
-                          i ? ", " : "", cand[i].tile1, cand[i].tile2, cand[i].pieces, cand[i].variant, t * 1e3);
+            char buf[320];
+            std::snprintf(buf, sizeof buf,
+                          "%s{\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"wide1\": %d, "
+                          "\"wide2\": %d, \"rows2\": %d, \"order1\": %d, \"order2\": %d, \"ms\": %.4f, "
+                          "\"ms_pass1\": %.4f}",
+                          i ? ", " : "", cand[i].tile1, cand[i].tile2, cand[i].pieces, cand[i].variant, cand[i].wide1,
+                          cand[i].wide2, cand[i].rows2, cand[i].order1, cand[i].order2, t * 1e3,
+                          ss.pass1_seconds / reps * 1e3);
             rep += buf;
             if (t < best_t) {
                 best_t = t;
                 best = cand[i];
             }
         }
-        char buf[200];
-        std::snprintf(buf, sizeof buf, "], \"best\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"ms\": %.4f}}",
-                      best.tile1, best.tile2, best.pieces, best.variant, best_t * 1e3);
+        char buf[320];
+        std::snprintf(buf, sizeof buf,
+                      "], \"best\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.0f, \"variant\": %d, \"wide1\": %d, "
+                      "\"wide2\": %d, \"rows2\": %d, \"order1\": %d, \"order2\": %d, \"ms\": %.4f}}",
+                      best.tile1, best.tile2, best.pieces, best.variant, best.wide1, best.wide2, best.rows2,
+                      best.order1, best.order2, best_t * 1e3);
         rep += buf;
         tune_store(st.tune_key(), best);
         st.cfg = best;

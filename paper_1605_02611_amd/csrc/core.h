@@ -185,19 +185,25 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 // the tasks and terms; active: DEVICE flags per instance or nullptr
 // tile: output tile edge of every task (64 or 32); variant (tile 64): 0
 // plain, 1 packed K-steps, 2 software pipeline, 3 persistent pipeline, -1
-// the process default (2, or DMRG_GEMM_VARIANT)
+// the process default (2, or DMRG_GEMM_VARIANT); tile_n > 0 (128 or 256):
+// tiles of 64 rows and tile_n columns (wide_gemm) instead of square ones
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* bases, const int* active, hipStream_t s, int tile = kTile, int variant = -1);
+                 void* const* bases, const int* active, hipStream_t s, int tile = kTile, int variant = -1,
+                 int tile_n = 0);
 // same kernel, separate symbol for the two passes of the sigma vector
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                        void* const* bases, const int* active, hipStream_t s, int tile = kTile,
-                       int variant = -1);
+                       int variant = -1, int tile_n = 0);
 
 // Launch configuration of the two sigma passes (chosen by the autotuner).
 struct SigmaConfig {
     int tile1 = kTile, tile2 = kTile;  // output tile edges of pass 1 and pass 2
     double pieces = 16384;             // target split-K pieces of pass 2
     int variant = -1;                  // grouped-GEMM variant of the tile-64 passes
+    int wide1 = 0, wide2 = 0;          // > 0: 64-row tiles of this many columns (128 or 256)
+    int rows2 = 64;                    // rows of the pass-2 tiles when wide2 > 0 (64 or 128)
+    int order1 = 0;                    // pass-1 task order: 0 channel-major, 1 sector-major
+    int order2 = 0;                    // pass 2: 0 unit by unit, 1 pieces aligned across the units of a sector
 };
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]

@@ -71,16 +71,49 @@ TwoSite make_two_site(const Bond& left, const Bond& right) {
 // ---------------------------------------------------------------------------
 // grouped GEMM task lists
 
-void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
-              const std::vector<UTerm>& terms, int splits, int64_t slice) {
-    if (m <= 0 || n <= 0) return;
-    int64_t ktot = 0;
+void add_unit_flops(GemmList& L, int m, int n, const std::vector<UTerm>& terms) {
     for (const UTerm& u : terms) {
         const double f = 2.0 * m * n * u.k;
         L.flops += f;
         if (u.model) L.model_flops += f;
-        ktot += u.k;
     }
+}
+
+void add_tile(GemmList& L, int c_buf, int64_t c_off, int ldc, int r0, int c0, int tm, int tn, int accumulate,
+              const std::vector<UTerm>& terms, size_t begin, size_t end) {
+    GemmTask tk;
+    tk.c_buf = c_buf;
+    tk.c_off = c_off + int64_t(r0) * ldc + c0;
+    tk.ldc = ldc;
+    tk.m = tm;
+    tk.n = tn;
+    tk.accumulate = accumulate;
+    tk.l_begin = int(L.terms.size());
+    for (size_t i = begin; i < end; ++i) {
+        const UTerm& u = terms[i];
+        GemmTerm g;
+        g.a_buf = u.a_buf;
+        g.a_off = u.ta ? u.a_off + r0 : u.a_off + int64_t(r0) * u.lda;
+        g.b_buf = u.b_buf;
+        g.b_off = u.tb ? u.b_off + int64_t(c0) * u.ldb : u.b_off + c0;
+        g.k = u.k;
+        g.lda = u.lda;
+        g.ldb = u.ldb;
+        g.flags = (u.ta ? GT_TA : 0) | (u.tb ? GT_TB : 0);
+        g.alpha = u.alpha;
+        L.terms.push_back(g);
+    }
+    tk.l_end = int(L.terms.size());
+    tk.inst = 0;
+    L.tasks.push_back(tk);
+}
+
+void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
+              const std::vector<UTerm>& terms, int splits, int64_t slice) {
+    if (m <= 0 || n <= 0) return;
+    add_unit_flops(L, m, n, terms);
+    int64_t ktot = 0;
+    for (const UTerm& u : terms) ktot += u.k;
     if (splits < 1) splits = 1;
     std::vector<size_t> cut(splits + 1, terms.size());
     cut[0] = 0;
@@ -93,37 +126,13 @@ void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int 
         }
         for (; part < splits; ++part) cut[part] = terms.size();
     }
-    const int ts = L.tile;
+    const int ts = L.tile, tsn = L.tile_n > 0 ? L.tile_n : L.tile;
     for (int r0 = 0; r0 < m; r0 += ts)
-        for (int c0 = 0; c0 < n; c0 += ts) {
-            const int tm = std::min(ts, m - r0), tn = std::min(ts, n - c0);
-            for (int sp = 0; sp < splits; ++sp) {
-                GemmTask tk;
-                tk.c_buf = c_buf;
-                tk.c_off = c_off + int64_t(sp) * slice + int64_t(r0) * ldc + c0;
-                tk.ldc = ldc;
-                tk.m = tm;
-                tk.n = tn;
-                tk.accumulate = accumulate;
-                tk.l_begin = int(L.terms.size());
-                for (size_t i = cut[sp]; i < cut[sp + 1]; ++i) {
-                    const UTerm& u = terms[i];
-                    GemmTerm g;
-                    g.a_buf = u.a_buf;
-                    g.a_off = u.ta ? u.a_off + r0 : u.a_off + int64_t(r0) * u.lda;
-                    g.b_buf = u.b_buf;
-                    g.b_off = u.tb ? u.b_off + int64_t(c0) * u.ldb : u.b_off + c0;
-                    g.k = u.k;
-                    g.lda = u.lda;
-                    g.ldb = u.ldb;
-                    g.flags = (u.ta ? GT_TA : 0) | (u.tb ? GT_TB : 0);
-                    g.alpha = u.alpha;
-                    L.terms.push_back(g);
-                }
-                tk.l_end = int(L.terms.size());
-                tk.inst = 0;
-                L.tasks.push_back(tk);
-            }
+        for (int c0 = 0; c0 < n; c0 += tsn) {
+            const int tm = std::min(ts, m - r0), tn = std::min(tsn, n - c0);
+            for (int sp = 0; sp < splits; ++sp)
+                add_tile(L, c_buf, c_off + int64_t(sp) * slice, ldc, r0, c0, tm, tn, accumulate, terms, cut[sp],
+                         cut[sp + 1]);
         }
 }
 
@@ -148,16 +157,18 @@ void GemmList::launch(Prec p, const Bases& b, hipStream_t s) {
 void GemmList::launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const {
     if (sigma_role)
         launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                          dev_bases, active, s, tile, variant);
+                          dev_bases, active, s, tile, variant, tile_n);
     else
         launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                    dev_bases, active, s, tile, variant);
+                    dev_bases, active, s, tile, variant, tile_n);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
     auto bad = [](const char* what) { throw Error(E_STATE, std::string("internal: task list ") + what + " out of bounds"); };
     for (const GemmTask& t : L.tasks) {
-        if (t.c_buf < 0 || t.c_buf >= kMaxBufs || t.m < 1 || t.n < 1 || t.m > L.tile || t.n > L.tile) bad("task shape");
+        if (t.c_buf < 0 || t.c_buf >= kMaxBufs || t.m < 1 || t.n < 1 || t.m > L.tile ||
+            t.n > (L.tile_n > 0 ? L.tile_n : L.tile))
+            bad("task shape");
         if (t.c_off < 0 || t.c_off + int64_t(t.m - 1) * t.ldc + t.n > sizes[t.c_buf]) bad("output");
         if (t.l_begin < 0 || t.l_end < t.l_begin || t.l_end > int(L.terms.size())) bad("term range");
         for (int l = t.l_begin; l < t.l_end; ++l) {
@@ -1312,12 +1323,25 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
         }
     }
     pass1.clear();
-    pass1.tile = cfg.tile1;
+    pass1.tile = cfg.wide1 > 0 ? kTile : cfg.tile1;
+    pass1.tile_n = cfg.wide1;
     pass1.variant = cfg.variant;
     std::vector<UTerm> terms;
-    for (int y = 0; y < nch; ++y) {
+    // pass-1 units (y, q, s'): T_y(q)[rows of segment s'] = sum_s Y(y, s', s) psi_q[rows of s];
+    // order 0 walks the channels outermost, order 1 the sectors (the tasks
+    // of one psi sector then run together and keep it in L2)
+    std::vector<std::pair<int, int>> p1_order;
+    p1_order.reserve(size_t(nch) * nq);
+    if (cfg.order1 == 1) {
+        for (int iq = 0; iq < nq; ++iq)
+            for (int y = 0; y < nch; ++y) p1_order.push_back({y, iq});
+    } else {
+        for (int y = 0; y < nch; ++y)
+            for (int iq = 0; iq < nq; ++iq) p1_order.push_back({y, iq});
+    }
+    for (const auto& [y, iq] : p1_order) {
         const std::vector<int>& dv = dest_of(mpo.chan_dq[j + 1][y]);
-        for (int iq = 0; iq < nq; ++iq) {
+        {
             const int64_t to = t_off[size_t(y) * nq + iq];
             if (to < 0) continue;
             const int iq2 = dv[iq];
@@ -1345,11 +1369,13 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
     }
     // sigma_q' [:, (t', Q'_r)] = sum_y sum_t T_y(q)[:, (t, Q_r)] Z_(y,t',t)^T
     pass2.clear();
-    pass2.tile = cfg.tile2;
+    pass2.tile = cfg.wide2 > 0 ? cfg.rows2 : cfg.tile2;
+    pass2.tile_n = cfg.wide2;
     pass2.variant = cfg.variant;
     std::vector<int> unit_base(nq + 1, 0);
     for (int iq2 = 0; iq2 < nq; ++iq2) unit_base[iq2 + 1] = unit_base[iq2] + int(ts.env[iq2].segs.size());
     std::vector<std::vector<UTerm>> uterms(unit_base[nq]);
+    std::vector<std::vector<int>> uchan(unit_base[nq]);  // channel y of every term
     for (int y = 0; y < nch; ++y) {
         if (!hy[y] || !hz[y]) continue;
         const std::vector<int>& dv = dest_of(mpo.chan_dq[j + 1][y]);
@@ -1374,6 +1400,7 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
                     uterms[unit_base[iq2] + ui].push_back({0, to + sg.off, ts.env[iq].dim, false, 1,
                                                            r.off + blk.off, blk.cols, true, blk.cols,
                                                            1.0, !r.identity});
+                    uchan[unit_base[iq2] + ui].push_back(y);
                 }
             }
         }
@@ -1389,8 +1416,9 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
         for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
             const int u = unit_base[iq2] + int(ui);
             for (const UTerm& t : uterms[u]) ku[u] += t.k;
+            const int tn2 = pass2.tile_n > 0 ? pass2.tile_n : pass2.tile;
             tu[u] = int64_t((ts.sys[iq2].dim + pass2.tile - 1) / pass2.tile) *
-                    ((ts.env[iq2].segs[ui].dim + pass2.tile - 1) / pass2.tile);
+                    ((ts.env[iq2].segs[ui].dim + tn2 - 1) / tn2);
             work += double(tu[u]) * ku[u];
         }
     constexpr int kMaxSplits = 32;
@@ -1401,12 +1429,64 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
         su[u] = int(std::min<double>(kMaxSplits, std::max(1.0, std::ceil(ku[u] / k_target))));
         splits = std::max(splits, su[u]);
     }
-    for (int iq2 = 0; iq2 < nq; ++iq2) {
-        const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
-        for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
-            const Seg& so = ts.env[iq2].segs[ui];
-            const int u = unit_base[iq2] + int(ui);
-            add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[u], su[u], ts.n);
+    if (cfg.order2 != 1) {
+        for (int iq2 = 0; iq2 < nq; ++iq2) {
+            const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
+            for (size_t ui = 0; ui < ts.env[iq2].segs.size(); ++ui) {
+                const Seg& so = ts.env[iq2].segs[ui];
+                const int u = unit_base[iq2] + int(ui);
+                add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[u], su[u], ts.n);
+            }
+        }
+    } else {
+        // The units of one destination sector (its column segments t') read
+        // the same panels T_y(q): cut their K ranges at common channel
+        // boundaries and emit their tiles side by side, piece by piece, so
+        // that the tasks reading one panel run together and share it in L2.
+        const int tm2 = pass2.tile, tn2 = pass2.tile_n > 0 ? pass2.tile_n : pass2.tile;
+        for (int iq2 = 0; iq2 < nq; ++iq2) {
+            const int nrow = ts.sys[iq2].dim, ld2 = ts.env[iq2].dim;
+            const int u0 = unit_base[iq2], u1 = unit_base[iq2 + 1];
+            int S = 1;
+            int64_t ktot = 0;
+            std::map<int, int64_t> ky;  // channel -> K of the sector's terms
+            for (int u = u0; u < u1; ++u) {
+                S = std::max(S, su[u]);
+                add_unit_flops(pass2, nrow, ts.env[iq2].segs[u - u0].dim, uterms[u]);
+                for (size_t i = 0; i < uterms[u].size(); ++i) {
+                    ky[uchan[u][i]] += uterms[u][i].k;
+                    ktot += uterms[u][i].k;
+                }
+            }
+            // channel cuts: piece p holds the channels y with ycut[p] <= y < ycut[p + 1]
+            std::vector<int> ycut(S + 1, nch);
+            ycut[0] = 0;
+            {
+                int64_t cum = 0;
+                int part = 1;
+                for (const auto& [y, k] : ky) {
+                    while (part < S && cum * S >= ktot * part) ycut[part++] = y;
+                    cum += k;
+                }
+            }
+            std::vector<std::vector<size_t>> cut(u1 - u0, std::vector<size_t>(S + 1));
+            for (int u = u0; u < u1; ++u) {
+                const std::vector<int>& yc = uchan[u];
+                for (int p = 0; p <= S; ++p)
+                    cut[u - u0][p] = size_t(std::lower_bound(yc.begin(), yc.end(), ycut[p]) - yc.begin());
+                cut[u - u0][S] = yc.size();
+            }
+            for (int r0 = 0; r0 < nrow; r0 += tm2)
+                for (int p = 0; p < S; ++p)
+                    for (int u = u0; u < u1; ++u) {
+                        const size_t b = cut[u - u0][p], e = cut[u - u0][p + 1];
+                        if (b == e) continue;  // its slice p stays zero
+                        const Seg& so = ts.env[iq2].segs[u - u0];
+                        for (int c0 = 0; c0 < so.dim; c0 += tn2)
+                            add_tile(pass2, 2, ts.off[iq2] + so.off + int64_t(p) * ts.n, ld2, r0, c0,
+                                     std::min(tm2, nrow - r0), std::min(tn2, so.dim - c0), 0, uterms[u], b, e);
+                    }
+            splits = std::max(splits, S);
         }
     }
     {
@@ -2185,15 +2265,20 @@ std::string tune_dump() {
     bool first = true;
     for (auto& [k, c] : tune_table()) {
         char buf[256];
-        std::snprintf(buf, sizeof buf, "%s\"%s\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.17g, \"variant\": %d}",
-                      first ? "" : ", ", k.c_str(), c.tile1, c.tile2, c.pieces, c.variant);
+        std::snprintf(buf, sizeof buf,
+                      "%s\"%s\": {\"tile1\": %d, \"tile2\": %d, \"pieces\": %.17g, \"variant\": %d, "
+                      "\"wide1\": %d, \"wide2\": %d, \"rows2\": %d, \"order1\": %d, \"order2\": %d}",
+                      first ? "" : ", ", k.c_str(), c.tile1, c.tile2, c.pieces, c.variant, c.wide1, c.wide2,
+                      c.rows2, c.order1, c.order2);
         out += buf;
         first = false;
     }
     return out + "}";
 }
 
-// Reads the format tune_dump writes: {"key": {"tile1": a, "tile2": b, "pieces": p, "variant": v}, ...}
+// Reads the format tune_dump writes: {"key": {"tile1": a, "tile2": b, "pieces": p, "variant": v,
+// "wide1": w1, "wide2": w2, "rows2": r2, "order1": o1, "order2": o2}, ...} (the fields after
+// "variant" may be absent)
 void tune_load(const std::string& js) {
     size_t pos = 0;
     auto expect = [&](char ch) {
@@ -2237,13 +2322,22 @@ void tune_load(const std::string& js) {
                 else if (f == "tile2") c.tile2 = int(v);
                 else if (f == "pieces") c.pieces = v;
                 else if (f == "variant") c.variant = int(v);
+                else if (f == "wide1") c.wide1 = int(v);
+                else if (f == "wide2") c.wide2 = int(v);
+                else if (f == "rows2") c.rows2 = int(v);
+                else if (f == "order1") c.order1 = int(v);
+                else if (f == "order2") c.order2 = int(v);
                 else require(false, "tuning table: unknown field " + f);
                 if (peek() == ',') { ++pos; continue; }
                 expect('}');
                 break;
             }
             require((c.tile1 == 32 || c.tile1 == 64 || c.tile1 == 128) && (c.tile2 == 32 || c.tile2 == 64 || c.tile2 == 128) && c.pieces >= 256 &&
-                        c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 3,
+                        c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 3 &&
+                        (c.wide1 == 0 || c.wide1 == 128 || c.wide1 == 256) &&
+                        (c.wide2 == 0 || (c.rows2 == 64 && (c.wide2 == 128 || c.wide2 == 256)) ||
+                         (c.rows2 == 128 && (c.wide2 == 64 || c.wide2 == 128))) &&
+                        (c.order1 == 0 || c.order1 == 1) && (c.order2 == 0 || c.order2 == 1),
                     "tuning table: configuration out of range");
             add[key] = c;
             if (peek() == ',') { ++pos; continue; }

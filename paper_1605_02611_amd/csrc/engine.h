@@ -143,6 +143,7 @@ struct GemmList {
     }
     bool sigma_role = false;  // launch under the sigma-vector kernel symbol
     int tile = kTile;         // output tile edge of the tasks (64 or 32)
+    int tile_n = 0;           // > 0: tiles of `tile` rows and tile_n columns
     int variant = -1;         // grouped-GEMM variant (-1: process default)
     DevBuf dbases;            // device copy of the buffer table
     Bases hbases{};           // host copy (kept alive for the async upload)
@@ -304,6 +305,29 @@ class State {
             if (std::sscanf(e, "%d,%d", &a, &b) == 2 && ok(a) && ok(b)) {
                 cfg.tile1 = a;
                 cfg.tile2 = b;
+                cfg_explicit = true;
+            }
+        }
+        if (const char* e = std::getenv("DMRG_SIGMA_WIDE")) {
+            // "w1,w2[,r2]": column count of the wide tiles of each pass (0
+            // square) and the row count of the pass-2 tiles (64 or 128)
+            int a = 0, b = 0, r = 64;
+            const int n = std::sscanf(e, "%d,%d,%d", &a, &b, &r);
+            const bool ok1 = a == 0 || a == 128 || a == 256;
+            const bool ok2 = b == 0 || (r == 64 && (b == 128 || b == 256)) || (r == 128 && (b == 64 || b == 128));
+            if (n >= 2 && ok1 && ok2) {
+                cfg.wide1 = a;
+                cfg.wide2 = b;
+                cfg.rows2 = r;
+                cfg_explicit = true;
+            }
+        }
+        if (const char* e = std::getenv("DMRG_SIGMA_ORDER")) {
+            // "o1,o2": task order of each pass (0 or 1)
+            int a = 0, b = 0;
+            if (std::sscanf(e, "%d,%d", &a, &b) == 2 && (a == 0 || a == 1) && (b == 0 || b == 1)) {
+                cfg.order1 = a;
+                cfg.order2 = b;
                 cfg_explicit = true;
             }
         }

@@ -464,6 +464,184 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
             }
 }
 
+// Wide tiles: TM rows x TN columns per workgroup of four waves.  The
+// 16-column sub-tiles of the output are dealt to the waves round robin
+// (sub-tile c to wave c % 4), so every wave keeps all TM rows of its columns
+// in accumulators: a narrow task still spreads over the waves, and a wide
+// one gives each wave TM/16 x TN/64 MFMA tiles per 4-deep K group against
+// TM/16 + TN/64 LDS operand reads.  The blocks of the sigma vector are far wider than tall
+// (first pass: one operator block, a few tens of rows, against every
+// column of a two-site sector; second pass: all rows of a sector against one
+// right-state segment), so a 64 x 64 tile re-read its row panel once per 64
+// columns and paid its per-task latency on very little MFMA work.  Operands
+// are staged through LDS in K-steps of KS with the next step's loads in
+// flight during the current step's MFMAs (as VAR 2 of grouped_gemm).
+template <int MODE, int ROLE, int TM, int TN>
+__global__ __launch_bounds__(256, TM * TN <= 64 * 128 ? 4 : 2) void wide_gemm(const GemmTask* __restrict__ tasks,
+                                                                    const GemmTerm* __restrict__ terms,
+                                                                    void* const* __restrict__ bases,
+                                                                    const int* __restrict__ active, int xcd,
+                                                                    int64_t n_tasks) {
+    using T = typename Cfg<MODE>::T;
+    using Acc = typename Cfg<MODE>::Acc;
+    constexpr int NT = 256, NS = TN / 64, MS = TM / 16;  // sub-tile columns per wave, sub-tile rows
+    constexpr int PA = TM * KS / NT, PB = TN * KS / NT;
+    __shared__ T As[KS][lds_pitch<MODE>(TM)];
+    __shared__ T Bs[KS][lds_pitch<MODE>(TN)];
+
+    const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
+                       : xcd == 1 ? xcd_task(blockIdx.x, gridDim.x)
+                                  : xcd_chunk_task(blockIdx.x, xcd);
+    if (ti >= n_tasks) return;  // padding of the chunked grid (before any barrier)
+    const GemmTask task = tasks[ti];
+    if (active && !active[task.inst]) return;  // uniform per workgroup
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int lr = lane & 15;  // row / column inside a 16x16 MFMA tile
+    const int lk = lane >> 4;  // k-group of the lane
+
+    Acc acc[MS][NS];
+    bool act[MS][NS];  // sub-tile overlaps the task's m x n (uniform per wave)
+#pragma unroll
+    for (int i = 0; i < MS; ++i)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            acc[i][j] = Acc{0, 0, 0, 0};
+            act[i][j] = (16 * i < task.m) && (16 * (wave + 4 * j) < task.n);
+        }
+    bool any_col[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) any_col[j] = 16 * (wave + 4 * j) < task.n;
+
+    auto mfma_step = [&](int kv) {
+        if constexpr (MODE == 0 || MODE == 1) {
+            for (int ks = 0; ks < kv; ks += 4) {
+                T a[MS], b[NS];
+#pragma unroll
+                for (int i = 0; i < MS; ++i) a[i] = As[ks + lk][16 * i + lr];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) b[j] = any_col[j] ? Bs[ks + lk][16 * (wave + 4 * j) + lr] : T(0);
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+#pragma unroll
+                    for (int j = 0; j < NS; ++j)
+                        if (act[i][j]) {
+                            if constexpr (MODE == 0)
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                            else
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                        }
+            }
+        } else {
+            // one 16x16x16 BF16 MFMA per tile and 16 K: lane holds k = 4 lk .. 4 lk + 3
+            for (int k16 = 0; k16 < kv; k16 += 16) {
+                shrt4 a[MS], b[NS];
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        a[i][e] = short(f32_to_bf16_rne(As[k16 + 4 * lk + e][16 * i + lr]));
+#pragma unroll
+                for (int j = 0; j < NS; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        b[j][e] = any_col[j] ? short(f32_to_bf16_rne(Bs[k16 + 4 * lk + e][16 * (wave + 4 * j) + lr]))
+                                             : short(0);
+#pragma unroll
+                for (int i = 0; i < MS; ++i)
+#pragma unroll
+                    for (int j = 0; j < NS; ++j)
+                        if (act[i][j])
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    };
+
+    T ra[PA], rb[PB];
+    // operands of K-step (t, kb0) into registers; zero outside the slice
+    auto load = [&](const GemmTerm& t, int kb0) {
+        const T* A = static_cast<const T*>(bases[t.a_buf]) + t.a_off;
+        const T* B = static_cast<const T*>(bases[t.b_buf]) + t.b_off;
+        const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+        const T alpha = T(t.alpha);
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int idx = tid + i * NT;
+            const int r = ta ? idx % TM : idx / KS, kk = ta ? idx / TM : idx % KS;
+            T v = T(0);
+            if (r < task.m && kb0 + kk < t.k)
+                v = ta ? A[int64_t(kb0 + kk) * t.lda + r] : A[int64_t(r) * t.lda + kb0 + kk];
+            ra[i] = v * alpha;
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int idx = tid + i * NT;
+            const int c = tb ? idx / KS : idx % TN, kb = tb ? idx % KS : idx / TN;
+            T u = T(0);
+            if (c < task.n && kb0 + kb < t.k)
+                u = tb ? B[int64_t(c) * t.ldb + kb0 + kb] : B[int64_t(kb0 + kb) * t.ldb + c];
+            rb[i] = u;
+        }
+    };
+    auto store = [&](const GemmTerm& t) {
+        const bool ta = t.flags & GT_TA, tb = t.flags & GT_TB;
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int idx = tid + i * NT;
+            As[ta ? idx / TM : idx % KS][ta ? idx % TM : idx / KS] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int idx = tid + i * NT;
+            Bs[tb ? idx % KS : idx / TN][tb ? idx / KS : idx % TN] = rb[i];
+        }
+    };
+    int l = task.l_begin, k0 = 0;
+    GemmTerm g{}, gn{};
+    if (l < task.l_end) {
+        g = terms[l];
+        if (l + 1 < task.l_end) gn = terms[l + 1];
+        load(g, 0);
+    }
+    while (l < task.l_end) {
+        store(g);
+        __syncthreads();
+        const int kv = min(KS, g.k - k0);
+        int nl = l, nk = k0 + KS;
+        if (nk >= g.k) {
+            nl = l + 1;
+            nk = 0;
+            if (nl < task.l_end) {
+                g = gn;
+                if (nl + 1 < task.l_end) gn = terms[nl + 1];
+            }
+        }
+        if (nl < task.l_end) load(g, nk);  // in flight during the MFMAs
+        mfma_step(kv);
+        __syncthreads();
+        l = nl;
+        k0 = nk;
+    }
+    // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds row
+    // 4 lk + e for the FP32 MFMAs and row 4 e + lk for the FP64 MFMA.
+    T* C = static_cast<T*>(bases[task.c_buf]) + task.c_off;
+#pragma unroll
+    for (int i = 0; i < MS; ++i)
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
+                const int c = 16 * (wave + 4 * j) + lr;
+                if (r < task.m && c < task.n) {
+                    T* p = C + int64_t(r) * task.ldc + c;
+                    T v = T(acc[i][j][e]);
+                    *p = task.accumulate ? *p + v : v;
+                }
+            }
+}
+
 // Descriptors are the same for the whole workgroup: keep them in scalar
 // registers (the compiler cannot prove it across the persistent loop).
 __device__ inline int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -1183,10 +1361,49 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     }
 }
 
+template <int ROLE, int TM, int TN>
+static void launch_wide(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
+                        const int* act, hipStream_t s, int xcd) {
+    const int64_t kMaxGrid = 1 << 30;
+    for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
+        const int64_t nt = std::min<int64_t>(kMaxGrid, n_tasks - off);
+        const int64_t step = xcd > 1 ? 8 * int64_t(xcd) : 1;
+        const unsigned g = unsigned((nt + step - 1) / step * step);
+        switch (p) {
+            case Prec::F64:
+                hipLaunchKernelGGL((wide_gemm<0, ROLE, TM, TN>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::F32:
+                hipLaunchKernelGGL((wide_gemm<1, ROLE, TM, TN>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::BF16:
+                hipLaunchKernelGGL((wide_gemm<2, ROLE, TM, TN>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+        }
+    }
+}
+
 template <int ROLE>
 static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                             void* const* b, const int* act, int tile, hipStream_t s, int variant) {
+                             void* const* b, const int* act, int tile, hipStream_t s, int variant, int tile_n) {
     if (n_tasks <= 0) return;
+    if (tile_n > 0) {
+        // tiles of `tile` rows and tile_n columns
+        static const int xcd_w = gemm_env("DMRG_GEMM_XCD", 4);
+        if (tile == 64 && tile_n == 128)
+            launch_wide<ROLE, 64, 128>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        else if (tile == 64 && tile_n == 256)
+            launch_wide<ROLE, 64, 256>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        else if (tile == 128 && tile_n == 64)
+            launch_wide<ROLE, 128, 64>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        else if (tile == 128 && tile_n == 128)
+            launch_wide<ROLE, 128, 128>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        else
+            require(false, "grouped GEMM: wide tiles are 64 x 128, 64 x 256, 128 x 64 or 128 x 128");
+        DMRG_HIP(hipGetLastError());
+        return;
+    }
+
     require(tile == 128 || tile == 64 || tile == 32, "grouped GEMM: tile must be 128, 64 or 32");
     static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 4);
     const int var = variant >= 0 ? variant : var_env;
@@ -1256,12 +1473,12 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 }
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* b, const int* act, hipStream_t s, int tile, int variant) {
-    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s, variant);
+                 void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n);
 }
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* b, const int* act, hipStream_t s, int tile, int variant) {
-    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s, variant);
+                       void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {

@@ -120,6 +120,59 @@ def env_blocks_to_dense(values, sectors_list, shifts):
     return dense
 
 
+def env_values_to_blocks(values, sectors_list, shifts):
+    """Channel-major block values -> per channel {(Q_out, Q_in): block view}
+    (no copies: large environments stay one array)."""
+    secs = [(n, s) for n, s, _ in sectors_list]
+    out, pos = [], 0
+    for blocks in env_block_shapes(sectors_list, shifts):
+        d = {}
+        for o, i, r, c in blocks:
+            d[(secs[o], secs[i])] = values[pos:pos + r * c].reshape(r, c)
+            pos += r * c
+        out.append(d)
+    assert pos == len(values)
+    return out
+
+
+def merged_blocks(vec, left, right):
+    """Two-site vector in the merged sector layout -> {(Q_l, s, t, Q_r): block
+    view}; left, right: {(N, 2Sz): dim} of bonds j and j+2 (the layout of
+    include/dmrg.h: sectors sorted, rows (Q_l, s) by Q_l, columns (t, Q_r) by t)."""
+    def add(a, b, sg=1):
+        return (a[0] + sg * b[0], a[1] + sg * b[1])
+    cand = sorted({add(Q, SITE_QN[s]) for Q in left for s in range(4)})
+    out, pos = {}, 0
+    for q in cand:
+        rows = [(s, add(q, SITE_QN[s], -1)) for s in SYS_ORDER if add(q, SITE_QN[s], -1) in left]
+        cols = [(t, add(q, SITE_QN[t])) for t in range(4) if add(q, SITE_QN[t]) in right]
+        if not rows or not cols:
+            continue
+        nr = sum(left[Q] for _, Q in rows)
+        nc = sum(right[Q] for _, Q in cols)
+        mat = vec[pos:pos + nr * nc].reshape(nr, nc)
+        r0 = 0
+        for s, Ql in rows:
+            c0 = 0
+            for t, Qr in cols:
+                out[(Ql, s, t, Qr)] = mat[r0:r0 + left[Ql], c0:c0 + right[Qr]]
+                c0 += right[Qr]
+            r0 += left[Ql]
+        pos += nr * nc
+    assert pos == len(vec)
+    return out
+
+
+def site_value_count(bonds):
+    """Values of the fine-block site tensors of bonds [{(N, 2Sz): dim}]."""
+    n = 0
+    for j in range(len(bonds) - 1):
+        for Q, m in bonds[j].items():
+            for s in range(4):
+                n += m * bonds[j + 1].get((Q[0] + SITE_QN[s][0], Q[1] + SITE_QN[s][1]), 0)
+    return n
+
+
 # --- MPS checkpoint files (the layout documented with dmrg_mps_save) ------------------
 
 MPS_MAGIC = b"DMRGMPS\x01"

@@ -137,16 +137,25 @@ def test_gpu_calls_on_host_context_fail_cleanly(hctx):
 
 def test_tuning_table_round_trip_and_validation():
     base = P.tune_table()
+    defaults = {"wide1": 0, "wide2": 0, "rows2": 64, "order1": 0, "order2": 0}
     entry = {"K99_M1024_d3": {"tile1": 64, "tile2": 32, "pieces": 4096.0, "variant": 2}}
     P.tune_table_load(entry)
     t = P.tune_table()
-    assert t["K99_M1024_d3"] == entry["K99_M1024_d3"]
+    assert t["K99_M1024_d3"] == dict(entry["K99_M1024_d3"], **defaults)  # absent fields: defaults
+    wide = {"K98_M1024_d3": {"tile1": 64, "tile2": 64, "pieces": 16384.0, "variant": 2, "wide1": 128,
+                             "wide2": 64, "rows2": 128, "order1": 1, "order2": 1}}
+    P.tune_table_load(wide)
+    t = P.tune_table()
+    assert t["K98_M1024_d3"] == wide["K98_M1024_d3"]
     for k in base:
         assert t[k] == base[k]
     # malformed or out-of-range tables are rejected and change nothing
     for bad in ({"x": {"tile1": 48, "tile2": 64, "pieces": 4096, "variant": 0}},
                 {"x": {"tile1": 64, "tile2": 64, "pieces": 10, "variant": 0}},
                 {"x": {"tile1": 64, "tile2": 64, "pieces": 4096, "variant": 7}},
+                {"x": {"tile1": 64, "tile2": 64, "pieces": 4096, "variant": 2, "wide1": 96}},
+                {"x": {"tile1": 64, "tile2": 64, "pieces": 4096, "variant": 2, "wide2": 64, "rows2": 64}},
+                {"x": {"tile1": 64, "tile2": 64, "pieces": 4096, "variant": 2, "order2": 2}},
                 {"x": {"tile1": 64, "colour": 1}}):
         with pytest.raises(P.DmrgError):
             P.tune_table_load(bad)

@@ -1,0 +1,105 @@
+"""Element-wise parity of the sigma vector at the benchmark shapes.
+
+The middle pair of the K=24 N=24 M=512 and K=36 N=36 M=1024 chain
+workloads, on bonds with the block structure of a converging state
+(workloads.bonds.peaked_bond_dims: at K=36 the first-pass intermediate
+holds 2.18e9 elements, past 2^31, and the blocks span several 64-wide tiles
+and split-K pieces), random environment operators in every allowed block
+(dmrg_env_import) and a random two-site vector.  The library's sigma (FP64,
+the launch configuration the benchmark uses) is compared, fine block by fine
+block, with the block-sparse oracle (oracle.blocksparse, Eq. Hpartition) on
+sampled output sectors: the one with the most work, a mid-sized one and the
+smallest.  The tolerance is 1e-12 of the sector's largest element: random
+operators make every element a sum of ~1e5 products of O(1) numbers, whose
+FP64 rounding in two summation orders differs by ~1e-14 relative.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1605_02611_amd as P  # noqa: E402
+from oracle import blocksparse as ob, mpo as omp  # noqa: E402
+from oracle.fermions import spin_orbital_integrals  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from workloads import WORKLOADS, mps_values, workload_integrals  # noqa: E402
+from workloads.bonds import as_triples, peaked_bond_dims  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _sector_work(left, right, q):
+    def add(a, b, sg=1):
+        return (a[0] + sg * b[0], a[1] + sg * b[1])
+    rows = sum(left.get(add(q, H.SITE_QN[s], -1), 0) for s in range(4))
+    cols = sum(right.get(add(q, H.SITE_QN[t]), 0) for t in range(4))
+    return rows * cols
+
+
+@pytest.mark.parametrize("workload", ["chain_k24_m512", "chain_k36_m1024"])
+def test_full_size_sigma_matches_block_sparse_oracle(ctx, workload):
+    c = WORKLOADS[workload]
+    K, M = c["K"], c["M"]
+    I = workload_integrals(workload)
+    N, tsz = I.n_elec, I.two_sz
+    j = K // 2 - 1
+    t0 = time.time()
+    bonds = peaked_bond_dims(K, N, tsz, M)
+    mpo = P.Mpo(ctx, I.h, I.v, N, tsz)
+    # random site tensors scaled so that the environments the import builds
+    # stay of order one (they are replaced at the center anyway)
+    vals = mps_values(c["seed"], H.site_value_count(bonds)) / np.sqrt(4.0 * M)
+    mps = P.Mps.from_tensors(ctx, mpo, [as_triples(b) for b in bonds], vals, j)
+    _log("%s: state imported at pair %d in %.1fs, psi %d" % (workload, j, time.time() - t0, mps.psi_size()))
+    rng = np.random.default_rng(c["seed"] + 7)
+    left, right = bonds[j], bonds[j + 2]
+    Lv = rng.standard_normal(mps.env_size(0, j))
+    Rv = rng.standard_normal(mps.env_size(1, j + 2))
+    mps.env_import(0, j, Lv)
+    mps.env_import(1, j + 2, Rv)
+    psi = rng.standard_normal(mps.psi_size())
+    x = torch.tensor(psi, device="cuda")
+    y = torch.zeros_like(x)
+    mps.sigma(x, y)  # builds the blocked operators and task lists
+    y.zero_()
+    mps.sigma(x, y)
+    sig = y.cpu().numpy()
+    del x, y
+    _log("%s: GPU sigma done %.1fs" % (workload, time.time() - t0))
+    # the oracle on sampled output sectors
+    t, vs = spin_orbital_integrals(I.h, I.v)
+    w = vs - vs.transpose(0, 1, 3, 2)
+    Wj, Wj1 = omp._build_site(K, j, t, w, vs), omp._build_site(K, j + 1, t, w, vs)
+    ch = [omp.channels(K, k) for k in (j, j + 1, j + 2)]
+    L = H.env_values_to_blocks(Lv, as_triples(left), [omp.channel_qn(x) for x in ch[0]])
+    R = H.env_values_to_blocks(Rv, as_triples(right), [omp.channel_qn(x) for x in ch[2]])
+    mids = ob.middle_sectors(left, right)
+    by_work = sorted(mids, key=lambda q: _sector_work(left, right, q))
+    sample = [by_work[-1], by_work[len(by_work) // 2], by_work[0]]
+    got_blocks = H.merged_blocks(sig, left, right)
+    want = ob.sigma_sectors(Wj, Wj1, ch[0], ch[1], ch[2], left, right, L, R, H.merged_blocks(psi, left, right),
+                            sample)
+    _log("%s: oracle on sectors %s done %.1fs" % (workload, sample, time.time() - t0))
+    n_checked = 0
+    for q in sample:
+        keys = [k for k in want if (k[0][0] + H.SITE_QN[k[1]][0], k[0][1] + H.SITE_QN[k[1]][1]) == q]
+        scale = max(np.abs(want[k]).max() for k in keys)
+        for k in keys:
+            err = np.abs(got_blocks[k] - want[k]).max()
+            assert err <= 1e-12 * scale, (workload, q, k, err, scale)
+            n_checked += want[k].size
+    assert n_checked > 1000

@@ -46,7 +46,7 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (16, 16, 4), (17, 33, 19), (64, 64, 16), (65, 63
           (70, 130, 50), (130, 65, 200), (3, 300, 2)]
 
 
-@pytest.mark.parametrize("tile", [64, 32])
+@pytest.mark.parametrize("tile", [64, 32, 128, 256])
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
@@ -79,12 +79,29 @@ def _oracle_case(K, N, tsz, M, seed, kind="random"):
     return I, od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n))
 
 
+@pytest.fixture
+def sigma_tiles(request, monkeypatch):
+    """Launch configuration of the sigma passes for the states a test makes:
+    "" the default, else "w1,w2[,r2]|o1,o2": wide tiles of w1 / w2 columns
+    (0 square) with r2 rows in pass 2, and the task orders of the passes."""
+    for var in ("DMRG_SIGMA_WIDE", "DMRG_SIGMA_ORDER"):
+        monkeypatch.delenv(var, raising=False)
+    if request.param:
+        wide, _, order = request.param.partition("|")
+        monkeypatch.setenv("DMRG_SIGMA_WIDE", wide)
+        if order:
+            monkeypatch.setenv("DMRG_SIGMA_ORDER", order)
+    return request.param
+
+
+@pytest.mark.parametrize("sigma_tiles", ["", "0,0|0,0", "0,0|1,1", "128,128", "256,256|1,0",
+                                         "128,64,128|1,1", "128,128,128|0,1", "0,256|1,1"], indirect=True)
 @pytest.mark.parametrize("K,N,tsz,M,centers,kind", [
     (5, 5, 1, 6, (0, 2), "random"),
     (6, 6, 0, 12, (0, 1, 3), "chain"),
     (7, 8, 2, 20, (0, 2, 5), "random"),
 ])
-def test_environments_sigma_diag_match_oracle(ctx, K, N, tsz, M, centers, kind):
+def test_environments_sigma_diag_match_oracle(ctx, K, N, tsz, M, centers, kind, sigma_tiles):
     I, d = _oracle_case(K, N, tsz, M, 100 + K, kind)
     mpo = P.Mpo(ctx, I.h, I.v, N, tsz)
     done = 0
