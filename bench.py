@@ -4,8 +4,10 @@
 Workload (default): the K=36, N=36, M=1024 chain molecule (integral seed
 1003).  Setup, untimed: build the MPO, draw the random initial MPS, run
 --presweeps full sweeps (default 2) so that the state has the sector
-structure of a production sweep, move the center to the middle pair
-(17, 18) by exact SVD splits, run the warm-up steps.  A timed step is one complete two-site DMRG step at the middle bond:
+structure of a production sweep.  Then one more full sweep is timed (sweep
+seconds), the center moves to the middle pair (17, 18) by exact SVD splits,
+the middle-pair eigenproblem is solved from one start vector in FP64, FP32
+and BF16 (mixed vs FP64), and the warm-up steps run.  A timed step is one complete two-site DMRG step at the middle bond:
 blocking of the renormalized operators, Davidson with the sigma vector,
 sector-wise SVD truncation to M, environment update and the next guess.
 Steps alternate between the pairs (17, 18) forward and (18, 19) backward, so
@@ -13,6 +15,8 @@ every step works at the middle of the chain.
 
 The metric value is the sigma-vector rate: model flops of all sigma calls in
 the timed steps divided by their GPU time (HIP events on the library stream).
+The same JSON line carries the measured sweep seconds, the mixed-precision
+comparison, the roofline of the sigma kernel and the CPU oracle baseline.
 """
 
 import argparse
@@ -29,13 +33,22 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA, TFLOP/s
 
 
-def recorded_traffic(prec, steps, warmup, presweeps):
-    """HBM bytes per sigma launch from the committed rocprofv3 counter summary,
-    only while the kernel source is the one the counters were taken on and the
-    run is the recorded one; otherwise None."""
+def source_hash():
+    """sha256 over the sources that decide the sigma launches (kernels and the
+    task-list builder)."""
     import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "engine.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1605_02611_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic(prec, presweeps):
+    """HBM bytes per sigma launch from the committed rocprofv3 counter summary,
+    only while the sources are the ones the counters were taken on and the
+    state is the recorded one (the traffic of a launch depends on the state's
+    blocks, not on how many steps are timed); otherwise None."""
     try:
-        src = open(os.path.join(ROOT, "paper_1605_02611_amd", "csrc", "kernels.hip"), "rb").read()
         txt = open(os.path.join(ROOT, "profiles", "hbm_traffic_sigma_k36_m1024_fp64.txt")).read()
     except OSError:
         return None
@@ -43,8 +56,7 @@ def recorded_traffic(prec, steps, warmup, presweeps):
     for line in txt.splitlines():
         if line.startswith("machine-readable:"):
             rec = json.loads(line.split(":", 1)[1])
-    if (rec is None or rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest()
-            or prec != "fp64" or rec.get("steps") != steps or rec.get("warmup") != warmup
+    if (rec is None or rec.get("sources_sha256") != source_hash() or prec != "fp64"
             or rec.get("presweeps", 0) != presweeps):
         return None
     return rec["traffic_bytes_per_launch"]
@@ -54,66 +66,76 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, ctx, m_sample, seed):
-    """Oracle sigma at the same Hamiltonian and middle pair, bond dimension
-    m_sample; rate = library model flops of that shape / oracle time."""
-    import numpy as np
+def cpu_baseline(mps, j, budget_s):
+    """The oracle's block-sparse sigma (oracle.blocksparse, FP64, NumPy) on a
+    bounded sample of the benchmarked sigma: the middle pair of the K=36
+    M=1024 workload with the sector structure of the benchmarked state,
+    random environment operators and two-site vector, whole output sectors
+    taken from the largest down until budget_s of oracle time is spent;
+    rate = model flops of those sectors (oracle.flops) / oracle time."""
     from threadpoolctl import threadpool_info
 
-    from oracle import dmrg as od
+    from oracle import blocksparse as ob
+    from oracle import flops as of
     from oracle import mpo as omp
     from oracle.fermions import spin_orbital_integrals
-    from workloads import WORKLOADS, workload_integrals, mps_values
+    from tests import helpers as H
+    from workloads import workload_integrals
 
-    c = WORKLOADS["chain_k36_m1024"]
-    K = c["K"]
-    j = K // 2 - 1
     I = workload_integrals("chain_k36_m1024")
-    # model flops of this shape from the library
-    mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
-    n = mpo.n_values(m_sample)
-    mps = P.Mps.random(ctx, mpo, m_sample, mps_values(seed, n))
-    for _ in range(j):
-        mps.move(True)
-    import torch
-    x = torch.randn(mps.psi_size(), device="cuda", dtype=torch.float64)
-    y = torch.zeros_like(x)
-    flops = mps.sigma(x, y)
-    bl, br = mps.bond(j), mps.bond(j + 2)
-    del mps
-    # the oracle on the same shape
+    K = I.h.shape[0]
+    left = {(a, b): d for a, b, d in mps.bond(j)}
+    right = {(a, b): d for a, b, d in mps.bond(j + 2)}
     t0 = time.time()
     ts, vs = spin_orbital_integrals(I.h, I.v)
     w = vs - vs.transpose(0, 1, 3, 2)
-    D = omp.bond_dims(K)
-    W1 = omp.dense_site(omp._build_site(K, j, ts, w, vs), D[j], D[j + 1])
-    W2 = omp.dense_site(omp._build_site(K, j + 1, ts, w, vs), D[j + 1], D[j + 2])
-    t_build = time.time() - t0
-    lab_l = od.labels_from_dims({(a, b): d for a, b, d in bl})
-    lab_r = od.labels_from_dims({(a, b): d for a, b, d in br})
+    Wj, Wj1 = omp._build_site(K, j, ts, w, vs), omp._build_site(K, j + 1, ts, w, vs)
+    ch = [omp.channels(K, k) for k in (j, j + 1, j + 2)]
     rng = np.random.default_rng(0)
-    o = object.__new__(od.DMRG)
-    o.Lenv = {j: rng.standard_normal((D[j], len(lab_l), len(lab_l)))}
-    o.Renv = {j + 2: rng.standard_normal((D[j + 2], len(lab_r), len(lab_r)))}
-    o.Wd = {j: W1, j + 1: W2}
-    o.labels = {j: lab_l, j + 2: lab_r}
-    psi = rng.standard_normal((len(lab_l), 4, 4, len(lab_r))) * o.mask(j)
-    reps, t1 = 0, time.time()
-    while reps < 1 or time.time() - t1 < 8.0:
-        o.sigma(j, psi)
-        reps += 1
-    dt = time.time() - t1
+    trip = lambda d: [(q[0], q[1], m) for q, m in sorted(d.items())]
+    shl = [omp.channel_qn(c) for c in ch[0]]
+    shr = [omp.channel_qn(c) for c in ch[2]]
+    nl = sum(r * c for bl in H.env_block_shapes(trip(left), shl) for _, _, r, c in bl)
+    nr = sum(r * c for bl in H.env_block_shapes(trip(right), shr) for _, _, r, c in bl)
+    L = H.env_values_to_blocks(rng.standard_normal(nl), trip(left), shl)
+    R = H.env_values_to_blocks(rng.standard_normal(nr), trip(right), shr)
+    mids = ob.middle_sectors(left, right)
+
+    def rows_cols(q):
+        r = sum(left.get((q[0] - a, q[1] - b), 0) for a, b in H.SITE_QN)
+        c = sum(right.get((q[0] + a, q[1] + b), 0) for a, b in H.SITE_QN)
+        return r * c
+    psi = H.merged_blocks(rng.standard_normal(sum(rows_cols(q) for q in mids)), left, right)
+    t_setup = time.time() - t0
+
+    per = of.sigma_model_flops_by_sector(Wj, Wj1, ch[0], ch[1], ch[2], left, right)
+    work = {q: float(sum(per.get(q, (0, 0)))) for q in mids}
+    whole = sum(work.values())
+    # sectors from the two-thirds quantile of work upwards, each taken only if the
+    # rate measured so far says it fits the budget
+    order = sorted(mids, key=lambda q: work[q])
+    order = order[(2 * len(order)) // 3:]
+    done, flops, dt = [], 0.0, 0.0
+    for q in order:
+        if done and dt + work[q] / (flops / max(dt, 1e-9)) > budget_s:
+            break
+        t1 = time.time()
+        ob.sigma_sectors(Wj, Wj1, ch[0], ch[1], ch[2], left, right, L, R, psi, [q])
+        dt += time.time() - t1
+        done.append(q)
+        flops += work[q]
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
     return {
-        "value": flops * reps / dt / 1e12,
+        "value": flops / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": ("oracle sigma (dense FP64 tensordot over MPO channels) at the middle pair of the "
-                   "K=36 workload with bond dimension %d instead of 1024 (%d psi elements), %d call(s) "
-                   "in %.1f s; rate = library model flops of the same shape / oracle time; MPO tensors "
-                   "of the two sites built in %.1f s (not timed)" % (m_sample, int(o.mask(j).sum()), reps,
-                                                                      dt, t_build)),
+        "sample": ("oracle block-sparse sigma (FP64 NumPy, Eq. Hpartition per quantum-number block) at the "
+                   "middle pair of the K=36 M=1024 workload with the benchmarked state's sectors, random "
+                   "environments and vector: output sectors %s, %.3g of the %.3g model flops of one sigma, "
+                   "in %.1f s; setup (MPO sites, random operators) %.1f s, not timed" % (
+                       [list(q) for q in done], flops, whole, dt, t_setup)),
+        "oracle_sigma_seconds_projected": dt * whole / flops,
     }
 
 
@@ -196,28 +218,37 @@ def batched(args, P, torch):
     print(json.dumps(out), flush=True)
 
 
-def precision_check(args, P, mps, pre_e):
-    """The same two-site eigenproblem (middle pair, state after the
-    presweeps) solved from the same start vector in every precision."""
+def precision_runs(P, mps, tol=1e-8, max_iter=60):
+    """The same two-site eigenproblem (the current center) solved from the
+    same start vector in every precision; the vector is restored after."""
     psi0 = mps.psi()
     rows = {}
     for name, prec, refine in (("fp64", P.DMRG_FP64, 0.0), ("fp32_refined", P.DMRG_FP32, 1e-4),
                                ("bf16_refined", P.DMRG_BF16, 1e-4), ("fp32_only", P.DMRG_FP32, 0.0),
                                ("bf16_only", P.DMRG_BF16, 0.0)):
         mps.set_psi(psi0)
-        o = P.default_opts(prec=prec, dav_tol=1e-8, dav_max_iter=60, refine_tol=refine)
+        o = P.default_opts(prec=prec, dav_tol=tol, dav_max_iter=max_iter, refine_tol=refine)
         t0 = time.time()
         th, rn, st = mps.solve(o)
-        rows[name] = {"theta": th, "rnorm": rn, "iters": st["dav_iters"], "sigma_calls": st["sigma_calls"],
-                      "sigma_seconds": st["sigma_seconds"], "seconds": time.time() - t0,
+        rows[name] = {"theta": th, "rnorm": rn, "converged": st["unconverged"] == 0, "iters": st["dav_iters"],
+                      "sigma_calls": st["sigma_calls"], "sigma_seconds": st["sigma_seconds"],
+                      "seconds": time.time() - t0,
                       "sigma_tflops": st["sigma_flops"] / max(st["sigma_seconds"], 1e-30) / 1e12}
         log("%-13s theta %.12f |r| %.2e iters %d sigma %.3fs" % (name, th, rn, st["dav_iters"], st["sigma_seconds"]))
+    mps.set_psi(psi0)
     ref = rows["fp64"]["theta"]
     for r in rows.values():
         r["abs_dtheta_vs_fp64"] = abs(r["theta"] - ref)
         r["speedup_vs_fp64"] = rows["fp64"]["seconds"] / r["seconds"]
+    return rows
+
+
+def precision_check(args, P, mps, pre_e):
+    """The same two-site eigenproblem (middle pair, state after the
+    presweeps) solved from the same start vector in every precision."""
+    rows = precision_runs(P, mps)
     print(json.dumps({"mode": "precision_check", "workload": "K=36 M=1024 middle pair after %d FP64 sweeps"
-                      % args.presweeps, "presweep_energy": pre_e, "psi_elements": int(psi0.size),
+                      % args.presweeps, "presweep_energy": pre_e, "psi_elements": mps.psi_size(),
                       "davidson_tol": 1e-8, "davidson_max_iter": 60, "runs": rows}), flush=True)
 
 
@@ -292,7 +323,10 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--dav-tol", type=float, default=1e-7)
     ap.add_argument("--dav-iter", type=int, default=24)
-    ap.add_argument("--sweep", action="store_true", help="also time one full sweep")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the timed full sweep (sweep seconds) after the presweeps")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the middle-pair FP64 / FP32 / BF16 eigenproblem comparison")
     ap.add_argument("--sweeps", type=int, default=0,
                     help="instead of middle steps: run this many full sweeps from the random "
                          "initial state and report energies and sweep seconds")
@@ -313,7 +347,8 @@ def main():
     ap.add_argument("--compress", type=float, default=0.0,
                     help="MPO compression threshold (Hartree); 0 = exact MPO")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-m", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="oracle time budget of the CPU baseline sample")
     ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--learned-mode", default="both", choices=["both", "diagonal", "learned"],
                     help="with --learned: run both preconditioners or only one (separate processes)")
@@ -365,12 +400,41 @@ def main():
             st, _ = mps.sweep(M, 1, opts)
             pre_e = st[-1]["energy"]
             log("presweep %d: E %.10f (%.1fs)" % (i, pre_e, time.time() - t0))
+    sweep = None
+    if not args.sweeps and not args.no_sweep and not args.precision_check:
+        # sweep seconds: one full sweep (forward and back over every pair:
+        # blocking, Davidson, SVD truncation, environment update), timed
+        torch.cuda.synchronize()
+        t2 = time.time()
+        st, _ = mps.sweep(M, 1, opts)
+        torch.cuda.synchronize()
+        st = st[0]
+        sweep = {"seconds": time.time() - t2, "energy": st["energy"], "sigma_seconds": st["sigma_seconds"],
+                 "sigma_tflops": st["sigma_flops"] / max(st["sigma_seconds"], 1e-30) / 1e12,
+                 "davidson_iterations": st["dav_iters"], "steps": st["n_steps"],
+                 "unconverged_steps": st["unconverged"], "max_residual": st["max_residual"],
+                 "discarded_weight": st["discarded"], "sweep_index": args.presweeps + 1}
+        log("timed sweep: %.1fs E %.10f (%d of %d steps at the iteration cap)" % (
+            sweep["seconds"], st["energy"], st["unconverged"], st["n_steps"]))
     for _ in range(0 if args.sweeps else j):
         mps.move(True)
     log("setup %.1fs: center %d, psi %d, D_mid %d" % (time.time() - t0, mps.center(), mps.psi_size(),
                                                       mpo.bond_dims()[j + 1]))
     if args.precision_check:
         return precision_check(args, P, mps, pre_e)
+    mixed = None
+    if not args.sweeps and not args.no_precision and args.prec == "fp64":
+        # mixed vs FP64: the middle-pair eigenproblem in every precision from
+        # the same start vector, each to the same residual tolerance
+        t3 = time.time()
+        rows = precision_runs(P, mps)
+        mixed = {"workload": "middle pair (17, 18) after %d sweeps, same start vector" % (
+                     args.presweeps + (sweep is not None)),
+                 "davidson_tol": 1e-8, "davidson_max_iter": 60, "tolerance_eh": 1e-5,
+                 "runs": rows,
+                 "fp32_refined_within_1e-5": rows["fp32_refined"]["abs_dtheta_vs_fp64"] <= 1e-5,
+                 "bf16_refined_within_1e-5": rows["bf16_refined"]["abs_dtheta_vs_fp64"] <= 1e-5,
+                 "seconds": time.time() - t3}
     tuned = None
     if args.autotune:
         t3 = time.time()
@@ -388,7 +452,7 @@ def main():
         log("warmup %d theta %.10f" % (w, th))
         fwd = not fwd
     torch.cuda.synchronize()
-    tot = dict(flops=0.0, sig=0.0, gemm=0.0, launches=0, calls=0, iters=0)
+    tot = dict(flops=0.0, sig=0.0, gemm=0.0, launches=0, calls=0, iters=0, unconverged=0)
     thetas = []
     t1 = time.time()
     for s in range(args.steps):
@@ -401,6 +465,7 @@ def main():
         tot["launches"] += st["gemm_launches"]
         tot["calls"] += st["sigma_calls"]
         tot["iters"] += st["dav_iters"]
+        tot["unconverged"] += st["unconverged"]
         log("step %d %s theta %.10f %.2fs sigma %d calls %.3fs" % (s, "fwd" if not fwd else "bwd", th,
                                                                   st["seconds"], st["sigma_calls"],
                                                                   st["sigma_seconds"]))
@@ -422,7 +487,9 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "chain molecule K=36 N=36 2Sz=0 M=1024 (integral seed 1003), "
-                               "two-site steps at the middle bond after %d untimed sweeps" % args.presweeps,
+                               "two-site steps at the middle bond after %d sweeps from the random state%s" % (
+                                   args.presweeps + (sweep is not None),
+                                   " (the last one timed for sweep_seconds)" if sweep else ""),
                    "K": K, "M": M, "D_mid": int(mpo.bond_dims()[j + 1]), "psi_elements": mps.psi_size(),
                    "presweeps": args.presweeps, "presweep_energy": pre_e, "autotuned": tuned,
                    "davidson_tol": args.dav_tol, "davidson_max_iter": args.dav_iter,
@@ -434,28 +501,18 @@ def main():
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK[args.prec],
                      "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec],
                      "traffic": (None if args.compress else
-                                 recorded_traffic(args.prec, args.steps, args.warmup, args.presweeps)),
+                                 recorded_traffic(args.prec, args.presweeps + (sweep is not None))),
                      "kernel": "grouped_gemm<%d,1>" % prec,
                      "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
                      "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},
-        "sweep_seconds": None,
+        "sweep_seconds": sweep["seconds"] if sweep else None,
+        "sweep": sweep,
+        "mixed_vs_fp64": mixed,
+        "unconverged_steps": tot["unconverged"],
     }
-    if args.sweep:
-        # one full sweep from the middle: move to the left end, then sweep
-        while mps.center() > 0:
-            mps.move(False)
-        t2 = time.time()
-        stats, _ = mps.sweep(M, 1, opts)
-        out["sweep_seconds"] = time.time() - t2
-        out["sweep_energy"] = stats[0]["energy"]
-    else:
-        # projection: middle-step time x number of steps x mean(D)/D_mid
-        D = mpo.bond_dims()
-        frac = float(sum(D[1:K])) / (K - 1) / D[j + 1]
-        out["sweep_seconds_projected"] = wall / args.steps * 2 * (K - 1) * frac
     if not args.no_cpu:
         try:
-            out["cpu_baseline"] = cpu_baseline(P, ctx, args.cpu_m, c["seed"])
+            out["cpu_baseline"] = cpu_baseline(mps, j, args.cpu_seconds)
         except Exception as e:  # report, do not hide
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)

@@ -73,67 +73,55 @@ def sigma_sectors(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, L, R, psi,
     mids = set(middle_sectors(left, right))
     sys_terms = _site_terms(Wj, 0)
     env_terms = _site_terms(Wj1, 1)
-    dq_j = [channel_qn(c) for c in chans_j]
-    dq_j2 = [channel_qn(c) for c in chans_j2]
+    dq_mid = [channel_qn(c) for c in chans_mid]
     out = {}
     for q2 in out_sectors:
         assert q2 in mids, q2
+        Ql2_of = [_add(q2, SITE_QN[s], -1) for s in range(4)]  # Q'_l of each s'
+        Qr2_of = [_add(q2, SITE_QN[t]) for t in range(4)]      # Q'_r of each t'
         for sp in range(4):
-            Ql2 = _add(q2, SITE_QN[sp], -1)
-            if Ql2 not in left:
+            if Ql2_of[sp] not in left:
                 continue
             for tp in range(4):
-                Qr2 = _add(q2, SITE_QN[tp])
-                if Qr2 in right:
-                    out[(Ql2, sp, tp, Qr2)] = np.zeros((left[Ql2], right[Qr2]))
-        for y, ch in enumerate(chans_mid):
+                if Qr2_of[tp] in right:
+                    out[(Ql2_of[sp], sp, tp, Qr2_of[tp])] = np.zeros((left[Ql2_of[sp]], right[Qr2_of[tp]]))
+        for y in range(len(chans_mid)):
             st, et = sys_terms.get(y), env_terms.get(y)
             if not st or not et:
                 continue
-            dq_y = channel_qn(ch)
-            q = _add(q2, dq_y, -1)  # the psi sector this channel maps onto q2
+            q = _add(q2, dq_mid[y], -1)  # the psi sector this channel maps onto q2
             if q not in mids:
                 continue
-            # blocked system operator (s' <- s) restricted to q -> q2
+            Ql_of = [_add(q, SITE_QN[s], -1) for s in range(4)]
+            Qr_of = [_add(q, SITE_QN[t]) for t in range(4)]
+            # blocked system operator (s' <- s) restricted to q -> q2; the
+            # block (Q'_l <- Q_l) of L[x] exists only where Q'_l = Q_l + dq_x
             osys = {}
             for x, sp, s, w in st:
-                Ql2, Ql = _add(q2, SITE_QN[sp], -1), _add(q, SITE_QN[s], -1)
-                if Ql2 not in left or Ql not in left:
-                    continue
-                blk = L[x].get((Ql2, Ql))
+                blk = L[x].get((Ql2_of[sp], Ql_of[s]))
                 if blk is None:
                     continue
-                assert _add(Ql, dq_j[x]) == Ql2
                 osys[(sp, s)] = osys[(sp, s)] + w * blk if (sp, s) in osys else w * blk
             oenv = {}
             for z, tp, t, w in et:
-                Qr2, Qr = _add(q2, SITE_QN[tp]), _add(q, SITE_QN[t])
-                if Qr2 not in right or Qr not in right:
-                    continue
-                blk = R[z].get((Qr2, Qr))
+                blk = R[z].get((Qr2_of[tp], Qr_of[t]))
                 if blk is None:
                     continue
-                assert _add(Qr, dq_j2[z]) == Qr2
                 oenv[(tp, t)] = oenv[(tp, t)] + w * blk if (tp, t) in oenv else w * blk
             if not osys or not oenv:
                 continue
             # T_y = O^sys_y psi_q: blocks (s', (t, Q_r))
             T = {}
             for (sp, s), ob in osys.items():
-                Ql = _add(q, SITE_QN[s], -1)
                 for t in range(4):
-                    Qr = _add(q, SITE_QN[t])
-                    pb = psi.get((Ql, s, t, Qr))
+                    pb = psi.get((Ql_of[s], s, t, Qr_of[t]))
                     if pb is None:
                         continue
                     v = ob @ pb
                     T[(sp, t)] = T[(sp, t)] + v if (sp, t) in T else v
             # sigma_q2 += T_y (O^env_y)^T
             for (sp, t), tb in T.items():
-                Ql2 = _add(q2, SITE_QN[sp], -1)
                 for (tp, t2), eb in oenv.items():
-                    if t2 != t:
-                        continue
-                    Qr2 = _add(q2, SITE_QN[tp])
-                    out[(Ql2, sp, tp, Qr2)] += tb @ eb.T
+                    if t2 == t:
+                        out[(Ql2_of[sp], sp, tp, Qr2_of[tp])] += tb @ eb.T
     return out

@@ -29,7 +29,9 @@ factor of the channels 1 (x) H^R (system side of channel I) and H^L (x) 1
 (environment side of channel H) costs nothing: it is not a product.
 
 Two functions compute the count independently:
-  sigma_model_flops        the block formula above, in integers;
+  sigma_model_flops        the block formula above, in integers (and
+                           sigma_model_flops_by_sector, the same per output
+                           sector);
   sigma_model_flops_dense  brute force for tiny states: the number of
                            nonzero multiply-adds of the dense two-product
                            evaluation with quantum-number masks on every
@@ -64,14 +66,13 @@ def _patterns(W, side, chans_outer):
     return pat
 
 
-def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_sectors=None):
-    """Model flops (system side, environment side) of one sigma at the pair
-    (j, j+1).  Wj, Wj1: sparse site tensors {(x, y): 4x4} of the oracle MPO;
-    chans_*: channel labels of bonds j, j+1, j+2; left, right: {(N, 2Sz):
-    dim} of bonds j and j+2.  out_sectors (optional): count only the work
-    whose result lands in these middle sectors of sigma (both sides: the
-    system-side product of channel y feeds sector q + dq_y).  Integers
-    only."""
+def sigma_model_flops_by_sector(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right):
+    """Model flops of one sigma at the pair (j, j+1), per middle sector q'
+    of sigma that the work lands in: {q': [system side, environment side]}
+    (the system-side product of channel y on psi sector q feeds q + dq_y).
+    Wj, Wj1: sparse site tensors {(x, y): 4x4} of the oracle MPO; chans_*:
+    channel labels of bonds j, j+1, j+2; left, right: {(N, 2Sz): dim} of
+    bonds j and j+2.  Integers only."""
     def cols(q):  # C(q): columns (t, Q_r) of middle sector q
         return sum(right.get(_shift(q, SITE_QN[t]), 0) for t in range(4))
 
@@ -87,13 +88,12 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_se
     def nonzero(pat, bond_dims):  # the factor has at least one fine block
         return any(_shift(Q, dq) in bond_dims for (_, _, dq) in pat for Q in bond_dims)
 
-    f_sys = f_env = 0
+    out = {}
     for y, ch in enumerate(chans_mid):
         ps, pe = sys_pat.get(y, set()), env_pat.get(y, set())
         if not (nonzero(ps, left) and nonzero(pe, right)):
             continue
         dq_y = channel_qn(ch)
-        keep = (lambda q2: True) if out_sectors is None else (lambda q2: q2 in out_sectors)
         if ch[0] != "I":
             for sp, s, dqx in ps:
                 for Ql, ml in left.items():
@@ -101,8 +101,9 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_se
                     if Qo not in left:
                         continue
                     q = _shift(Ql, SITE_QN[s])
-                    if middle(q) and middle(_shift(q, dq_y)) and keep(_shift(q, dq_y)):
-                        f_sys += 2 * left[Qo] * ml * cols(q)
+                    q2 = _shift(q, dq_y)
+                    if middle(q) and middle(q2):
+                        out.setdefault(q2, [0, 0])[0] += 2 * left[Qo] * ml * cols(q)
         if ch[0] != "H":
             for tp, t, dqz in pe:
                 for Qr, mr in right.items():
@@ -111,9 +112,18 @@ def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_se
                         continue
                     q = _shift(Qr, SITE_QN[t], -1)
                     q2 = _shift(q, dq_y)
-                    if middle(q) and middle(q2) and keep(q2):
-                        f_env += 2 * right[Qo] * mr * rows(q2)
-    return f_sys, f_env
+                    if middle(q) and middle(q2):
+                        out.setdefault(q2, [0, 0])[1] += 2 * right[Qo] * mr * rows(q2)
+    return out
+
+
+def sigma_model_flops(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right, out_sectors=None):
+    """Model flops (system side, environment side) of one sigma at the pair
+    (j, j+1): the sums of sigma_model_flops_by_sector, over out_sectors only
+    when given.  Integers only."""
+    per = sigma_model_flops_by_sector(Wj, Wj1, chans_j, chans_mid, chans_j2, left, right)
+    keep = [q for q in per if out_sectors is None or q in out_sectors]
+    return sum(per[q][0] for q in keep), sum(per[q][1] for q in keep)
 
 
 def _labels(dims):
