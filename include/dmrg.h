@@ -258,6 +258,21 @@ dmrg_status dmrg_psi_export(dmrg_ctx* ctx, const dmrg_mps* mps, double* psi_host
  * not NULL. */
 dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
                        double* out, dmrg_prec prec, double* flops);
+/* The FP64 sigma of dmrg_sigma without any allocation, for callers that
+ * cannot allocate device memory at call time: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid it.  The first-pass
+ * intermediate, the split-K slices and the launch tables live in a scratch
+ * array of 256 MiB that the library holds on every GPU it runs on (set up
+ * by dmrg_ctx_create); the call makes no hipMalloc, hipFree or other
+ * allocating call and does not wait for the GPU: the work is ordered on the
+ * context's stream.  psi and out are DEVICE pointers of dmrg_psi_size FP64
+ * values (not overlapping).  The center must have been prepared by one
+ * dmrg_sigma or dmrg_sigma_diag call on it (else DMRG_E_STATE); a state
+ * whose intermediate and slices exceed the 256 MiB returns DMRG_E_INVAL
+ * with the size it needs.  All calls on one GPU share the array: two calls
+ * that overlap on one GPU (other streams or threads) race. */
+dmrg_status dmrg_sigma_noalloc(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
+                               double* out);
 /* Diagonal of H_eff at the current center (DEVICE pointer, FP64). */
 dmrg_status dmrg_sigma_diag(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, double* out);
 /* Dense copy of environment operators (test hook): side 0 = left block of

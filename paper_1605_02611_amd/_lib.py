@@ -76,6 +76,7 @@ SIGNATURES = {
     "dmrg_psi_size": (c_int, [c_void_p, P(c_int64)]),
     "dmrg_psi_export": (c_int, [c_void_p, c_void_p, P(c_double)]),
     "dmrg_sigma": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, P(c_double)]),
+    "dmrg_sigma_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_sigma_diag": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "dmrg_env_export": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double)]),
     "dmrg_env_size": (c_int, [c_void_p, c_int, c_int, P(c_int64)]),

@@ -311,6 +311,15 @@ class Mps:
                                            C.c_void_p(y_dev.data_ptr()), prec, C.byref(f)))
         return f.value
 
+    def sigma_noalloc(self, x_dev, y_dev):
+        """y = H_eff x (FP64) with no allocation (dmrg_sigma_noalloc); the
+        center must have been prepared by sigma() or diag() once."""
+        n = self.psi_size()
+        assert x_dev.numel() == n and y_dev.numel() == n
+        _torch_sync()
+        self.ctx.check(self.lib.dmrg_sigma_noalloc(self.ctx.h, self.h, self.mpo.h, C.c_void_p(x_dev.data_ptr()),
+                                                   C.c_void_p(y_dev.data_ptr())))
+
     def diag(self, y_dev):
         assert y_dev.numel() == self.psi_size()
         _torch_sync()

@@ -164,6 +164,7 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, const dmrg_allocator* 
         DMRG_HIP(hipEventCreate(&ctx->c.ev2));
         DMRG_HIP(hipEventCreate(&ctx->c.ev3));
         DMRG_HIP(hipDeviceGetAttribute(&ctx->c.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        scratch_init(device);  // address of this device's scratch array (dmrg_sigma_noalloc)
         if (rocblas_create_handle(&ctx->c.blas) != rocblas_status_success)
             throw Error(E_HIP, "rocblas_create_handle failed");
         if (rocblas_set_stream(ctx->c.blas, ctx->c.stream) != rocblas_status_success)
@@ -659,6 +660,19 @@ dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const 
         StepStats st;
         mps->st->sigma(psi, out, Prec(prec), &st);
         if (flops) *flops += st.sigma_flops;
+    });
+}
+
+dmrg_status dmrg_sigma_noalloc(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const double* psi,
+                               double* out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mps && mpo && psi && out, "null argument");
+        require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
+        const int64_t n = mps->st->ts.n;
+        require(psi + n <= out || out + n <= psi, "psi and out overlap");
+        use_device(ctx->c);
+        mps->st->sigma_noalloc(psi, out, scratch_ptr(ctx->c.device), kScratchElems);
     });
 }
 

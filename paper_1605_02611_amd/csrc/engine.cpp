@@ -1622,6 +1622,44 @@ void State::sigma(const double* x, double* y, Prec p, StepStats* st) {
     }
 }
 
+void State::sigma_noalloc(const double* x, double* y, double* scr, int64_t cap) {
+    require(prepared, "the center is not prepared: call dmrg_sigma or dmrg_sigma_diag on it once first",
+            E_STATE);
+    require(scr != nullptr, "scratch memory is not set up on this device", E_STATE);
+    hipStream_t s = ctx->stream;
+    // scratch layout (doubles): [0, 16) the two launch tables, T from 64,
+    // the split-K slices after T (each start 256-byte aligned)
+    constexpr int64_t kTables = 64;
+    auto up32 = [](int64_t n) { return (n + 31) / 32 * 32; };
+    const int64_t t_at = kTables, part_at = t_at + up32(std::max<int64_t>(1, t_total));
+    const int64_t need = part_at + (splits > 1 ? int64_t(splits) * ts.n : 0);
+    if (need > cap) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "state too large for the scratch memory: needs %lld bytes, the maximum is %lld bytes",
+                      (long long)(need * 8), (long long)(cap * 8));
+        throw Error(E_INVAL, buf);
+    }
+    double* T = scr + t_at;
+    double* part_s = scr + part_at;
+    nb1 = Bases{};
+    nb1.p[0] = Y.buf.p;
+    nb1.p[1] = const_cast<double*>(x);
+    nb1.p[2] = T;
+    nb2 = Bases{};
+    nb2.p[0] = T;
+    nb2.p[1] = Z.buf.p;
+    nb2.p[2] = splits > 1 ? static_cast<void*>(part_s) : static_cast<void*>(y);
+    DMRG_HIP(hipMemcpyAsync(scr, &nb1, sizeof(Bases), hipMemcpyHostToDevice, s));
+    DMRG_HIP(hipMemcpyAsync(scr + 8, &nb2, sizeof(Bases), hipMemcpyHostToDevice, s));
+    // slices that no task of a unit writes must read as zero: the scratch
+    // keeps whatever the previous call left (a fill kernel, not a memset)
+    if (splits > 1) launch_fill(part_s, 0.0, int64_t(splits) * ts.n, s);
+    pass1.launch_dev(Prec::F64, reinterpret_cast<void* const*>(scr), nullptr, s);
+    pass2.launch_dev(Prec::F64, reinterpret_cast<void* const*>(scr + 8), nullptr, s);
+    if (splits > 1) launch_sum_slices(y, part_s, splits, ts.n, 0, s);
+}
+
 // Static features of the learned preconditioner for every element of the
 // two-site vector: labels of its left sector and of the two site states.
 void State::build_mlp_static() {

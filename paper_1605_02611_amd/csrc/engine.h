@@ -182,6 +182,14 @@ struct UTerm {
 void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
               const std::vector<UTerm>& terms, int splits = 1, int64_t slice = 0);
 
+// Scratch array of the entry point that allocates nothing (noalloc.hip):
+// 256 MiB of FP64 per device.  scratch_init fetches the address of the
+// current device's copy once (hipGetSymbolAddress); scratch_ptr returns it
+// (nullptr before set-up).
+constexpr int64_t kScratchElems = int64_t(32) << 20;
+void scratch_init(int device);
+double* scratch_ptr(int device);
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -386,6 +394,11 @@ class State {
     void prepare();                      // blocking + task lists at the center
     void ensure_f32();                   // FP32 copies of the blocked operators
     void sigma(const double* x, double* y, Prec p, StepStats* st);
+    // The same FP64 sigma on a prepared center with the first-pass
+    // intermediate, the split-K slices and the launch tables in the caller's
+    // scratch (cap doubles); no allocation, no host synchronisation.
+    void sigma_noalloc(const double* x, double* y, double* scratch, int64_t cap);
+    Bases nb1{}, nb2{};  // launch tables of sigma_noalloc (copied to the scratch)
     void build_diag();
     double step(int M, bool forward, const SweepOpts& o, StepStats& st, bool solve = true);
     // Davidson at the current center only: psi becomes the lowest eigenvector
