@@ -144,6 +144,33 @@ typedef struct {
 dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
                            int n_elec, int two_sz, const dmrg_mpo_opts* opts,
                            dmrg_mpo** out);
+/* Sum-of-sub-Hamiltonians MPO (Sec. 4.2, Eqs. subH, hmrenorm; Appendix,
+ * recursion bases d4 and r5): H = sum_m H_m over spin orbitals
+ * m = 2*site + sigma (sigma 0 up, 1 down), with spin-orbital integrals
+ * t_PQ = h_pq d(sP,sQ), v_PQRS = (ps|qr) d(sP,sS) d(sQ,sR) and
+ *   grouping 0:  H_m = sum_Q t_mQ a+_m a_Q + sum_{Q>m} sum_RS v_mQRS a+_m a+_Q a_R a_S
+ *                (Eq. subH; each pair a+_P a+_Q counted once, under its
+ *                smaller index, which is 1/2 sum_PQ of H since v_QPSR = v_PQRS)
+ *   grouping 1:  H_m = the terms t_PQ a+_P a_Q and v_PQRS a+_P a+_Q a_R a_S
+ *                (P < Q) of H whose largest spin-orbital index is m (the
+ *                rightmost-operator split).
+ * The MPOs of the H_m are stacked in one channel space: interior bonds hold
+ * every sub-Hamiltonian's channels, bond 0 and bond K one shared channel,
+ * and W never couples channels of different m, so every call that takes a
+ * dmrg_mpo (states, sweeps, sigma, energy) works on sum_m H_m with one
+ * environment block per sub-Hamiltonian.  Channel labels (dmrg_mpo_channels):
+ * p = m (-1 for the shared channels of bonds 0 and K); kind 0 (identity
+ * left operator) and 1 (identity right operator) as for dmrg_build_mpo, else
+ * kind 13 with q = (class << 26) | (length << 24) | (op0 << 12) | op1:
+ * class 0 start / 1 normal (left string fixed), 2 complementary / 3 done
+ * (right string fixed), op = 2*P + (1 for a+_P, 0 for a_P) of the fixed
+ * string's operators in site order.  Channels of one bond are sorted by
+ * (m, class, string); the sub-Hamiltonian bond dimensions D(m, k) are the
+ * counts of labels with p = m.  Channels whose operator vanishes are not
+ * created.  Errors as for dmrg_build_mpo, and DMRG_E_INVAL for a grouping
+ * other than 0 or 1.  Host-only: works on a host-only context. */
+dmrg_status dmrg_build_sum_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
+                               int n_elec, int two_sz, int grouping, dmrg_mpo** out);
 /* MPO bond dimensions D[0..K] (caller-owned array of K+1). */
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D);
 /* Channel labels of bond k: 3*D[k] ints (kind, p, q), kinds

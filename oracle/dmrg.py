@@ -241,10 +241,12 @@ class DMRG:
     """Dense-tensor two-site DMRG on the oracle's MPO."""
 
     def __init__(self, h, v, n_elec, two_sz, M, values, dav_tol=1e-9,
-                 dav_max_iter=200, dav_max_space=24, dav_keep=4, compress_tol=0.0):
+                 dav_max_iter=200, dav_max_space=24, dav_keep=4, compress_tol=0.0, mpo=None):
+        """mpo: (Ws, chans) of another MPO of the same H (e.g. the stacked
+        sub-Hamiltonians of oracle.submpo); None builds oracle.mpo's."""
         self.K = K = h.shape[0]
         self.N, self.tsz, self.M = n_elec, two_sz, M
-        self.Ws, self.chans = mpo_mod.build_mpo(h, v)
+        self.Ws, self.chans = mpo if mpo is not None else mpo_mod.build_mpo(h, v)
         if compress_tol > 0.0:
             self.Ws, self.chans, _ = mpo_mod.compress_mpo(self.Ws, self.chans, h, v, compress_tol)
         self.Wd = [mpo_mod.dense_site(self.Ws[j], len(self.chans[j]), len(self.chans[j + 1]))

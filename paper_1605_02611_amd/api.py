@@ -152,6 +152,36 @@ class Mpo:
         self.h = out
         self.n_elec, self.two_sz = n_elec, two_sz
 
+    @classmethod
+    def sum_of_subhamiltonians(cls, ctx, h, v, n_elec, two_sz=None, grouping=0):
+        """H = sum_m H_m, the sub-Hamiltonian MPOs stacked in one channel
+        space (dmrg_build_sum_mpo); grouping 0: H_m = a+_m T_m (Eq. subH),
+        1: the terms whose rightmost operator is m."""
+        self = cls.__new__(cls)
+        self.ctx, self.lib = ctx, ctx.lib
+        h = np.asarray(h, dtype=np.float64)
+        self.K = K = h.shape[0]
+        if two_sz is None:
+            two_sz = n_elec % 2
+        hh, hp = _dptr(h)
+        vv, vp = _dptr(v)
+        out = C.c_void_p()
+        ctx.check(self.lib.dmrg_build_sum_mpo(ctx.h, hp, vp, K, n_elec, two_sz, int(grouping),
+                                              C.byref(out)))
+        self.h = out
+        self.n_elec, self.two_sz = n_elec, two_sz
+        return self
+
+    def sub_bond_dims(self):
+        """Sub-Hamiltonian bond dimensions D[m, k] of a sum MPO (channels of
+        bond k labelled with p = m)."""
+        D = np.zeros((2 * self.K, self.K + 1), dtype=np.int64)
+        for k in range(self.K + 1):
+            for p in self.channels(k)[:, 1]:
+                if p >= 0:
+                    D[p, k] += 1
+        return D
+
     def bond_dims(self):
         D = np.zeros(self.K + 1, dtype=np.int32)
         self.ctx.check(self.lib.dmrg_mpo_bond_dims(self.h, D.ctypes.data_as(C.POINTER(C.c_int32))))

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmrg.so")
-SOURCES = ["kernels.hip", "mlp.hip", "noalloc.hip", "mpo.cpp", "engine.cpp", "batch.cpp", "mlp.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "noalloc.hip", "mpo.cpp", "subham.cpp", "engine.cpp", "batch.cpp", "mlp.cpp", "capi.cpp"]
 ARCH = os.environ.get("DMRG_OFFLOAD_ARCH", "gfx950")
 
 

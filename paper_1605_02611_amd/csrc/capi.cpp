@@ -235,6 +235,18 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
     });
 }
 
+dmrg_status dmrg_build_sum_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K, int n_elec,
+                               int two_sz, int grouping, dmrg_mpo** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(h && v && out, "null argument");
+        auto m = build_sum_mpo(h, v, K, n_elec, two_sz, grouping);
+        auto* r = new dmrg_mpo();
+        r->m = std::move(m);
+        *out = r;
+    });
+}
+
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D) {
     if (!mpo || !D) return DMRG_E_INVAL;
     for (size_t k = 0; k < mpo->m->chans.size(); ++k) D[k] = int32_t(mpo->m->chans[k].size());

@@ -108,9 +108,11 @@ struct Mat4 {
 
 // ---------------------------------------------------------------------------
 // MPO: channels per bond and sparse site tensors
-enum ChanKind { CK_I = 0, CK_H, CK_Cd, CK_C, CK_SL, CK_SLd, CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q, CK_X };
+enum ChanKind { CK_I = 0, CK_H, CK_Cd, CK_C, CK_SL, CK_SLd, CK_A, CK_Ad, CK_B, CK_P, CK_Pd, CK_Q, CK_X, CK_S };
 // CK_X: a compressed 2-index channel (p = its family's kind, q = its index
 // among the compressed channels of that family at the bond)
+// CK_S: a channel of a sub-Hamiltonian MPO (p = the sub-Hamiltonian, q its
+// encoded key; see subham.cpp); its shift is stored in MPO::chan_dq
 struct Chan {
     int kind, p, q;
 };
@@ -150,6 +152,15 @@ struct MPO {
 // compress_tol > 0: SVD compression of the 2-index channel blocks (mpo.cpp)
 std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
                                int switch_bond, double compress_tol = 0.0);
+// Sum of sub-Hamiltonian MPOs stacked in one channel space (subham.cpp);
+// grouping 0: H_m collects the terms whose first creation operator is m
+// (Eq. subH), 1: the terms whose rightmost operator sits on spin orbital m
+std::unique_ptr<MPO> build_sum_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
+                                   int grouping);
+// argument checks shared by the builders (symmetry of h and v, N, 2S_z)
+void check_integrals(const double* h, const double* v, int K, int n_elec, int two_sz);
+// fine entries and blocking groups of W[j] (after W[j] is complete)
+void index_site(MPO& mpo, int j);
 
 // ---------------------------------------------------------------------------
 // kernels (kernels.hip)

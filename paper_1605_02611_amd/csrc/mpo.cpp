@@ -416,8 +416,6 @@ bool chan_odd(const Chan& c) {
     return c.kind == CK_Cd || c.kind == CK_C || c.kind == CK_SL || c.kind == CK_SLd;
 }
 
-namespace {
-
 // fine entries of W[j] and their groupings for the two blocking directions
 void index_site(MPO& mpo, int j) {
     auto* m = &mpo;
@@ -455,6 +453,8 @@ void index_site(MPO& mpo, int j) {
         }
     }
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Hamiltonian compression (Sec. "Hamiltonian compression", Eqs.
@@ -862,10 +862,8 @@ void compress(MPO& m, const double* h, const double* v, double tol) {
 
 }  // namespace
 
-std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
-                               int switch_bond, double compress_tol) {
+void check_integrals(const double* h, const double* v, int K, int n_elec, int two_sz) {
     require(K >= 1 && K <= 1000, "K must be in [1, 1000]");
-    require(std::isfinite(compress_tol) && compress_tol >= 0.0, "compress_tol must be finite and >= 0");
     require(n_elec >= 0 && n_elec <= 2 * K, "N must be in [0, 2K]");
     require(((n_elec - two_sz) % 2 + 2) % 2 == 0, "parity of 2Sz must equal parity of N");
     require(std::abs(two_sz) <= std::min(n_elec, 2 * K - n_elec), "|2Sz| too large for N, K");
@@ -889,6 +887,12 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
                                 std::fabs(x - V(k, l, i, j)) <= tv,
                             "v lacks the 8-fold symmetry of (ij|kl)");
                 }
+}
+
+std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
+                               int switch_bond, double compress_tol) {
+    require(std::isfinite(compress_tol) && compress_tol >= 0.0, "compress_tol must be finite and >= 0");
+    check_integrals(h, v, K, n_elec, two_sz);
 
     auto m = std::make_unique<MPO>();
     m->K = K;

@@ -14,6 +14,7 @@ sys.path.insert(0, ROOT)
 
 from oracle import dmrg as od  # noqa: E402
 from oracle import fermions as fm  # noqa: E402
+from oracle import submpo as sm  # noqa: E402
 from workloads import WORKLOADS, chain_integrals, mps_values, workload_integrals  # noqa: E402
 
 CASES = {
@@ -29,6 +30,12 @@ CASES = {
     # threshold 0.037 lies in a gap of the singular values (0.0306, 0.0439)
     # and keeps 202 of 248 directions
     "chain8_compressed": dict(kind="chain", K=8, N=8, seed=77, M=16, sweeps=3, compress_tol=0.037),
+    # chain8, chain7_odd and random_k8 on the stacked sub-Hamiltonian MPOs
+    # (Sec. 4.2): grouping 0 = Eq. subH (first index), 1 = rightmost operator
+    "chain8_subham0": dict(kind="chain", K=8, N=8, seed=77, M=16, sweeps=3, subham=0),
+    "chain8_subham1": dict(kind="chain", K=8, N=8, seed=77, M=16, sweeps=3, subham=1),
+    "chain7_odd_subham1": dict(kind="chain", K=7, N=7, seed=78, M=16, sweeps=3, subham=1),
+    "random_k8_subham0": dict(kind="workload", name="random_k8", M=64, sweeps=6, subham=0),
 }
 
 
@@ -43,7 +50,9 @@ def run(name, c):
     n = od.n_mps_values(K, N, tsz, M)
     t0 = time.time()
     tol = c.get("compress_tol", 0.0)
-    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n), compress_tol=tol)
+    sub = c.get("subham")
+    mpo = sm.build_sum_mpo(I.h, I.v, sub) if sub is not None else None
+    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(seed, n), compress_tol=tol, mpo=mpo)
     sweeps = []
     for _ in range(c["sweeps"]):
         d.sweep()
@@ -53,6 +62,7 @@ def run(name, c):
                sweep_energies=sweeps, last_sweep_thetas=thetas, energy=d.energy(),
                bonds=[[list(q) + [dd] for q, dd in d.bond_sectors(k)] for k in range(K + 1)],
                compress_tol=tol, mpo_bond_dims=[len(ch) for ch in d.chans],
+               subham=sub,
                seconds=time.time() - t0)
     if K <= 10:
         out["fci"] = fm.fci_energy(I.h, I.v, N, tsz)

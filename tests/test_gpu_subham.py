@@ -1,0 +1,107 @@
+"""The stacked sub-Hamiltonian MPO on the GPU (Sec. 4.2, Eqs. subH, hmrenorm).
+
+The library's sum-of-sub-Hamiltonians MPO runs through the same blocking,
+sigma and sweep kernels as the main MPO: every interior channel belongs to
+one H_m and W never couples two of them, so each sigma is the sum over m of
+the sub-Hamiltonians' sigma vectors on their own environment blocks.
+Checked here:
+  * sigma, diagonal and energy of one state equal those of the main MPO
+    (the same H) element by element, and the oracle's dense sigma;
+  * whole sweeps give the oracle's energies on the same stacked MPO
+    (goldens written by tests/golden/make_golden.py from oracle.submpo) and
+    the main path's energies, to 1e-8.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1605_02611_amd as P  # noqa: E402
+from oracle import dmrg as od  # noqa: E402
+from tests import helpers as H  # noqa: E402
+from workloads import chain_integrals, mps_values, workload_integrals  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_dmrg.json")
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a), device="cuda", dtype=torch.float64)
+
+
+def test_sum_mpo_sigma_diag_energy_equal_the_main_mpo(ctx):
+    K, N, tsz, M = 8, 8, 0, 20
+    I = chain_integrals(K, n_elec=N, seed=401)
+    d = od.DMRG(I.h, I.v, N, tsz, M, mps_values(401, od.n_mps_values(K, N, tsz, M)), dav_max_iter=20)
+    mpos = {"main": P.Mpo(ctx, I.h, I.v, N, tsz)}
+    for g in (0, 1):
+        mpos["subham%d" % g] = P.Mpo.sum_of_subhamiltonians(ctx, I.h, I.v, N, tsz, grouping=g)
+    done = 0
+    for c in (0, 3, 6):
+        while done < c:
+            d.step(done, True, False)
+            done += 1
+        bonds = [H.sectors(l) for l in d.labels]
+        fine = np.concatenate([H.site_fine_blocks(d.A[j], d.labels[j], d.labels[j + 1]) for j in range(K)])
+        lab_l, lab_r = d.labels[c], d.labels[c + 2]
+        rng = np.random.default_rng(c)
+        msk = d.mask(c)
+        x = rng.standard_normal(msk.shape) * msk
+        ref = H.dense_to_merged(d.sigma(c, x), lab_l, lab_r)
+        xd = _dev(H.dense_to_merged(x, lab_l, lab_r))
+        out = {}
+        for name, mpo in mpos.items():
+            _log("center %d %s D=%s" % (c, name, list(mpo.bond_dims())))
+            mps = P.Mps.from_tensors(ctx, mpo, bonds, fine, c)
+            yd = torch.zeros_like(xd)
+            mps.sigma(xd, yd)
+            dg = torch.zeros_like(xd)
+            mps.diag(dg)
+            out[name] = (yd.cpu().numpy(), dg.cpu().numpy(), mps.energy())
+            del mps
+        scale = np.abs(ref).max()
+        for name, (y, dg, e) in out.items():
+            assert np.abs(y - ref).max() <= 1e-12 * scale, (c, name)
+            assert np.abs(y - out["main"][0]).max() <= 1e-12 * scale, (c, name)
+            assert np.abs(dg - out["main"][1]).max() <= 1e-12 * max(1.0, np.abs(dg).max()), (c, name)
+            assert abs(e - out["main"][2]) <= 1e-12 * max(1.0, abs(e)), (c, name)
+
+
+@pytest.mark.parametrize("name", ["chain8_subham0", "chain8_subham1", "chain7_odd_subham1", "random_k8_subham0"])
+def test_sum_mpo_sweeps_match_oracle_and_main_path_energies(ctx, name):
+    gold = json.load(open(GOLD))
+    g = gold[name]
+    main = gold[name.rsplit("_subham", 1)[0]]
+    _log("sweeps", name)
+    if g["kind"] == "random":
+        I = workload_integrals("random_k8")
+    else:
+        I = chain_integrals(g["K"], n_elec=g["N"], seed=g["seed"])
+    mpo = P.Mpo.sum_of_subhamiltonians(ctx, I.h, I.v, g["N"], g["two_sz"], grouping=g["subham"])
+    assert list(mpo.bond_dims()) == g["mpo_bond_dims"]
+    mps = P.Mps.random(ctx, mpo, g["M"], mps_values(g["seed"], mpo.n_values(g["M"])))
+    stats, thetas = mps.sweep(g["M"], g["sweeps"])
+    es = np.array([s["energy"] for s in stats])
+    for ref in (g, main):
+        assert np.abs(es - np.array(ref["sweep_energies"])).max() < 1e-8
+        assert np.abs(thetas - np.array(ref["last_sweep_thetas"])).max() < 1e-8
+        assert abs(mps.energy() - ref["energy"]) < 1e-8
+    for k in range(g["K"] + 1):
+        assert [list(t) for t in mps.bond(k)] == g["bonds"][k]
+    if "fci" in g:
+        assert mps.energy() >= g["fci"] - 1e-10
