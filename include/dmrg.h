@@ -133,6 +133,22 @@ typedef struct {
                             block that keeps every direction is unchanged.
                             Singular values below about 1e-8 of the largest
                             in a block are not resolved. */
+    int basis;           /* choice of normal / complementary two-index
+                            intermediates (Appendix, recursion bases r1-r4),
+                            per family: the pair family (a+_p a+_q and
+                            a_q a_p on the left, partners P^R; or P^L on the
+                            left, bare pairs on the right) and the a+a family
+                            (a+_p a_q on the left, partners Q^R; or Q^L on
+                            the left, bare a+a on the right).
+                            0: both normal on bonds k <= switch_bond and
+                               complementary beyond (r1 then r2);
+                            1: both normal at every bond (r1, D ~ 2k^2);
+                            2: both complementary (r2, D ~ 2(K-k)^2);
+                            3: pairs normal, a+a complementary (r3);
+                            4: a+a normal, pairs complementary (r4);
+                            3 and 4 give D ~ k^2 + (K-k)^2 (spin orbitals).
+                            switch_bond is used by basis 0 only.  A
+                            zero-initialised struct keeps basis 0. */
 } dmrg_mpo_opts;
 
 /* Build the normal/complementary MPO of H for K sites, N electrons and
@@ -140,7 +156,8 @@ typedef struct {
  * Errors: DMRG_E_INVAL if K < 1, N outside [0, 2K], parity(2S_z) !=
  * parity(N), |2S_z| > min(N, 2K-N), h not symmetric, v without the
  * 8-fold symmetry (relative tolerance 1e-12), compress_tol negative or not
- * finite; DMRG_E_NUMERIC if the compression's eigensolver fails. */
+ * finite, basis outside 0..4; DMRG_E_NUMERIC if the compression's
+ * eigensolver fails. */
 dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
                            int n_elec, int two_sz, const dmrg_mpo_opts* opts,
                            dmrg_mpo** out);

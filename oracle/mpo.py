@@ -9,7 +9,9 @@ What is built (Sec. 2.3-2.4 of the paper):
     operators of Eqs. Sm and norm_complementary and w_pqrs = v_pqrs - v_pqsr.
   * The 2-index complementary operators (P, Q) sit on the right for
     k <= floor(K/2) and on the left beyond it (the switch described after
-    Eq. Hdecomp; Appendix, recursions r1/r2).
+    Eq. Hdecomp; Appendix, recursions r1/r2).  The other recursion bases of
+    the Appendix choose per family and bond (family_normal): r1 or r2 at
+    every bond, and the mixed r3 / r4.
   * Each bond index ("channel") is the pair (left operator, right partner);
     the MPO matrix W[site] is the blocking rule that writes every left
     operator at bond k+1 as sum_x O^L_x[k] (x) w_xy (Eqs. leftrenorm,
@@ -52,7 +54,24 @@ def switch_bond(K):
     return K // 2
 
 
-def channels(K, k):
+def family_normal(K, k, basis=0):
+    """(pair family normal, a+a family normal) at bond k.
+
+    Appendix, recursion bases r1-r4.  The pair family holds a+_p a+_q and
+    a_q a_p on the left (partners P^R, normal) or P^L, P^L+ (partners bare
+    pairs on the right, complementary); the a+a family holds a+_p a_q on the
+    left (partner Q^R) or Q^L (partner bare a+a).  basis 0 switches both at
+    floor(K/2) (r1 on the left half, r2 on the right), 1 = r1 everywhere,
+    2 = r2, 3 = r3 (B^R with P^R_LL: pairs normal, a+a complementary),
+    4 = r4 (Q^R_LL with bare pairs on the right: a+a normal, pairs
+    complementary)."""
+    if basis == 0:
+        n = k <= switch_bond(K)
+        return n, n
+    return {1: (True, True), 2: (False, False), 3: (True, False), 4: (False, True)}[basis]
+
+
+def channels(K, k, basis=0):
     """Ordered channel labels of bond k."""
     if k == 0:
         return [("I", -1, -1)]
@@ -63,13 +82,16 @@ def channels(K, k):
     out = [("I", -1, -1), ("H", -1, -1)]
     out += [("Cd", p, -1) for p in L] + [("C", p, -1) for p in L]
     out += [("SL", p, -1) for p in R] + [("SLd", p, -1) for p in R]
-    if k <= switch_bond(K):
+    pn, bn = family_normal(K, k, basis)
+    if pn:
         pairs = [(p, q) for p in L for q in L if p < q]
         out += [("A", p, q) for p, q in pairs] + [("Ad", p, q) for p, q in pairs]
-        out += [("B", p, q) for p in L for q in L]
     else:
         pairs = [(p, q) for p in R for q in R if p < q]
         out += [("P", p, q) for p, q in pairs] + [("Pd", p, q) for p, q in pairs]
+    if bn:
+        out += [("B", p, q) for p in L for q in L]
+    else:
         out += [("Q", p, q) for p in R for q in R]
     return out
 
@@ -111,17 +133,17 @@ class _Site:
         return SITE["c"][p - 2 * self.j]
 
 
-def _build_site(K, j, t, w, v):
+def _build_site(K, j, t, w, v, basis=0):
     """Sparse W of site j: {(x index, y index): 4x4 matrix}."""
     site = _Site(j)
     S = site.orbs
     Pm, Id = site.P, site.I
     cd, c = site.cdag, site.c
-    left = channels(K, j)
-    right = channels(K, j + 1)
+    left = channels(K, j, basis)
+    right = channels(K, j + 1, basis)
     lidx = {ch: i for i, ch in enumerate(left)}
     Lold = range(0, 2 * j)
-    normal_old = j <= switch_bond(K)
+    pair_normal_old, b_normal_old = family_normal(K, j, basis)
 
     def S_site(p):  # S^{site}_p = sum_q t_pq c_q + sum_qrs w_pqrs c+_q c_r c_s
         m = np.zeros((4, 4))
@@ -225,7 +247,7 @@ def _build_site(K, j, t, w, v):
                 out.append((("Cd", a, -1), m1 @ Pm))
                 out.append((("C", a, -1), -m2 @ Pm))
                 out.append((("C", a, -1), m3 @ Pm))
-            if normal_old:
+            if b_normal_old:
                 for a in Lold:
                     for b in Lold:
                         m = np.zeros((4, 4))
@@ -236,6 +258,10 @@ def _build_site(K, j, t, w, v):
                         for r in S:  # q=a, s=b, r on site: -B[a,b]
                             m -= w[p, a, r, b] * c(r)
                         out.append((("B", a, b), m @ Pm))
+            else:
+                for s in S:
+                    out.append((("Q", p, s), -2.0 * c(s) @ Pm))
+            if pair_normal_old:
                 for r in Lold:
                     for s in Lold:
                         sa = ad_pair(r, s)
@@ -247,8 +273,6 @@ def _build_site(K, j, t, w, v):
                             m += w[p, qq, r, s] * cd(qq)
                         out.append((x, sg * m @ Pm))
             else:
-                for s in S:
-                    out.append((("Q", p, s), -2.0 * c(s) @ Pm))
                 for qq in S:
                     if p < qq:
                         out.append((("P", p, qq), 2.0 * cd(qq) @ Pm))
@@ -271,7 +295,7 @@ def _build_site(K, j, t, w, v):
             else:
                 out.append((("B", p, q), Id.copy()))
         elif kind == "P":
-            if normal_old:
+            if pair_normal_old:
                 for a in Lold:
                     for b in Lold:
                         if a < b:
@@ -294,7 +318,7 @@ def _build_site(K, j, t, w, v):
                     m += v[p, q, r, s] * (c(r) @ c(s))
             out.append((("I", -1, -1), m))
         elif kind == "Q":
-            if normal_old:
+            if b_normal_old:
                 for r in Lold:
                     for s in Lold:
                         out.append((("B", r, s), w[p, r, q, s] * Id))
@@ -349,13 +373,14 @@ def _build_site(K, j, t, w, v):
     return {k: m for k, m in W.items() if np.any(m != 0.0)}
 
 
-def build_mpo(h, v):
-    """List of K sparse site tensors {(x, y): 4x4} and the channel lists."""
+def build_mpo(h, v, basis=0):
+    """List of K sparse site tensors {(x, y): 4x4} and the channel lists
+    (basis: the recursion basis of family_normal)."""
     K = h.shape[0]
     t, vs = spin_orbital_integrals(h, v)
     w = vs - vs.transpose(0, 1, 3, 2)
-    Ws = [_build_site(K, j, t, w, vs) for j in range(K)]
-    chans = [channels(K, k) for k in range(K + 1)]
+    Ws = [_build_site(K, j, t, w, vs, basis) for j in range(K)]
+    chans = [channels(K, k, basis) for k in range(K + 1)]
     return Ws, chans
 
 
@@ -397,8 +422,8 @@ def apply_mpo(Ws, chans, x):
     return T.reshape(-1)
 
 
-def bond_dims(K):
-    return [len(channels(K, k)) for k in range(K + 1)]
+def bond_dims(K, basis=0):
+    return [len(channels(K, k, basis)) for k in range(K + 1)]
 
 
 # --- Hamiltonian compression (Sec. "Hamiltonian compression") ----------------
@@ -427,15 +452,16 @@ def _coupling_row(kind, p, q, other, vs, w):
     return np.array([w[p, r, q, s] for r in other for s in other])
 
 
-def compression_blocks(h, v, K, k):
+def compression_blocks(h, v, K, k, basis=0):
     """2-index blocks of bond k: list of (family, row channel indices, G)."""
     _, vs = spin_orbital_integrals(h, v)
     w = vs - vs.transpose(0, 1, 3, 2)
-    ch = channels(K, k)
-    normal = k <= switch_bond(K)
-    other = range(2 * k, 2 * K) if normal else range(0, 2 * k)
+    ch = channels(K, k, basis)
+    pn, bn = family_normal(K, k, basis)
     out = []
-    for fam in (("A", "B") if normal else ("P", "Q")):
+    for fam in ("A" if pn else "P", "B" if bn else "Q"):
+        normal = pn if fam in ("A", "P") else bn
+        other = range(2 * k, 2 * K) if normal else range(0, 2 * k)
         order = []
         rows = {}
         for i, c in enumerate(ch):
@@ -452,7 +478,7 @@ def compression_blocks(h, v, K, k):
     return out
 
 
-def compress_mpo(Ws, chans, h, v, tol):
+def compress_mpo(Ws, chans, h, v, tol, basis=0):
     """Compressed site tensors, channel labels and, per bond, every
     singular value of its 2-index blocks (zeros included, one per row)."""
     K = len(Ws)
@@ -466,7 +492,7 @@ def compress_mpo(Ws, chans, h, v, tol):
         kept = []  # (family, row indices, U) of the blocks that lose directions
         full_rows = set()
         conj_of = {"A": "Ad", "P": "Pd"}
-        for fam, rows, G in compression_blocks(h, v, K, k):
+        for fam, rows, G in compression_blocks(h, v, K, k, basis):
             if G.shape[1] == 0:
                 U, s = np.zeros((len(rows), 0)), np.zeros(0)
             else:

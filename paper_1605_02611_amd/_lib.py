@@ -23,7 +23,7 @@ STATUS = {0: "DMRG_OK", 1: "DMRG_E_INVAL", 2: "DMRG_E_NOMEM", 3: "DMRG_E_HIP",
 
 
 class MpoOpts(C.Structure):
-    _fields_ = [("switch_bond", c_int), ("compress_tol", c_double)]
+    _fields_ = [("switch_bond", c_int), ("compress_tol", c_double), ("basis", c_int)]
 
 
 class SweepOpts(C.Structure):

@@ -136,7 +136,7 @@ class Context:
 class Mpo:
     """Normal/complementary MPO of H (dmrg_build_mpo)."""
 
-    def __init__(self, ctx, h, v, n_elec, two_sz=None, switch_bond=-1, compress_tol=0.0):
+    def __init__(self, ctx, h, v, n_elec, two_sz=None, switch_bond=-1, compress_tol=0.0, basis=0):
         self.ctx, self.lib = ctx, ctx.lib
         h = np.asarray(h, dtype=np.float64)
         K = h.shape[0]
@@ -145,7 +145,7 @@ class Mpo:
             two_sz = n_elec % 2
         hh, hp = _dptr(h)
         vv, vp = _dptr(v)
-        opts = L.MpoOpts(switch_bond, compress_tol)
+        opts = L.MpoOpts(switch_bond, compress_tol, basis)
         out = C.c_void_p()
         ctx.check(self.lib.dmrg_build_mpo(ctx.h, hp, vp, K, n_elec, two_sz, C.byref(opts),
                                           C.byref(out)))

@@ -219,16 +219,18 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(h && v && out, "null argument");
-        int sw = -1;
+        int sw = -1, basis = 0;
         double tol = 0.0;
         if (opts) {
             require(std::isfinite(opts->compress_tol) && opts->compress_tol >= 0.0,
                     "compress_tol must be finite and >= 0");
             require(opts->switch_bond >= -1 && opts->switch_bond <= K, "switch_bond out of range");
+            require(opts->basis >= 0 && opts->basis <= 4, "basis must be in 0..4");
             sw = opts->switch_bond;
             tol = opts->compress_tol;
+            basis = opts->basis;
         }
-        auto m = build_mpo(h, v, K, n_elec, two_sz, sw, tol);
+        auto m = build_mpo(h, v, K, n_elec, two_sz, sw, tol, basis);
         auto* r = new dmrg_mpo();
         r->m = std::move(m);
         *out = r;

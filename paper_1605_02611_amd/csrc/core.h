@@ -138,7 +138,11 @@ struct WGroups {
 };
 
 struct MPO {
-    int K = 0, n_elec = 0, two_sz = 0, switch_bond = 0;
+    int K = 0, n_elec = 0, two_sz = 0;
+    // bonds k <= switch_bond keep the a+a family normal (B on the left),
+    // k <= pair_switch_bond the pair family (A, Ad on the left); basis: the
+    // dmrg_mpo_opts value they came from (-1 for a sum MPO)
+    int switch_bond = 0, pair_switch_bond = 0, basis = 0;
     std::vector<WGroups> sys_groups;  // per site: grouped by right channel (left blocking)
     std::vector<WGroups> env_groups;  // per site: grouped by left channel (right blocking)
     std::vector<std::vector<Chan>> chans;        // bonds 0..K
@@ -151,7 +155,7 @@ struct MPO {
 };
 // compress_tol > 0: SVD compression of the 2-index channel blocks (mpo.cpp)
 std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
-                               int switch_bond, double compress_tol = 0.0);
+                               int switch_bond, double compress_tol = 0.0, int basis = 0);
 // Sum of sub-Hamiltonian MPOs stacked in one channel space (subham.cpp);
 // grouping 0: H_m collects the terms whose first creation operator is m
 // (Eq. subH), 1: the terms whose rightmost operator sits on spin orbital m

@@ -100,7 +100,11 @@ int64_t key_of(const Chan& c) {
     return (int64_t(c.kind) * 4096 + (c.p + 1)) * 4096 + (c.q + 1);
 }
 
-std::vector<Chan> bond_channels(int K, int k, int sw) {
+// Channels of bond k.  The pair family (a+a+ / a a on the left with the
+// P^R partners, or P^L with bare pairs on the right) is normal on bonds
+// k <= swp, the a+a family (B on the left with Q^R, or Q^L with bare a+a on
+// the right) on bonds k <= swb (Appendix, recursion bases r1-r4).
+std::vector<Chan> bond_channels(int K, int k, int swb, int swp) {
     std::vector<Chan> out;
     if (k == 0) return {{CK_I, -1, -1}};
     if (k == K) return {{CK_H, -1, -1}};
@@ -111,20 +115,22 @@ std::vector<Chan> bond_channels(int K, int k, int sw) {
     for (int p = 0; p < nl; ++p) out.push_back({CK_C, p, -1});
     for (int p = nl; p < nso; ++p) out.push_back({CK_SL, p, -1});
     for (int p = nl; p < nso; ++p) out.push_back({CK_SLd, p, -1});
-    int lo = (k <= sw) ? 0 : nl, hi = (k <= sw) ? nl : nso;
-    int kA = (k <= sw) ? CK_A : CK_P, kAd = (k <= sw) ? CK_Ad : CK_Pd, kB = (k <= sw) ? CK_B : CK_Q;
-    for (int p = lo; p < hi; ++p)
-        for (int q = p + 1; q < hi; ++q) out.push_back({kA, p, q});
-    for (int p = lo; p < hi; ++p)
-        for (int q = p + 1; q < hi; ++q) out.push_back({kAd, p, q});
-    for (int p = lo; p < hi; ++p)
-        for (int q = lo; q < hi; ++q) out.push_back({kB, p, q});
+    const bool np = k <= swp, nb = k <= swb;
+    const int plo = np ? 0 : nl, phi = np ? nl : nso, blo = nb ? 0 : nl, bhi = nb ? nl : nso;
+    const int kA = np ? CK_A : CK_P, kAd = np ? CK_Ad : CK_Pd, kB = nb ? CK_B : CK_Q;
+    for (int p = plo; p < phi; ++p)
+        for (int q = p + 1; q < phi; ++q) out.push_back({kA, p, q});
+    for (int p = plo; p < phi; ++p)
+        for (int q = p + 1; q < phi; ++q) out.push_back({kAd, p, q});
+    for (int p = blo; p < bhi; ++p)
+        for (int q = blo; q < bhi; ++q) out.push_back({kB, p, q});
     return out;
 }
 
 class Builder {
   public:
-    Builder(const double* h, const double* v, int K, int sw) : h_(h), v_(v), K_(K), sw_(sw) {}
+    Builder(const double* h, const double* v, int K, int swb, int swp)
+        : h_(h), v_(v), K_(K), swb_(swb), swp_(swp) {}
 
     double t(int P, int Q) const {
         return (P % 2 == Q % 2) ? h_[(P / 2) * K_ + Q / 2] : 0.0;
@@ -218,7 +224,7 @@ class Builder {
         const Mat4& P = o_.P;
         const int a0 = 2 * j_, a1 = 2 * j_ + 2;  // site orbitals [a0, a1)
         const int nold = 2 * j_;                 // old left block orbitals [0, nold)
-        const bool normal_old = j_ <= sw_;
+        const bool normal_b_old = j_ <= swb_, normal_p_old = j_ <= swp_;
         auto push = [&](Chan c, const Mat4& m) { out.push_back({c, m}); };
         switch (y.kind) {
             case CK_I: push({CK_I, -1, -1}, o_.I); break;
@@ -249,7 +255,7 @@ class Builder {
                     addto(m23, -1.0, m2);
                     push({CK_C, a, -1}, mul(m23, P));
                 }
-                if (normal_old) {
+                if (normal_b_old) {
                     for (int a = 0; a < nold; ++a)
                         for (int b = 0; b < nold; ++b) {
                             Mat4 m;  // q=a r=b (s on site)  minus  q=a s=b (r on site)
@@ -259,6 +265,10 @@ class Builder {
                             }
                             push({CK_B, a, b}, mul(m, P));
                         }
+                } else {
+                    for (int s = a0; s < a1; ++s) push({CK_Q, p, s}, scal(-2.0, mul(cc(s), P)));
+                }
+                if (normal_p_old) {
                     for (int r = 0; r < nold; ++r)
                         for (int s = 0; s < nold; ++s) {
                             if (r == s) continue;
@@ -269,7 +279,6 @@ class Builder {
                             else push({CK_Ad, r, s}, scal(-1.0, mul(m, P)));
                         }
                 } else {
-                    for (int s = a0; s < a1; ++s) push({CK_Q, p, s}, scal(-2.0, mul(cc(s), P)));
                     for (int q = a0; q < a1; ++q) {
                         if (p < q) push({CK_P, p, q}, scal(2.0, mul(cd(q), P)));
                         else push({CK_P, q, p}, scal(-2.0, mul(cd(q), P)));
@@ -290,7 +299,7 @@ class Builder {
                 break;
             case CK_P: {
                 const int p = y.p, q = y.q;
-                if (normal_old) {
+                if (normal_p_old) {
                     for (int a = 0; a < nold; ++a)
                         for (int b = a + 1; b < nold; ++b) {
                             double c = vs(p, q, b, a) - vs(p, q, a, b);
@@ -315,7 +324,7 @@ class Builder {
             }
             case CK_Q: {
                 const int p = y.p, q = y.q;
-                if (normal_old) {
+                if (normal_b_old) {
                     for (int r = 0; r < nold; ++r)
                         for (int s = 0; s < nold; ++s) {
                             double c = w(p, r, q, s);
@@ -387,7 +396,7 @@ class Builder {
   private:
     const double* h_;
     const double* v_;
-    int K_, sw_, j_ = 0;
+    int K_, swb_, swp_, j_ = 0;
     SiteOps o_;
     std::vector<Chan> left_;
 };
@@ -633,8 +642,7 @@ CBond compress_bond(const MPO& m, const double* h, const double* v, int k, doubl
         if (P % 2 != S % 2 || Q % 2 != R % 2) return 0.0;
         return v[((int64_t(P / 2) * K + S / 2) * K + Q / 2) * K + R / 2];
     };
-    const bool normal = k <= m.switch_bond;
-    const int o0 = normal ? 2 * k : 0, o1 = normal ? 2 * K : 2 * k;  // other side's orbitals
+    const bool pnormal = k <= m.pair_switch_bond, bnormal = k <= m.switch_bond;
     std::unordered_map<int64_t, int> index;
     for (int i = 0; i < D; ++i) index[key_of(ch[i])] = i;
 
@@ -645,7 +653,7 @@ CBond compress_bond(const MPO& m, const double* h, const double* v, int k, doubl
         int r = 0;
     };
     std::vector<Block> blocks;
-    for (int fam : {normal ? CK_A : CK_P, normal ? CK_B : CK_Q}) {
+    for (int fam : {pnormal ? CK_A : CK_P, bnormal ? CK_B : CK_Q}) {
         const int conj = fam == CK_A ? CK_Ad : fam == CK_P ? CK_Pd : -1;
         std::vector<QN> order;
         std::vector<std::vector<int>> rows;
@@ -678,6 +686,8 @@ CBond compress_bond(const MPO& m, const double* h, const double* v, int k, doubl
     std::vector<char> keep_old(D, 1);
     for (Block& B : blocks) {
         const int n = int(B.rows.size());
+        const bool normal = (B.fam == CK_A || B.fam == CK_P) ? pnormal : bnormal;
+        const int o0 = normal ? 2 * k : 0, o1 = normal ? 2 * K : 2 * k;  // other side's orbitals
         // G (n x ncol)
         std::vector<double> G;
         int ncol = 0;
@@ -890,22 +900,28 @@ void check_integrals(const double* h, const double* v, int K, int n_elec, int tw
 }
 
 std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
-                               int switch_bond, double compress_tol) {
+                               int switch_bond, double compress_tol, int basis) {
     require(std::isfinite(compress_tol) && compress_tol >= 0.0, "compress_tol must be finite and >= 0");
+    require(basis >= 0 && basis <= 4, "basis must be 0 (switch), 1 (r1), 2 (r2), 3 (r3) or 4 (r4)");
     check_integrals(h, v, K, n_elec, two_sz);
 
     auto m = std::make_unique<MPO>();
     m->K = K;
     m->n_elec = n_elec;
     m->two_sz = two_sz;
-    m->switch_bond = switch_bond < 0 ? K / 2 : switch_bond;
+    const int sw = switch_bond < 0 ? K / 2 : switch_bond;
+    // (a+a family, pair family) normal up to these bonds
+    const int swb[5] = {sw, K, 0, 0, K}, swp[5] = {sw, K, 0, K, 0};
+    m->switch_bond = swb[basis];
+    m->pair_switch_bond = swp[basis];
+    m->basis = basis;
     for (int k = 0; k <= K; ++k) {
-        m->chans.push_back(bond_channels(K, k, m->switch_bond));
+        m->chans.push_back(bond_channels(K, k, m->switch_bond, m->pair_switch_bond));
         std::vector<QN> dq;
         for (const Chan& c : m->chans.back()) dq.push_back(chan_qn(c));
         m->chan_dq.push_back(dq);
     }
-    Builder b(h, v, K, m->switch_bond);
+    Builder b(h, v, K, m->switch_bond, m->pair_switch_bond);
     m->W.resize(K);
     m->fine.resize(K);
     m->sys_groups.resize(K);

@@ -376,6 +376,8 @@ std::unique_ptr<MPO> build_sum_mpo(const double* h, const double* v, int K, int 
     m->n_elec = n_elec;
     m->two_sz = two_sz;
     m->switch_bond = -1;
+    m->pair_switch_bond = -1;
+    m->basis = -1;
     m->chans.resize(K + 1);
     m->chan_dq.resize(K + 1);
     for (int k = 0; k <= K; ++k) {

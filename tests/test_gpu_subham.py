@@ -1,4 +1,5 @@
-"""The stacked sub-Hamiltonian MPO on the GPU (Sec. 4.2, Eqs. subH, hmrenorm).
+"""Other MPOs of the same H on the GPU: the stacked sub-Hamiltonians
+(Sec. 4.2, Eqs. subH, hmrenorm) and the recursion bases r1-r4 (Appendix).
 
 The library's sum-of-sub-Hamiltonians MPO runs through the same blocking,
 sigma and sweep kernels as the main MPO: every interior channel belongs to
@@ -9,7 +10,9 @@ Checked here:
     (the same H) element by element, and the oracle's dense sigma;
   * whole sweeps give the oracle's energies on the same stacked MPO
     (goldens written by tests/golden/make_golden.py from oracle.submpo) and
-    the main path's energies, to 1e-8.
+    the main path's energies, to 1e-8;
+  * sweeps on the main MPO built with each recursion basis give the
+    oracle's energies of the default basis, to 1e-8.
 """
 
 import json
@@ -105,3 +108,17 @@ def test_sum_mpo_sweeps_match_oracle_and_main_path_energies(ctx, name):
         assert [list(t) for t in mps.bond(k)] == g["bonds"][k]
     if "fci" in g:
         assert mps.energy() >= g["fci"] - 1e-10
+
+
+@pytest.mark.parametrize("basis", [1, 2, 3, 4])
+def test_recursion_bases_sweep_to_the_oracle_energies(ctx, basis):
+    g = json.load(open(GOLD))["chain8"]
+    _log("sweeps chain8 basis", basis)
+    I = chain_integrals(g["K"], n_elec=g["N"], seed=g["seed"])
+    mpo = P.Mpo(ctx, I.h, I.v, g["N"], g["two_sz"], basis=basis)
+    mps = P.Mps.random(ctx, mpo, g["M"], mps_values(g["seed"], mpo.n_values(g["M"])))
+    stats, thetas = mps.sweep(g["M"], g["sweeps"])
+    es = np.array([s["energy"] for s in stats])
+    assert np.abs(es - np.array(g["sweep_energies"])).max() < 1e-8
+    assert np.abs(thetas - np.array(g["last_sweep_thetas"])).max() < 1e-8
+    assert abs(mps.energy() - g["energy"]) < 1e-8
