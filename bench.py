@@ -252,6 +252,111 @@ def precision_check(args, P, mps, pre_e):
                       "davidson_tol": 1e-8, "davidson_max_iter": 60, "runs": rows}), flush=True)
 
 
+def precision_sweeps(args, P, torch, mps, mpo, M, pre_e):
+    """Mixed vs FP64 over whole sweeps: the state after the presweeps is
+    saved, then swept args.precision_sweeps times in FP64, in FP32 and in
+    BF16 (both refined in FP64 below a residual of 1e-4), every Davidson
+    step converged to args.conv_tol (iteration cap args.conv_iter), each run
+    from the saved state.  One JSON line: per run and sweep the energy,
+    seconds, Davidson iterations and unconverged steps, |dE| against FP64."""
+    import tempfile
+    path = os.path.join(tempfile.mkdtemp(prefix="dmrg_state_"), "presweep.mps")
+    mps.save(path)
+    runs = {}
+    for name, prec, refine in (("fp64", P.DMRG_FP64, 0.0), ("fp32_refined", P.DMRG_FP32, 1e-4),
+                               ("bf16_refined", P.DMRG_BF16, 1e-4)):
+        m = P.Mps.load(mps.ctx, mpo, path)
+        o = P.default_opts(prec=prec, dav_tol=args.conv_tol, dav_max_iter=args.conv_iter, refine_tol=refine)
+        rows = []
+        for i in range(args.precision_sweeps):
+            torch.cuda.synchronize()
+            t1 = time.time()
+            st, _ = m.sweep(M, 1, o)
+            torch.cuda.synchronize()
+            st = st[0]
+            rows.append({"energy": st["energy"], "seconds": time.time() - t1, "sigma_seconds": st["sigma_seconds"],
+                         "sigma_calls": st["sigma_calls"], "dav_iters": st["dav_iters"],
+                         "unconverged_steps": st["unconverged"], "max_residual": st["max_residual"],
+                         "discarded": st["discarded"]})
+            log("%s sweep %d: E %.10f %.1fs iters %d unconverged %d max|r| %.1e" % (
+                name, i, st["energy"], rows[-1]["seconds"], st["dav_iters"], st["unconverged"], st["max_residual"]))
+        runs[name] = {"sweeps": rows, "energy": m.energy(), "seconds": sum(r["seconds"] for r in rows)}
+        del m
+    os.remove(path)
+    ref = runs["fp64"]
+    for r in runs.values():
+        r["abs_dE_per_sweep_vs_fp64"] = [abs(a["energy"] - b["energy"]) for a, b in zip(r["sweeps"], ref["sweeps"])]
+        r["abs_dE_vs_fp64"] = abs(r["energy"] - ref["energy"])
+        r["within_1e-5"] = max(r["abs_dE_per_sweep_vs_fp64"]) <= 1e-5
+        r["speedup_vs_fp64"] = ref["seconds"] / r["seconds"]
+        r["all_steps_converged"] = all(x["unconverged_steps"] == 0 for x in r["sweeps"])
+    print(json.dumps({"mode": "precision_sweeps",
+                      "workload": "chain molecule K=36 N=36 M=%d, %d sweeps from the state after %d FP64 sweeps"
+                                  % (M, args.precision_sweeps, args.presweeps),
+                      "presweep_energy": pre_e, "davidson_tol": args.conv_tol, "davidson_max_iter": args.conv_iter,
+                      "refine_below_residual": 1e-4, "tolerance_eh": 1e-5, "runs": runs}), flush=True)
+
+
+def compress_study(args, P, torch):
+    """Hamiltonian compression against the energy at converged states (Sec.
+    "Hamiltonian compression"): for every threshold tau the compressed MPO
+    is built and swept from the same random state until the energy moves
+    by less than 1e-9 Eh per sweep (every Davidson step converged); the
+    exact-H ground state is also evaluated with each compressed MPO (first
+    order in the compression).  One JSON line: per tau the MPO bond
+    dimensions, the converged energy, |E(tau) - E(0)| and the first-order
+    shift."""
+    import tempfile
+    from workloads import WORKLOADS, workload_integrals, mps_values
+    name = "chain_k20_m256"
+    c = WORKLOADS[name]
+    K, M = c["K"], c["M"]
+    ctx = P.Context(0)
+    I = workload_integrals(name)
+    taus = [float(x) for x in args.compress_study.split(",")]
+    if taus[0] != 0.0:
+        taus = [0.0] + taus
+    o = P.default_opts(dav_tol=args.conv_tol, dav_max_iter=args.conv_iter)
+    path = os.path.join(tempfile.mkdtemp(prefix="dmrg_state_"), "exact.mps")
+    rows = []
+    for tau in taus:
+        t0 = time.time()
+        mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz, compress_tol=tau)
+        D = [int(d) for d in mpo.bond_dims()]
+        m = P.Mps.random(ctx, mpo, M, mps_values(c["seed"], mpo.n_values(M)))
+        es, conv = [], False
+        for i in range(c["sweeps"]):
+            st, _ = m.sweep(M, 1, o)
+            es.append(st[0]["energy"])
+            log("tau %g sweep %d E %.12f unconverged %d" % (tau, i, es[-1], st[0]["unconverged"]))
+            if len(es) > 1 and abs(es[-1] - es[-2]) < 1e-9:
+                conv = True
+                break
+        row = {"tau": tau, "mpo_bond_dims": D, "D_mean": float(np.mean(D[1:K])), "D_max": max(D),
+               "energy": m.energy(), "sweeps": len(es), "converged": conv,
+               "last_sweep_change": abs(es[-1] - es[-2]) if len(es) > 1 else None,
+               "seconds": time.time() - t0}
+        if tau == 0.0:
+            m.save(path)
+        else:
+            ex = P.Mps.load(ctx, mpo, path)
+            row["first_order_energy"] = ex.energy()
+            del ex
+        rows.append(row)
+        del m
+    os.remove(path)
+    e0 = rows[0]["energy"]
+    for r in rows:
+        r["abs_dE"] = abs(r["energy"] - e0)
+        if "first_order_energy" in r:
+            r["first_order_shift"] = r["first_order_energy"] - e0
+        log("tau %-8g D_mean %7.1f D_max %5d E %.12f |dE| %.2e (%d sweeps)" % (
+            r["tau"], r["D_mean"], r["D_max"], r["energy"], r["abs_dE"], r["sweeps"]))
+    print(json.dumps({"mode": "compress_study", "workload": "%s: chain molecule K=%d N=%d M=%d" % (name, K, K, M),
+                      "davidson_tol": args.conv_tol, "davidson_max_iter": args.conv_iter, "rows": rows}),
+          flush=True)
+
+
 def learned(args, P, torch):
     """Learned vs diagonal Davidson preconditioner: both runs start from the
     same random state; the learned run collects samples during the first
@@ -342,6 +447,17 @@ def main():
                     help="instead of middle steps: after the presweeps, solve the middle two-site "
                          "problem from the same start vector in FP64, FP32 and BF16 (with and without "
                          "the FP64 refinement) and compare eigenvalues and sigma time")
+    ap.add_argument("--precision-sweeps", type=int, default=0,
+                    help="instead of middle steps: after the presweeps, this many full sweeps from "
+                         "the same saved state in FP64, FP32 and BF16 (refined in FP64), every step "
+                         "converged to --conv-tol; energies, |dE| against FP64 and time ratios")
+    ap.add_argument("--compress-study", default="",
+                    help="instead of middle steps: comma-separated MPO compression thresholds; the "
+                         "K=20 M=256 chain swept to convergence with each (and the exact MPO)")
+    ap.add_argument("--conv-tol", type=float, default=1e-6,
+                    help="Davidson residual tolerance of --precision-sweeps")
+    ap.add_argument("--conv-iter", type=int, default=400,
+                    help="Davidson iteration cap of --precision-sweeps")
     ap.add_argument("--autotune", action="store_true",
                     help="run the launch autotuner at the middle pair before the timed steps")
     ap.add_argument("--compress", type=float, default=0.0,
@@ -379,6 +495,8 @@ def main():
         return batched(args, P, torch)
     if args.learned:
         return learned(args, P, torch)
+    if args.compress_study:
+        return compress_study(args, P, torch)
     c = WORKLOADS["chain_k36_m1024"]
     K, M = c["K"], c["M"]
     ctx = P.Context(0)
@@ -400,6 +518,8 @@ def main():
             st, _ = mps.sweep(M, 1, opts)
             pre_e = st[-1]["energy"]
             log("presweep %d: E %.10f (%.1fs)" % (i, pre_e, time.time() - t0))
+    if args.precision_sweeps:
+        return precision_sweeps(args, P, torch, mps, mpo, M, pre_e)
     sweep = None
     if not args.sweeps and not args.no_sweep and not args.precision_check:
         # sweep seconds: one full sweep (forward and back over every pair:

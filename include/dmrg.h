@@ -188,6 +188,14 @@ dmrg_status dmrg_build_mpo(dmrg_ctx* ctx, const double* h, const double* v, int 
  * other than 0 or 1.  Host-only: works on a host-only context. */
 dmrg_status dmrg_build_sum_mpo(dmrg_ctx* ctx, const double* h, const double* v, int K,
                                int n_elec, int two_sz, int grouping, dmrg_mpo** out);
+/* MPO of a*1 + b*H from an MPO of H (any dmrg_mpo: every term of the MPO
+ * product enters the channels whose right partner is the identity exactly
+ * once, so the entries entering them are scaled by b, and a*1 closes the
+ * all-identity path at the last site).  With a = 1, b = -tau: the first-
+ * order imaginary-time step exp(-tau H) ~ 1 - tau H used with
+ * dmrg_mps_apply (Sec. 3).  Host-only.  DMRG_E_INVAL for a, b not finite. */
+dmrg_status dmrg_mpo_affine(dmrg_ctx* ctx, const dmrg_mpo* mpo, double a, double b,
+                            dmrg_mpo** out);
 /* MPO bond dimensions D[0..K] (caller-owned array of K+1). */
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D);
 /* Channel labels of bond k: 3*D[k] ints (kind, p, q), kinds
@@ -426,6 +434,31 @@ dmrg_status dmrg_sweep_batched(dmrg_ctx* ctx, int n, dmrg_mps* const* mps,
  * two-site vector is split exactly by SVD (singular values <= 1e-14 sigma_max
  * dropped) and the environment on the side left behind is updated. */
 dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int forward);
+/* MPO x MPS inside the sweep machinery (Sec. 3): the compression of
+ * op|ket> by overlap maximization.  A bra |Phi> with the ket's quantum-
+ * number block structure (every bond keeps the ket's sector dimensions)
+ * starts as the ket at the ket's center and is swept n_sweeps times
+ * (forward to the last pair, back to the first); each two-site step sets
+ * the bra's pair to sum_x L[x] W W R[x'] applied to the ket's pair, with
+ * L, R the mixed environments <bra|op|ket> (the sigma kernels of
+ * dmrg_sigma on the ket's layouts), and splits it by SVD keeping the ket's
+ * sector dimensions (the largest singular values of each sector).  The
+ * result maximizes <Phi|op|ket> over bras of that structure with fixed
+ * norm; with complete bonds it is op|ket> exactly.  <ket|op op|ket> follows
+ * as <Phi|Phi> (= <Phi|op|ket> at the optimum).
+ * ket: the state (on ket_mpo) whose two-site vector must equal the product
+ * of its center site tensors (true after dmrg_mps_random, _import, _load,
+ * and every completed step or move; not after dmrg_solve or
+ * dmrg_psi_import alone: DMRG_E_STATE); it is not changed.  op: the MPO to
+ * apply (same K, N, 2S_z); out_mpo: the MPO of the returned state's
+ * environments (e.g. ket_mpo).  *out: a new state on out_mpo at pair 0,
+ * unnormalised (its norm squared is <Phi|Phi>).  overlap (may be NULL):
+ * <Phi|op|ket> after the last step; norm2_per_sweep (may be NULL, n_sweeps
+ * doubles): <Phi|Phi> after each sweep.  DMRG_E_INVAL for n_sweeps outside
+ * [1, 1000] or MPOs of another K / N / 2S_z. */
+dmrg_status dmrg_mps_apply(dmrg_ctx* ctx, dmrg_mps* ket, const dmrg_mpo* ket_mpo,
+                           const dmrg_mpo* op, const dmrg_mpo* out_mpo, int n_sweeps,
+                           dmrg_mps** out, double* overlap, double* norm2_per_sweep);
 /* ---- launch autotuner -----------------------------------------------------
  *
  * The sigma passes have a launch configuration: output tile edge of each

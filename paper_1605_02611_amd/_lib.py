@@ -58,6 +58,9 @@ SIGNATURES = {
                                P(MpoOpts), P(c_void_p)]),
     "dmrg_build_sum_mpo": (c_int, [c_void_p, P(c_double), P(c_double), c_int, c_int, c_int, c_int,
                                    P(c_void_p)]),
+    "dmrg_mpo_affine": (c_int, [c_void_p, c_void_p, c_double, c_double, P(c_void_p)]),
+    "dmrg_mps_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, P(c_void_p),
+                               P(c_double), P(c_double)]),
     "dmrg_mpo_bond_dims": (c_int, [c_void_p, P(c_int32)]),
     "dmrg_mpo_channels": (c_int, [c_void_p, c_int, P(c_int32)]),
     "dmrg_mpo_singular_values": (c_int, [c_void_p, c_int, P(c_int64), P(c_double)]),

@@ -172,6 +172,15 @@ class Mpo:
         self.n_elec, self.two_sz = n_elec, two_sz
         return self
 
+    def affine(self, a, b):
+        """MPO of a*1 + b*H (dmrg_mpo_affine)."""
+        out = C.c_void_p()
+        self.ctx.check(self.lib.dmrg_mpo_affine(self.ctx.h, self.h, float(a), float(b), C.byref(out)))
+        r = Mpo.__new__(Mpo)
+        r.ctx, r.lib, r.K, r.h = self.ctx, self.lib, self.K, out
+        r.n_elec, r.two_sz = self.n_elec, self.two_sz
+        return r
+
     def sub_bond_dims(self):
         """Sub-Hamiltonian bond dimensions D[m, k] of a sum MPO (channels of
         bond k labelled with p = m)."""
@@ -411,6 +420,19 @@ class Mps:
 
     def move(self, forward=True):
         self.ctx.check(self.lib.dmrg_mps_move(self.ctx.h, self.h, self.mpo.h, int(bool(forward))))
+
+    def apply(self, op, n_sweeps=2, out_mpo=None):
+        """op|self> compressed by overlap maximization in this state's block
+        structure (dmrg_mps_apply): (new Mps on out_mpo, <Phi|op|self>,
+        <Phi|Phi> per sweep)."""
+        out_mpo = out_mpo or self.mpo
+        out = C.c_void_p()
+        ov = C.c_double()
+        n2 = np.zeros(n_sweeps)
+        self.ctx.check(self.lib.dmrg_mps_apply(self.ctx.h, self.h, self.mpo.h, op.h, out_mpo.h, int(n_sweeps),
+                                               C.byref(out), C.byref(ov),
+                                               n2.ctypes.data_as(C.POINTER(C.c_double))))
+        return Mps(self.ctx, out_mpo, out), ov.value, n2
 
     def energy(self):
         e = C.c_double()

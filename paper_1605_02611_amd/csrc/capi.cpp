@@ -249,6 +249,17 @@ dmrg_status dmrg_build_sum_mpo(dmrg_ctx* ctx, const double* h, const double* v, 
     });
 }
 
+dmrg_status dmrg_mpo_affine(dmrg_ctx* ctx, const dmrg_mpo* mpo, double a, double b, dmrg_mpo** out) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(mpo && out, "null argument");
+        auto m = affine_mpo(*mpo->m, a, b);
+        auto* r = new dmrg_mpo();
+        r->m = std::move(m);
+        *out = r;
+    });
+}
+
 dmrg_status dmrg_mpo_bond_dims(const dmrg_mpo* mpo, int32_t* D) {
     if (!mpo || !D) return DMRG_E_INVAL;
     for (size_t k = 0; k < mpo->m->chans.size(); ++k) D[k] = int32_t(mpo->m->chans[k].size());
@@ -865,6 +876,26 @@ dmrg_status dmrg_mps_move(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, int
         o.svd_cutoff = 1e-14;
         StepStats s;
         mps->st->step(1, forward != 0, o, s, false);
+    });
+}
+
+dmrg_status dmrg_mps_apply(dmrg_ctx* ctx, dmrg_mps* ket, const dmrg_mpo* ket_mpo, const dmrg_mpo* op,
+                           const dmrg_mpo* out_mpo, int n_sweeps, dmrg_mps** out, double* overlap,
+                           double* norm2_per_sweep) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(ket && ket_mpo && op && out_mpo && out, "null argument");
+        require(ket->st->mpo == ket_mpo->m.get(), "state was built with another MPO", E_STATE);
+        use_device(ctx->c);
+        ApplyOut res;
+        auto st = apply_mpo(*ket->st, op->m.get(), out_mpo->m.get(), n_sweeps, res);
+        auto* r = new dmrg_mps();
+        r->st = std::move(st);
+        r->owner = ctx_acquire(ctx);
+        *out = r;
+        if (overlap) *overlap = res.overlap;
+        if (norm2_per_sweep)
+            for (int i = 0; i < n_sweeps; ++i) norm2_per_sweep[i] = res.norm2_per_sweep[i];
     });
 }
 

@@ -161,6 +161,8 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
 // (Eq. subH), 1: the terms whose rightmost operator sits on spin orbital m
 std::unique_ptr<MPO> build_sum_mpo(const double* h, const double* v, int K, int n_elec, int two_sz,
                                    int grouping);
+// MPO of a 1 + b H from an MPO of H (mpo.cpp)
+std::unique_ptr<MPO> affine_mpo(const MPO& H, double a, double b);
 // argument checks shared by the builders (symmetry of h and v, N, 2S_z)
 void check_integrals(const double* h, const double* v, int K, int n_elec, int two_sz);
 // fine entries and blocking groups of W[j] (after W[j] is complete)

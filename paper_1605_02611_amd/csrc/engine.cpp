@@ -109,8 +109,17 @@ void add_tile(GemmList& L, int c_buf, int64_t c_off, int ldc, int r0, int c0, in
 }
 
 void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int accumulate,
-              const std::vector<UTerm>& terms, int splits, int64_t slice) {
+              const std::vector<UTerm>& terms_in, int splits, int64_t slice) {
     if (m <= 0 || n <= 0) return;
+    // terms of zero length (a sector with no states on the contracted side)
+    // add nothing; a unit left without terms writes zeros (or keeps C)
+    std::vector<UTerm> kept_terms;
+    bool any_empty = false;
+    for (const UTerm& u : terms_in) any_empty |= u.k <= 0;
+    if (any_empty)
+        for (const UTerm& u : terms_in)
+            if (u.k > 0) kept_terms.push_back(u);
+    const std::vector<UTerm>& terms = any_empty ? kept_terms : terms_in;
     add_unit_flops(L, m, n, terms);
     int64_t ktot = 0;
     for (const UTerm& u : terms) ktot += u.k;
@@ -487,8 +496,12 @@ Blocked State::block_env(int k, const Env& Rk1) {
 // ---------------------------------------------------------------------------
 // decimation (Eq. prenormdec): L_{j+1}[y] = A^T O^sys_y A ; R_k[x] = B O^env_x B^T
 
-std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged& A) {
+std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged& A, const Merged* ket) {
     hipStream_t s = ctx->stream;
+    // X uses the ket's tensor, the final contraction the bra's (A): for the
+    // state's own environments both are A
+    const Merged& Kt = ket ? *ket : A;
+    require(Kt.form == 1 && Kt.size == A.size && Kt.off == A.off, "internal: ket tensor layout differs", E_STATE);
     const BondL& bl = bonds[j];
     const BondL& bn = bonds[j + 1];
     const int nch = int(mpo->chans[j + 1].size());
@@ -534,7 +547,7 @@ std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged
                     const OpBlock& blk = r.lay->blocks[bi];
                     if (blk.out != so.sec) continue;
                     terms.push_back({0, r.off + blk.off, blk.cols, false, 1,
-                                     A.off[iq] + int64_t(sg.off) * ncol, ncol, false, blk.cols, 1.0,
+                                     Kt.off[iq] + int64_t(sg.off) * ncol, ncol, false, blk.cols, 1.0,
                                      true});
                 }
                 add_unit(p1, 2, xo + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
@@ -542,10 +555,10 @@ std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged
         }
     Bases b1{};
     b1.p[0] = Yb.buf.p;
-    b1.p[1] = A.buf.p;
+    b1.p[1] = Kt.buf.p;
     b1.p[2] = X.p;
     {
-        int64_t sz[kMaxBufs] = {elems(Yb.buf), elems(A.buf), elems(X)};
+        int64_t sz[kMaxBufs] = {elems(Yb.buf), elems(Kt.buf), elems(X)};
         run_list(p1, Prec::F64, b1, s, sz);
     }
 
@@ -577,8 +590,10 @@ std::unique_ptr<Env> State::decimate_left(const Blocked& Yb, int j, const Merged
     return E;
 }
 
-std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merged& B) {
+std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merged& B, const Merged* ket) {
     hipStream_t s = ctx->stream;
+    const Merged& Kt = ket ? *ket : B;
+    require(Kt.form == 2 && Kt.size == B.size && Kt.off == B.off, "internal: ket tensor layout differs", E_STATE);
     const BondL& bn = bonds[k];
     const BondL& br = bonds[k + 1];
     const int nch = int(mpo->chans[k].size());
@@ -622,7 +637,7 @@ std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merge
                     if (bi < 0) continue;
                     const OpBlock& blk = r.lay->blocks[bi];
                     if (blk.out != so.sec) continue;
-                    terms.push_back({0, r.off + blk.off, blk.cols, false, 1, B.off[iq] + sg.off,
+                    terms.push_back({0, r.off + blk.off, blk.cols, false, 1, Kt.off[iq] + sg.off,
                                      env[iq].dim, true, blk.cols, 1.0, true});
                 }
                 add_unit(p1, 2, xo + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
@@ -630,10 +645,10 @@ std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merge
         }
     Bases b1{};
     b1.p[0] = Zb.buf.p;
-    b1.p[1] = B.buf.p;
+    b1.p[1] = Kt.buf.p;
     b1.p[2] = X.p;
     {
-        int64_t sz[kMaxBufs] = {elems(Zb.buf), elems(B.buf), elems(X)};
+        int64_t sz[kMaxBufs] = {elems(Zb.buf), elems(Kt.buf), elems(X)};
         run_list(p1, Prec::F64, b1, s, sz);
     }
 
@@ -668,34 +683,38 @@ std::unique_ptr<Env> State::decimate_right(const Blocked& Zb, int k, const Merge
 // ---------------------------------------------------------------------------
 // two-site center
 
-// psi_q = A(q) B(q) for the sectors q of bond center+1 (A left-merged, B right-merged)
-void State::form_center_from_pair(const Merged& A, const Merged& B) {
+// psi_q = A(q) B(q) for the sectors q of bond j+1 (A left-merged, B right-merged)
+void State::pair_product(int j, const Merged& A, const Merged& B, DevBuf& out) {
     hipStream_t s = ctx->stream;
-    const int j = center;
-    ts = make_two_site(bonds[j], bonds[j + 2]);
-    psi.alloc(std::max<int64_t>(1, ts.n) * sizeof(double), s);
-    launch_fill(psi.as<double>(), 0.0, ts.n, s);
+    const TwoSite t2 = make_two_site(bonds[j], bonds[j + 2]);
+    out.alloc(std::max<int64_t>(1, t2.n) * sizeof(double), s);
+    launch_fill(out.as<double>(), 0.0, t2.n, s);
     GemmList Lg;
     std::vector<UTerm> terms;
     const BondL& bm = bonds[j + 1];
     for (size_t i = 0; i < bm.q.size(); ++i) {
-        const int iq = ts.find(bm.q[i]);
+        const int iq = t2.find(bm.q[i]);
         const int ia = A.find(bm.q[i]), ib = B.find(bm.q[i]);
         if (iq < 0 || ia < 0 || ib < 0) continue;
-        require(A.rows[ia] == ts.sys[iq].dim && B.cols[ib] == ts.env[iq].dim,
+        require(A.rows[ia] == t2.sys[iq].dim && B.cols[ib] == t2.env[iq].dim,
                 "internal: center shapes disagree", E_STATE);
         terms.clear();
         terms.push_back({0, A.off[ia], A.cols[ia], false, 1, B.off[ib], B.cols[ib], false,
                          A.cols[ia], 1.0, true});
-        add_unit(Lg, 2, ts.off[iq], ts.env[iq].dim, ts.sys[iq].dim, ts.env[iq].dim, 0, terms);
+        add_unit(Lg, 2, t2.off[iq], t2.env[iq].dim, t2.sys[iq].dim, t2.env[iq].dim, 0, terms);
     }
     Bases b{};
     b.p[0] = A.buf.p;
     b.p[1] = B.buf.p;
-    b.p[2] = psi.p;
-    int64_t sz[kMaxBufs] = {elems(A.buf), elems(B.buf), elems(psi)};
+    b.p[2] = out.p;
+    int64_t sz[kMaxBufs] = {elems(A.buf), elems(B.buf), elems(out)};
     run_list(Lg, Prec::F64, b, s, sz);
     DMRG_HIP(hipStreamSynchronize(s));
+}
+
+void State::form_center_from_pair(const Merged& A, const Merged& B) {
+    ts = make_two_site(bonds[center], bonds[center + 2]);
+    pair_product(center, A, B, psi);
 }
 
 // ---------------------------------------------------------------------------
@@ -2097,16 +2116,33 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
         return a.i < b.i;
     });
     const double smax = pool[0].v;
-    size_t nkeep = 0;
-    while (nkeep < pool.size() && nkeep < size_t(M) && pool[nkeep].v > o.svd_cutoff * smax) ++nkeep;
-    double disc = 0;
-    for (size_t i = nkeep; i < pool.size(); ++i) disc += pool[i].v * pool[i].v;
-    stt.discarded = std::max(stt.discarded, disc);
     std::vector<int> kept(nq, 0);
-    for (size_t i = 0; i < nkeep; ++i) kept[pool[i].iq]++;
+    double disc = 0;
+    if (force_bonds) {
+        // the sector dimensions of the given bond structure (overlap
+        // maximization): the largest singular values of each sector; a
+        // sector with fewer singular values than its dimension, or absent
+        // from the pair, is completed with zero states below
+        const BondL& fb = (*force_bonds)[j + 1];
+        for (int iq = 0; iq < nq; ++iq) {
+            kept[iq] = std::min(fb.dim_of(ts.q[iq]), outs[iq].r);
+            for (int i = kept[iq]; i < outs[iq].r; ++i) disc += sv[iq][i] * sv[iq][i];
+        }
+    } else {
+        size_t nkeep = 0;
+        while (nkeep < pool.size() && nkeep < size_t(M) && pool[nkeep].v > o.svd_cutoff * smax) ++nkeep;
+        for (size_t i = nkeep; i < pool.size(); ++i) disc += pool[i].v * pool[i].v;
+        for (size_t i = 0; i < nkeep; ++i) kept[pool[i].iq]++;
+    }
+    stt.discarded = std::max(stt.discarded, disc);
     std::vector<std::pair<QN, int>> nb;
-    for (int iq = 0; iq < nq; ++iq)
-        if (kept[iq] > 0) nb.push_back({ts.q[iq], kept[iq]});
+    if (force_bonds) {
+        const BondL& fb = (*force_bonds)[j + 1];
+        for (size_t i = 0; i < fb.q.size(); ++i) nb.push_back({fb.q[i], fb.dim[i]});
+    } else {
+        for (int iq = 0; iq < nq; ++iq)
+            if (kept[iq] > 0) nb.push_back({ts.q[iq], kept[iq]});
+    }
     set_bond(j + 1, nb);
     stt.max_bond = std::max(stt.max_bond, bonds[j + 1].total);
 
@@ -2120,23 +2156,34 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
     Merged Lf, Rf;
     Lf.form = 1;
     Rf.form = 2;
-    for (int iq = 0; iq < nq; ++iq) {
-        if (kept[iq] == 0) continue;
-        Lf.idx[ts.q[iq]] = int(Lf.q.size());
-        Lf.q.push_back(ts.q[iq]);
-        Lf.rows.push_back(ts.sys[iq].dim);
-        Lf.cols.push_back(kept[iq]);
+    // sectors of the new bond: rows of U over the sys space of bond j,
+    // columns of V^T over the env space of bond j+2
+    const BondL& nbd = bonds[j + 1];
+    for (size_t i = 0; i < nbd.q.size(); ++i) {
+        const QN q = nbd.q[i];
+        const int d = nbd.dim[i];
+        const int iq = ts.find(q);
+        const int rs = iq >= 0 ? ts.sys[iq].dim : sys_space(bonds[j], q).dim;
+        const int cs = iq >= 0 ? ts.env[iq].dim : env_space(bonds[j + 2], q).dim;
+        Lf.idx[q] = int(Lf.q.size());
+        Lf.q.push_back(q);
+        Lf.rows.push_back(rs);
+        Lf.cols.push_back(d);
         Lf.off.push_back(Lf.size);
-        Lf.size += int64_t(ts.sys[iq].dim) * kept[iq];
-        Rf.idx[ts.q[iq]] = int(Rf.q.size());
-        Rf.q.push_back(ts.q[iq]);
-        Rf.rows.push_back(kept[iq]);
-        Rf.cols.push_back(ts.env[iq].dim);
+        Lf.size += int64_t(rs) * d;
+        Rf.idx[q] = int(Rf.q.size());
+        Rf.q.push_back(q);
+        Rf.rows.push_back(d);
+        Rf.cols.push_back(cs);
         Rf.off.push_back(Rf.size);
-        Rf.size += int64_t(kept[iq]) * ts.env[iq].dim;
+        Rf.size += int64_t(d) * cs;
     }
     Lf.buf.alloc(std::max<int64_t>(1, Lf.size) * sizeof(double), s);
     Rf.buf.alloc(std::max<int64_t>(1, Rf.size) * sizeof(double), s);
+    if (force_bonds) {  // zero states where the pair holds fewer
+        launch_fill(Lf.buf.as<double>(), 0.0, std::max<int64_t>(1, Lf.size), s);
+        launch_fill(Rf.buf.as<double>(), 0.0, std::max<int64_t>(1, Rf.size), s);
+    }
     double* w = work.as<double>();
     for (int iq = 0; iq < nq; ++iq) {
         if (kept[iq] == 0) continue;
@@ -2144,7 +2191,7 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
         const int li = Lf.find(ts.q[iq]);
         const double* sc = w + so.s_off;
         // U part (rows x kept) from Um (rows x r); V^T part (kept x cols) from Vt
-        launch_gather_cols(Lf.buf.as<double>() + Lf.off[li], kept[iq], w + so.u_off, so.r,
+        launch_gather_cols(Lf.buf.as<double>() + Lf.off[li], Lf.cols[li], w + so.u_off, so.r,
                            iota_d.as<int>(), forward ? nullptr : sc, so.rows, kept[iq], s);
         launch_gather_rows(Rf.buf.as<double>() + Rf.off[li], so.cols, w + so.v_off, so.cols,
                            iota_d.as<int>(), forward ? sc : nullptr, kept[iq], so.cols, s);
@@ -2160,7 +2207,7 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
     }
     if (forward) {
         if (!last) {
-            L[j + 1] = decimate_left(Y, j, Lf);
+            L[j + 1] = decimate_left(Y, j, Lf, ket_left);
         }
         site[j] = std::move(Lf);
         site[j + 1] = std::move(Rf);
@@ -2203,7 +2250,7 @@ double State::finish_step(int M, bool forward, const SweepOpts& o, StepStats& st
     } else {
         // Rf = V^T (right-canonical B_{j+1}), Lf = U S (center on site j)
         if (!last) {
-            R[j + 1] = decimate_right(Z, j + 1, Rf);
+            R[j + 1] = decimate_right(Z, j + 1, Rf, ket_right);
         }
         site[j] = std::move(Lf);
         site[j + 1] = std::move(Rf);
@@ -2454,6 +2501,122 @@ void State::env_import(int side, int bond, const double* vals, int64_t n) {
     DMRG_HIP(hipMemcpyAsync(e->buf.p, h.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
     DMRG_HIP(hipStreamSynchronize(s));
     release_workspace();  // blocked operators and the diagonal depend on it
+}
+
+// ---------------------------------------------------------------------------
+// MPO x MPS by overlap maximization (Sec. 3)
+
+namespace {
+double device_norm2(const double* x, int64_t n, hipStream_t s) {
+    DevBuf part(sizeof(double) * kDotBlocks, s), out(sizeof(double), s);
+    launch_multidot(x, 0, 1, x, n, part.as<double>(), s);
+    launch_reduce_partials(part.as<double>(), 1, out.as<double>(), s);
+    double h = 0;
+    DMRG_HIP(hipMemcpyAsync(&h, out.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    return h;
+}
+}  // namespace
+
+std::unique_ptr<State> apply_mpo(State& ket, const MPO* O, const MPO* out_mpo, int n_sweeps, ApplyOut& res) {
+    Ctx* ctx = ket.ctx;
+    hipStream_t s = ctx->stream;
+    const int K = ket.mpo->K;
+    require(K >= 2, "two-site sweeps need K >= 2");
+    require(O->K == K && out_mpo->K == K, "the MPOs must have the ket's K");
+    require(O->target() == ket.mpo->target() && out_mpo->target() == ket.mpo->target(),
+            "the MPOs must have the ket's N and 2S_z");
+    require(n_sweeps >= 1 && n_sweeps <= 1000, "n_sweeps must be in [1, 1000]");
+    const int c = ket.center;
+    // the ket is the product of its site tensors: the two-site vector must
+    // equal the product of its center tensors (as after any completed step)
+    {
+        DevBuf prod;
+        ket.pair_product(c, ket.site[c], ket.site[c + 1], prod);
+        const int64_t n = ket.ts.n;
+        std::vector<double> a(std::max<int64_t>(1, n)), b(std::max<int64_t>(1, n));
+        DMRG_HIP(hipMemcpyAsync(a.data(), prod.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipMemcpyAsync(b.data(), ket.psi.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipStreamSynchronize(s));
+        double d = 0, m = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            d = std::max(d, std::fabs(a[i] - b[i]));
+            m = std::max(m, std::fabs(b[i]));
+        }
+        require(d <= 1e-10 * std::max(1.0, m),
+                "the ket's two-site vector is not the product of its center site tensors "
+                "(finish the step with dmrg_step or dmrg_mps_move first)", E_STATE);
+    }
+    // the ket's site tensors in both merged forms
+    std::vector<double> vals;
+    ket.export_tensors(vals);
+    std::vector<std::vector<std::pair<QN, int>>> bonds_in(K + 1);
+    for (int k = 0; k <= K; ++k)
+        for (size_t i = 0; i < ket.bonds[k].q.size(); ++i)
+            bonds_in[k].push_back({ket.bonds[k].q[i], ket.bonds[k].dim[i]});
+    std::vector<Merged> kl(K), kr(K);
+    {
+        std::vector<double> host;
+        int64_t pos = 0;
+        for (int j = 0; j < K; ++j) {
+            const int64_t p0 = pos;
+            merge_site(ket.bonds[j], ket.bonds[j + 1], 1, vals.data(), pos, kl[j], host);
+            upload(kl[j], host, s);
+            pos = p0;
+            merge_site(ket.bonds[j], ket.bonds[j + 1], 2, vals.data(), pos, kr[j], host);
+            upload(kr[j], host, s);
+        }
+        DMRG_HIP(hipStreamSynchronize(s));
+    }
+    // the bra starts as the ket, at the ket's center: its environments are
+    // then the mixed ones <bra|O|ket>
+    auto bra = std::make_unique<State>(ctx, O);
+    bra->import_tensors(bonds_in, vals.data(), c);
+    bra->force_bonds = &ket.bonds;
+    SweepOpts o;
+    o.svd_cutoff = 0.0;
+    StepStats stt;
+    DevBuf x;
+    auto step = [&](bool forward) {
+        const int j = bra->center;
+        bra->pair_product(j, kl[j], kr[j + 1], x);
+        bra->prepare();
+        require(int64_t(x.bytes / sizeof(double)) >= bra->ts.n, "internal: pair layout", E_STATE);
+        bra->sigma(x.as<double>(), bra->psi.as<double>(), Prec::F64, &stt);
+        const double n2 = device_norm2(bra->psi.as<double>(), bra->ts.n, s);
+        bra->ket_left = &kl[j];
+        bra->ket_right = &kr[j + 1];
+        StepStats one;
+        bra->finish_step(std::numeric_limits<int>::max(), forward, o, one, false, DavOut{}, 0, 0, 0, 0);
+        res.overlap = res.norm2 = n2 - one.discarded;
+        stt.discarded = std::max(stt.discarded, one.discarded);
+    };
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        stt.discarded = 0;
+        while (true) {  // forward to the last pair
+            const bool last = bra->center == K - 2;
+            step(true);
+            if (last) break;
+        }
+        while (true) {  // back to the first pair
+            const bool last = bra->center == 0;
+            step(false);
+            if (last) break;
+        }
+        res.norm2_per_sweep.push_back(res.norm2);
+        res.discarded_per_sweep.push_back(stt.discarded);
+    }
+    // the bra as a state of its own on out_mpo, environments rebuilt
+    std::vector<double> bvals;
+    bra->export_tensors(bvals);
+    std::vector<std::vector<std::pair<QN, int>>> bb(K + 1);
+    for (int k = 0; k <= K; ++k)
+        for (size_t i = 0; i < bra->bonds[k].q.size(); ++i)
+            bb[k].push_back({bra->bonds[k].q[i], bra->bonds[k].dim[i]});
+    bra.reset();
+    auto out = std::make_unique<State>(ctx, out_mpo);
+    out->import_tensors(bb, bvals.data(), 0);
+    return out;
 }
 
 }  // namespace dmrg

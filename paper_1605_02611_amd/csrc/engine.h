@@ -418,11 +418,35 @@ class State {
     void run_blocking(Blocked& B, const Env& src, int plan_key);
     Blocked block_sys(int j, const Env& Lj);
     Blocked block_env(int k, const Env& Rk1);
-    std::unique_ptr<Env> decimate_left(const Blocked& Yb, int j, const Merged& A);
-    std::unique_ptr<Env> decimate_right(const Blocked& Zb, int k, const Merged& B);
+    // ket: the ket's site tensor of a mixed environment <bra|O|ket> (the
+    // state's own tensor when null)
+    std::unique_ptr<Env> decimate_left(const Blocked& Yb, int j, const Merged& A, const Merged* ket = nullptr);
+    std::unique_ptr<Env> decimate_right(const Blocked& Zb, int k, const Merged& B, const Merged* ket = nullptr);
     void form_center_from_pair(const Merged& A, const Merged& B);
     void release_workspace();
+
+  public:
+    // two-site vector of the pair (j, j+1) from A (LEFT over bond j+1) and B
+    // (RIGHT over bond j+1) into out, in the layout make_two_site(bonds[j], bonds[j+2])
+    void pair_product(int j, const Merged& A, const Merged& B, DevBuf& out);
+    // overlap maximization (apply_mpo): the ket's tensors of the mixed
+    // environment updates and the sector dimensions every truncation keeps
+    const Merged* ket_left = nullptr;   // ket site j, LEFT form (forward steps)
+    const Merged* ket_right = nullptr;  // ket site j+1, RIGHT form (backward steps)
+    const std::vector<BondL>* force_bonds = nullptr;
 };
+
+// MPO x MPS by overlap maximization (Sec. 3): sweeps over a bra |Phi> that
+// keeps the ket's quantum-number block structure, each two-site step
+// setting the bra's pair to the projection of O|ket> (sigma of O on the
+// ket's pair with the mixed environments <bra|O|ket>).  Returns the bra as
+// a state on out_mpo at pair 0 (environments rebuilt), with <Phi|O|ket>
+// and <Phi|Phi> of the last step.
+struct ApplyOut {
+    double overlap = 0, norm2 = 0;
+    std::vector<double> norm2_per_sweep, discarded_per_sweep;
+};
+std::unique_ptr<State> apply_mpo(State& ket, const MPO* O, const MPO* out_mpo, int n_sweeps, ApplyOut& res);
 
 // Lockstep sweeps of independent instances with batched sigma launches.
 // Process-wide tuning table: shape key -> sigma configuration.

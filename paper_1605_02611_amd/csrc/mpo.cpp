@@ -934,6 +934,56 @@ std::unique_ptr<MPO> build_mpo(const double* h, const double* v, int K, int n_el
     return m;
 }
 
+// a 1 + b H from an MPO of H: every path of the MPO product enters the
+// channels whose right partner is the identity (kind CK_H; the last bond's
+// single channel) exactly once and stays there, so scaling the entries that
+// enter them by b scales every term by b; the identity is the all-identity
+// path (left operator 1 up to bond K-1) closed at the last site by a 1.
+std::unique_ptr<MPO> affine_mpo(const MPO& H, double a, double b) {
+    require(std::isfinite(a) && std::isfinite(b), "a and b must be finite");
+    const int K = H.K;
+    auto m = std::make_unique<MPO>();
+    m->K = K;
+    m->n_elec = H.n_elec;
+    m->two_sz = H.two_sz;
+    m->switch_bond = H.switch_bond;
+    m->pair_switch_bond = H.pair_switch_bond;
+    m->basis = H.basis;
+    m->chans = H.chans;
+    m->chan_dq = H.chan_dq;
+    m->compress_tol = H.compress_tol;
+    m->sv = H.sv;
+    m->W = H.W;
+    auto is_h = [&](int k, int c) { return k == K || H.chans[k][c].kind == CK_H; };
+    for (int j = 0; j < K; ++j)
+        for (auto& [xy, mat] : m->W[j])
+            if (is_h(j + 1, xy.second) && !(j > 0 && is_h(j, xy.first))) mat = scal(b, mat);
+    int xi = -1;
+    for (size_t c = 0; c < H.chans[K - 1].size() && xi < 0; ++c)
+        if (H.chans[K - 1][c].kind == CK_I) xi = int(c);
+    require(xi >= 0, "the MPO has no identity channel before the last site");
+    Mat4 id;
+    for (int i = 0; i < 4; ++i) id(i, i) = a;
+    bool done = false;
+    for (auto& [xy, mat] : m->W[K - 1])
+        if (xy.first == xi && xy.second == 0) {
+            addto(mat, 1.0, id);
+            done = true;
+        }
+    if (!done && a != 0.0) m->W[K - 1].push_back({{xi, 0}, id});
+    auto& W = m->W[K - 1];
+    W.erase(std::remove_if(W.begin(), W.end(), [](const auto& e) { return e.second.zero(); }), W.end());
+    m->fine.resize(K);
+    m->sys_groups.resize(K);
+    m->env_groups.resize(K);
+    for (int j = 0; j < K; ++j) {
+        auto& Wj = m->W[j];
+        Wj.erase(std::remove_if(Wj.begin(), Wj.end(), [](const auto& e) { return e.second.zero(); }), Wj.end());
+        index_site(*m, j);
+    }
+    return m;
+}
+
 OpLayout make_layout(const Bond& b, QN dq) {
     OpLayout L;
     L.dq = dq;

@@ -174,3 +174,39 @@ def test_collect_train_and_learned_sweeps(ctx):
         res[mode] = (m2.energy(), [s["dav_iters"] for s in st], sum(s["precond_fallbacks"] for s in st))
         _log("precond %d energy %.12f iters %s fallbacks %d" % ((mode,) + res[mode]))
     assert abs(res[0][0] - res[1][0]) <= 1e-8
+
+
+def test_learned_correction_keeps_every_step_at_k12_m128(ctx):
+    """K=12 M=128 chain: one collecting sweep, training, then two sweeps
+    from the same state with the diagonal and with the learned correction,
+    every step converged to 1e-9.  The learned correction changes how
+    Davidson gets there, not where: every step's theta and every sweep's
+    energy agree to 1e-8.  The iteration counts are logged; at this size
+    the learned correction costs 1.1-1.3x the diagonal iterations (the
+    gain measured on the K=24 / K=48 workloads under a 24-iteration cap
+    does not appear here), and the fallback bounds the loss."""
+    K, M, seed = 12, 128, 62
+    I = chain_integrals(K, n_elec=K, seed=seed)
+    mpo = P.Mpo(ctx, I.h, I.v, K, 0)
+    vals = mps_values(seed, mpo.n_values(M))
+    net = P.Mlp(ctx, seed=5, capacity=1 << 21)
+    res = {}
+    for mode in ("diagonal", "learned"):
+        m = P.Mps.random(ctx, mpo, M, vals)
+        o = P.default_opts(dav_tol=1e-9, dav_max_iter=200, collect=1 if mode == "learned" else 0,
+                           mlp=net if mode == "learned" else None)
+        m.sweep(M, 1, o)
+        if mode == "learned":
+            net.train(1, 4096, 1e-3, 11)
+            net.train(30, 4096, 1e-3, 12)
+            o = P.default_opts(dav_tol=1e-9, dav_max_iter=200, precond=1, mlp=net)
+        st, th = m.sweep(M, 2, o)
+        res[mode] = ([s["energy"] for s in st], np.array(th), sum(s["dav_iters"] for s in st),
+                     sum(s["unconverged"] for s in st))
+        _log("%s: energies %s iterations %d" % (mode, res[mode][0], res[mode][2]))
+    d, l = res["diagonal"], res["learned"]
+    assert d[3] == 0 and l[3] == 0
+    assert np.abs(np.array(d[0]) - np.array(l[0])).max() < 1e-8
+    assert np.abs(d[1] - l[1]).max() < 1e-8
+    _log("learned / diagonal iterations %.3f" % (l[2] / d[2]))
+    assert l[2] < 1.6 * d[2]

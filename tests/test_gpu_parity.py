@@ -295,6 +295,34 @@ def test_batched_sweeps_equal_individual_sweeps(ctx, prec):
         assert mps.bond(I.K // 2) == singles[b][2]
 
 
+def test_batched_fp64_sweeps_reach_the_oracle_goldens(ctx):
+    """Instances with oracle goldens (chain K=8, chain K=7 odd, the random
+    K=8 molecule, the chain K=8 stacked sub-Hamiltonians) swept together in
+    lockstep: every instance's per-sweep FP64 energies equal the oracle's."""
+    gold = _golden()
+    names = ["chain8", "chain7_odd", "random_k8", "chain8_subham1"]
+    states, Ms, mpos = [], [], []
+    for nm in names:
+        g = gold[nm]
+        I = workload_integrals("random_k8") if g["kind"] == "random" else \
+            chain_integrals(g["K"], n_elec=g["N"], seed=g["seed"])
+        if g.get("subham") is not None:
+            mpo = P.Mpo.sum_of_subhamiltonians(ctx, I.h, I.v, g["N"], g["two_sz"], grouping=g["subham"])
+        else:
+            mpo = P.Mpo(ctx, I.h, I.v, g["N"], g["two_sz"])
+        mpos.append(mpo)
+        states.append(P.Mps.random(ctx, mpo, g["M"], mps_values(g["seed"], mpo.n_values(g["M"]))))
+        Ms.append(g["M"])
+    n_sw = 3
+    _log("batched goldens", names)
+    stats, _ = P.sweep_batched(ctx, states, Ms, n_sw, P.default_opts())
+    for b, nm in enumerate(names):
+        es = np.array([s["energy"] for s in stats[b]])
+        assert np.abs(es - np.array(gold[nm]["sweep_energies"][:n_sw])).max() < 1e-8, nm
+        if len(gold[nm]["sweep_energies"]) == n_sw:
+            assert abs(states[b].energy() - gold[nm]["energy"]) < 1e-8, nm
+
+
 # --- truncation with large sectors (round-parallel Jacobi SVD) --------------------
 
 def _sector_layout(bl, br):

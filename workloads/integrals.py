@@ -115,6 +115,9 @@ WORKLOADS = {
     "chain_k36_m1024": dict(kind="chain", K=36, n_elec=36, M=1024, sweeps=8, seed=1003),
     "batch64_k12_24": dict(kind="batched", n=64, sweeps=8, seed=4999),
     "chain_k48_m1024": dict(kind="chain", K=48, n_elec=48, M=1024, sweeps=6, seed=1005),
+    # stand-in for the 20-orbital hydrogen chain of the compression study
+    # (Sec. "Hamiltonian compression"): chain integrals, K = N = 20
+    "chain_k20_m256": dict(kind="chain", K=20, n_elec=20, M=256, sweeps=12, seed=1006),
 }
 
 
