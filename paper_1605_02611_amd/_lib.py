@@ -59,6 +59,8 @@ SIGNATURES = {
     "dmrg_build_sum_mpo": (c_int, [c_void_p, P(c_double), P(c_double), c_int, c_int, c_int, c_int,
                                    P(c_void_p)]),
     "dmrg_mpo_affine": (c_int, [c_void_p, c_void_p, c_double, c_double, P(c_void_p)]),
+    "dmrg_debug_svd": (c_int, [c_void_p, c_int, P(c_int32), P(c_int32), P(c_double), P(c_double), P(c_double),
+                               P(c_double), c_int]),
     "dmrg_mps_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, P(c_void_p),
                                P(c_double), P(c_double)]),
     "dmrg_mpo_bond_dims": (c_int, [c_void_p, P(c_int32)]),

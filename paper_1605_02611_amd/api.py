@@ -113,6 +113,26 @@ class Context:
             self.h, prec, m, n, k, int(ta), int(tb), alpha, C_void(A), A.stride(0), C_void(B),
             B.stride(0), C_void(C), C.stride(0), int(accumulate), int(tile)))
 
+    def debug_svd(self, mats, path=0):
+        """dmrg_debug_svd on a list of 2-D arrays: [(U, S, Vt)]."""
+        mats = [np.ascontiguousarray(m, dtype=np.float64) for m in mats]
+        rows = np.array([m.shape[0] for m in mats], dtype=np.int32)
+        cols = np.array([m.shape[1] for m in mats], dtype=np.int32)
+        r = np.minimum(rows, cols)
+        a = np.concatenate([m.ravel() for m in mats])
+        S = np.zeros(int(r.sum()))
+        U = np.zeros(int((rows * r).sum()))
+        Vt = np.zeros(int((r * cols).sum()))
+        dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))
+        ip = lambda x: x.ctypes.data_as(C.POINTER(C.c_int32))
+        self.check(self.lib.dmrg_debug_svd(self.h, len(mats), ip(rows), ip(cols), dp(a), dp(S), dp(U), dp(Vt),
+                                           int(path)))
+        out, us, ss, vs = [], 0, 0, 0
+        for m, n, k in zip(rows, cols, r):
+            out.append((U[us:us + m * k].reshape(m, k), S[ss:ss + k], Vt[vs:vs + k * n].reshape(k, n)))
+            us, ss, vs = us + m * k, ss + k, vs + k * n
+        return out
+
     def check(self, st, allow_noconv=False):
         """Raise DmrgError for a failed call; DMRG_E_NOCONV (the call completed
         and its statistics count the unconverged solves) passes when

@@ -745,6 +745,16 @@ dmrg_status dmrg_env_import(dmrg_ctx* ctx, dmrg_mps* mps, int side, int bond, co
     });
 }
 
+dmrg_status dmrg_debug_svd(dmrg_ctx* ctx, int n, const int32_t* rows, const int32_t* cols,
+                           const double* a, double* S, double* U, double* Vt, int path) {
+    if (!ctx) return DMRG_E_INVAL;
+    return guard(ctx, [&] {
+        require(rows && cols && a && S && U && Vt, "null argument");
+        use_device(ctx->c);
+        debug_svd(&ctx->c, n, rows, cols, a, S, U, Vt, path);
+    });
+}
+
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
                             double* C, int ldc, int accumulate, int tile) {

@@ -300,6 +300,10 @@ void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s);
 void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
                          int* rotated, hipStream_t s);
 void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s);
+// every round of one sweep in one cooperative launch; false when the device
+// cannot launch it cooperatively (the caller then launches the rounds)
+bool launch_jacobi_sweep(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rounds, const int* live,
+                         int* rotated, hipStream_t s);
 constexpr int kJacobiRoundMin = 160;  // sectors with at least this many columns use the round launches
 
 // ---------------------------------------------------------------------------

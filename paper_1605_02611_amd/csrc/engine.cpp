@@ -954,8 +954,13 @@ struct SideJoin {
     }
 };
 
+// jacobi_max: sectors with min(rows, cols) above it go to rocSOLVER (-1:
+// 768, or 0 when DMRG_SVD_ROCSOLVER is set); round_launches: the large-
+// sector Jacobi path launches one kernel per round instead of one
+// cooperative kernel per sweep
 static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::pair<int, int>>>& mats,
-                      std::vector<SvdOut>& outs, DevBuf& work, DevBuf& info) {
+                      std::vector<SvdOut>& outs, DevBuf& work, DevBuf& info, int jacobi_max = -1,
+                      bool round_launches = false) {
     hipStream_t s = ctx->stream;
     outs.clear();
     int64_t tot = 0;
@@ -980,7 +985,8 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
     info.alloc(std::max<size_t>(1, mats.size()) * sizeof(rocblas_int), s);
     double* w = work.as<double>();
     // small sectors: batched one-sided Jacobi kernel; large ones: rocSOLVER
-    static const int jmax = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 768;
+    static const int jdefault = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 768;
+    const int jmax = jacobi_max >= 0 ? jacobi_max : jdefault;
     std::vector<char> jac(mats.size(), 0);
     std::vector<SvdJob> jobs;
     int64_t jtot = 0;
@@ -1052,9 +1058,11 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
             for (int sw = 0; sw < 60 && left > 0; ++sw) {
                 DMRG_HIP(hipMemcpyAsync(dlive.p, live.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
                 DMRG_HIP(hipMemsetAsync(drot.p, 0, nb * sizeof(int), s));
-                for (int rd = 0; rd < rounds; ++rd)
-                    launch_jacobi_round(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
-                                        drot.as<int>(), s);
+                if (round_launches || !launch_jacobi_sweep(big, dslots.as<int2>(), int64_t(slots.size()), rounds,
+                                                           dlive.as<int>(), drot.as<int>(), s))
+                    for (int rd = 0; rd < rounds; ++rd)
+                        launch_jacobi_round(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
+                                            drot.as<int>(), s);
                 DMRG_HIP(hipMemcpyAsync(rot.data(), drot.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
                 DMRG_HIP(hipStreamSynchronize(s));
                 for (int b = 0; b < nb; ++b)
@@ -2617,6 +2625,45 @@ std::unique_ptr<State> apply_mpo(State& ket, const MPO* O, const MPO* out_mpo, i
     auto out = std::make_unique<State>(ctx, out_mpo);
     out->import_tensors(bb, bvals.data(), 0);
     return out;
+}
+
+// SVD of host matrices through the library's sector SVD (test hook): path
+// 0 the library's choice, 1 every matrix through rocSOLVER, 2 the Jacobi
+// kernels with one launch per round, 3 the Jacobi kernels with one
+// cooperative launch per sweep.  U (rows x r), S (r), Vt (r x cols) with
+// r = min(rows, cols), row-major, concatenated.
+void debug_svd(Ctx* ctx, int n, const int32_t* rows, const int32_t* cols, const double* a, double* S, double* U,
+               double* Vt, int path) {
+    hipStream_t s = ctx->stream;
+    require(n >= 1 && n <= 4096 && path >= 0 && path <= 3, "bad debug_svd arguments");
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        require(rows[i] >= 1 && cols[i] >= 1 && rows[i] <= 8192 && cols[i] <= 8192, "bad matrix shape");
+        tot += int64_t(rows[i]) * cols[i];
+    }
+    DevBuf A(tot * sizeof(double), s);
+    DMRG_HIP(hipMemcpyAsync(A.p, a, tot * sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<std::pair<const double*, std::pair<int, int>>> mats;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        mats.push_back({A.as<double>() + off, {rows[i], cols[i]}});
+        off += int64_t(rows[i]) * cols[i];
+    }
+    std::vector<SvdOut> outs;
+    DevBuf work, info;
+    svd_batch(ctx, mats, outs, work, info, path == 1 ? 0 : (path >= 2 ? 8192 : -1), path == 2);
+    int64_t us = 0, ss = 0, vs = 0;
+    for (const SvdOut& o : outs) {
+        DMRG_HIP(hipMemcpyAsync(U + us, work.as<double>() + o.u_off, sizeof(double) * o.rows * o.r,
+                                hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipMemcpyAsync(S + ss, work.as<double>() + o.s_off, sizeof(double) * o.r, hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipMemcpyAsync(Vt + vs, work.as<double>() + o.v_off, sizeof(double) * o.r * o.cols,
+                                hipMemcpyDeviceToHost, s));
+        us += int64_t(o.rows) * o.r;
+        ss += o.r;
+        vs += int64_t(o.r) * o.cols;
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace dmrg

@@ -447,6 +447,9 @@ struct ApplyOut {
     std::vector<double> norm2_per_sweep, discarded_per_sweep;
 };
 std::unique_ptr<State> apply_mpo(State& ket, const MPO* O, const MPO* out_mpo, int n_sweeps, ApplyOut& res);
+// sector SVD of host matrices (test hook of dmrg_debug_svd)
+void debug_svd(Ctx* ctx, int n, const int32_t* rows, const int32_t* cols, const double* a, double* S, double* U,
+               double* Vt, int path);
 
 // Lockstep sweeps of independent instances with batched sigma launches.
 // Process-wide tuning table: shape key -> sigma configuration.

@@ -9,6 +9,7 @@
 //    renormalized operators with MPO coefficients).
 //  * FP64 vector kernels for Davidson (multi-dot with fixed-order partial
 //    sums, linear combinations, preconditioner) and small gathers.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -1309,6 +1310,39 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const SvdJob* __restr
     if (jacobi_rotate(A, V, d.m, d.n, p, q, threadIdx.x & 63) && (threadIdx.x & 63) == 0) rotated[sl.x] = 1;
 }
 
+// All rounds of one Jacobi sweep of the large sectors in one cooperative
+// launch: each wave takes (sector, pair) slots of the round in a grid-
+// stride loop, and a grid barrier separates the rounds (the next round's
+// pairs read the columns the previous one rotated).  Every workgroup runs
+// the same number of rounds and barriers; nothing returns early.
+__global__ __launch_bounds__(256) void jacobi_sweep_kernel(const SvdJob* __restrict__ jobs,
+                                                           const int2* __restrict__ slots, int64_t n_slots,
+                                                           int rounds, const int* __restrict__ live,
+                                                           int* __restrict__ rotated) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int64_t nw = int64_t(gridDim.x) * 4;
+    const int64_t w0 = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int rd = 0; rd < rounds; ++rd) {
+        for (int64_t w = w0; w < n_slots; w += nw) {
+            const int2 sl = slots[w];
+            if (!live[sl.x]) continue;
+            const SvdJob job = jobs[sl.x];
+            const JacobiDims d = jacobi_dims(job);
+            const int nn = d.n + (d.n & 1);
+            if (rd >= nn - 1) continue;
+            int p, q;
+            jacobi_pair_of(nn, rd, sl.y, p, q);
+            if (p >= d.n || q >= d.n) continue;
+            double* A = job.work;
+            double* V = job.work + int64_t(d.m) * d.n;
+            if (jacobi_rotate(A, V, d.m, d.n, p, q, lane) && lane == 0) rotated[sl.x] = 1;
+        }
+        __threadfence();
+        grid.sync();
+    }
+}
+
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_finish_kernel(const SvdJob* __restrict__ jobs,
                                                                       const int* __restrict__ info) {
     const SvdJob job = jobs[blockIdx.x];
@@ -1595,6 +1629,30 @@ void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots,
                        n_slots, rd, live, rotated);
     DMRG_HIP(hipGetLastError());
 }
+bool launch_jacobi_sweep(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rounds, const int* live,
+                         int* rotated, hipStream_t s) {
+    // co-resident workgroups of the kernel on this device (0: no cooperative launch)
+    static int max_grid = -1;
+    if (max_grid < 0) {
+        int dev = 0, coop = 0, cus = 0, per_cu = 0;
+        DMRG_HIP(hipGetDevice(&dev));
+        DMRG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        DMRG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        DMRG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jacobi_sweep_kernel, 256, 0));
+        max_grid = coop ? per_cu * cus : 0;
+    }
+    if (max_grid <= 0 || n_slots <= 0 || rounds <= 0) return false;
+    const int g = int(std::min<int64_t>(max_grid, (n_slots + 3) / 4));
+    void* args[] = {&jobs, &slots, &n_slots, &rounds, &live, &rotated};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(jacobi_sweep_kernel), dim3(g),
+                                                    dim3(256), args, 0, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
 void launch_jacobi_finish(const SvdJob* jobs, int n_jobs, const int* info, hipStream_t s) {
     if (n_jobs <= 0) return;
     hipLaunchKernelGGL(jacobi_finish_kernel, dim3(n_jobs), dim3(kJacobiThreads), 0, s, jobs, info);

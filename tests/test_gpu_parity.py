@@ -340,6 +340,32 @@ def _sector_layout(bl, br):
     return out
 
 
+@pytest.mark.parametrize("path", [0, 1, 2, 3])
+def test_sector_svd_paths_match_numpy(ctx, path):
+    """The truncation's sector SVD through each of its paths (0 the
+    library's choice: Jacobi per workgroup below 160 columns, the
+    cooperative round-parallel Jacobi up to 768, rocSOLVER beyond; 1 all
+    rocSOLVER; 2 Jacobi with one launch per round; 3 the cooperative
+    Jacobi) against numpy: singular values, U S V^T = A, orthonormal U and
+    V^T rows for the nonzero singular values."""
+    rng = np.random.default_rng(70 + path)
+    shapes = [(1, 1), (5, 3), (3, 5), (64, 64), (100, 120), (200, 170), (170, 230), (300, 260)]
+    if path in (0, 1):
+        shapes += [(800, 790), (790, 900)]  # beyond 768: rocSOLVER in the library's choice
+    mats = [rng.standard_normal(sh) for sh in shapes]
+    # a rank-deficient one
+    mats.append(rng.standard_normal((180, 6)) @ rng.standard_normal((6, 175)))
+    _log("svd path", path, [m.shape for m in mats])
+    for A, (U, S, Vt) in zip(mats, ctx.debug_svd(mats, path)):
+        ref = np.linalg.svd(A, compute_uv=False)
+        smax = ref[0]
+        assert np.abs(S - ref).max() <= 1e-12 * smax, A.shape
+        assert np.abs((U * S) @ Vt - A).max() <= 1e-12 * smax * max(A.shape) ** 0.5, A.shape
+        k = int(np.sum(S > 1e-10 * smax))
+        assert np.abs(U[:, :k].T @ U[:, :k] - np.eye(k)).max() < 1e-10, A.shape
+        assert np.abs(Vt[:k] @ Vt[:k].T - np.eye(k)).max() < 1e-10, A.shape
+
+
 def test_truncation_with_large_sectors_matches_numpy_svd(ctx):
     """A K=12 random state at M=1024 has two-site sectors of a few hundred
     columns at the middle: one truncating step to M=64 (Davidson limited to
