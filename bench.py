@@ -30,7 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA, TFLOP/s
+# dense MFMA, TFLOP/s; bf16x3 does six BF16 products per product of the
+# model, so its peak in model flops is a sixth of the BF16 one
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 6}
 
 
 def source_hash():
@@ -224,8 +226,9 @@ def precision_runs(P, mps, tol=1e-8, max_iter=60):
     psi0 = mps.psi()
     rows = {}
     for name, prec, refine in (("fp64", P.DMRG_FP64, 0.0), ("fp32_refined", P.DMRG_FP32, 1e-4),
-                               ("bf16_refined", P.DMRG_BF16, 1e-4), ("fp32_only", P.DMRG_FP32, 0.0),
-                               ("bf16_only", P.DMRG_BF16, 0.0)):
+                               ("bf16_refined", P.DMRG_BF16, 1e-4), ("bf16x3_refined", P.DMRG_BF16X3, 1e-4),
+                               ("fp32_only", P.DMRG_FP32, 0.0), ("bf16_only", P.DMRG_BF16, 0.0),
+                               ("bf16x3_only", P.DMRG_BF16X3, 0.0)):
         mps.set_psi(psi0)
         o = P.default_opts(prec=prec, dav_tol=tol, dav_max_iter=max_iter, refine_tol=refine)
         t0 = time.time()
@@ -264,7 +267,7 @@ def precision_sweeps(args, P, torch, mps, mpo, M, pre_e):
     mps.save(path)
     runs = {}
     for name, prec, refine in (("fp64", P.DMRG_FP64, 0.0), ("fp32_refined", P.DMRG_FP32, 1e-4),
-                               ("bf16_refined", P.DMRG_BF16, 1e-4)):
+                               ("bf16_refined", P.DMRG_BF16, 1e-4), ("bf16x3_refined", P.DMRG_BF16X3, 1e-4)):
         m = P.Mps.load(mps.ctx, mpo, path)
         o = P.default_opts(prec=prec, dav_tol=args.conv_tol, dav_max_iter=args.conv_iter, refine_tol=refine)
         rows = []
@@ -370,7 +373,7 @@ def learned(args, P, torch):
     n_col, n_cmp = int(n_col), int(n_cmp)
     c = WORKLOADS[name]
     K, M = c["K"], c["M"]
-    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
+    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16, "bf16x3": P.DMRG_BF16X3}[args.prec]
     ctx = P.Context(0)
     I = workload_integrals(name)
     mpo = P.Mpo(ctx, I.h, I.v, I.n_elec, I.two_sz)
@@ -428,7 +431,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"])
     ap.add_argument("--dav-tol", type=float, default=1e-7)
     ap.add_argument("--dav-iter", type=int, default=24)
     ap.add_argument("--no-sweep", action="store_true",
@@ -486,7 +489,7 @@ def main():
     import paper_1605_02611_amd as P
     from workloads import WORKLOADS, workload_integrals, mps_values
 
-    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16}[args.prec]
+    prec = {"fp64": P.DMRG_FP64, "fp32": P.DMRG_FP32, "bf16": P.DMRG_BF16, "bf16x3": P.DMRG_BF16X3}[args.prec]
     if args.calib:
         src = torch.ones(32 << 20, device="cuda", dtype=torch.float64)  # 256 MiB
         dst = torch.empty_like(src)
@@ -557,6 +560,7 @@ def main():
                  "runs": rows,
                  "fp32_refined_within_1e-5": rows["fp32_refined"]["abs_dtheta_vs_fp64"] <= 1e-5,
                  "bf16_refined_within_1e-5": rows["bf16_refined"]["abs_dtheta_vs_fp64"] <= 1e-5,
+                 "bf16x3_refined_within_1e-5": rows["bf16x3_refined"]["abs_dtheta_vs_fp64"] <= 1e-5,
                  "seconds": time.time() - t3}
     tuned = None
     if args.autotune:
@@ -607,7 +611,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc", "bf16x3": "bf16x3-in/f32-acc"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "chain molecule K=36 N=36 2Sz=0 M=1024 (integral seed 1003), "
                                "two-site steps at the middle bond after %d sweeps from the random state%s" % (

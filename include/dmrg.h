@@ -71,7 +71,11 @@ typedef enum {
 typedef enum {
     DMRG_FP64 = 0,  /* contractions in FP64 */
     DMRG_FP32 = 1,  /* contractions in FP32 (FP32 accumulation) */
-    DMRG_BF16 = 2   /* contraction inputs rounded to BF16, FP32 accumulation */
+    DMRG_BF16 = 2,  /* contraction inputs rounded to BF16, FP32 accumulation */
+    DMRG_BF16X3 = 3 /* each FP32 input split into three BF16 parts x = h + m + l and
+                       the six products hh, hm, mh, mm, hl, lh summed on BF16 matrix
+                       cores with FP32 accumulation: FP32-like products (the bf16x3
+                       split of Henry, Tang and Heinecke, ARITH 2019) */
 } dmrg_prec;
 
 typedef struct dmrg_ctx dmrg_ctx;

@@ -17,7 +17,7 @@ c_int, c_int32, c_int64, c_double, c_void_p, c_char_p = (
     C.c_int, C.c_int32, C.c_int64, C.c_double, C.c_void_p, C.c_char_p)
 P = C.POINTER
 
-DMRG_FP64, DMRG_FP32, DMRG_BF16 = 0, 1, 2
+DMRG_FP64, DMRG_FP32, DMRG_BF16, DMRG_BF16X3 = 0, 1, 2, 3
 STATUS = {0: "DMRG_OK", 1: "DMRG_E_INVAL", 2: "DMRG_E_NOMEM", 3: "DMRG_E_HIP",
           4: "DMRG_E_NOCONV", 5: "DMRG_E_NUMERIC", 6: "DMRG_E_STATE", 7: "DMRG_E_IO"}
 

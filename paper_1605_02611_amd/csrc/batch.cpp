@@ -316,7 +316,7 @@ void sweep_batched(Ctx* ctx, std::vector<State*>& st, const std::vector<int>& M,
                 std::vector<char> live(na, 1);
                 int nlive = na;
                 while (nlive > 0) {
-                    for (Prec p : {Prec::F64, Prec::F32, Prec::BF16}) {
+                    for (Prec p : {Prec::F64, Prec::F32, Prec::BF16, Prec::BF16X3}) {
                         std::vector<char> on(na, 0);
                         bool any = false;
                         for (int a = 0; a < na; ++a)

@@ -61,7 +61,7 @@ dmrg_status guard(dmrg_ctx* ctx, F&& f) {
 SweepOpts to_opts(const dmrg_sweep_opts* o) {
     SweepOpts r;
     if (!o) return r;
-    require(o->prec >= DMRG_FP64 && o->prec <= DMRG_BF16, "unknown precision");
+    require(o->prec >= DMRG_FP64 && o->prec <= DMRG_BF16X3, "unknown precision");
     require(o->dav_tol > 0 && o->dav_max_iter >= 1 && o->dav_max_space >= 2 &&
                 o->dav_max_space <= 40 && o->dav_keep >= 1 && o->dav_keep < o->dav_max_space,
             "invalid Davidson options");
@@ -678,7 +678,7 @@ dmrg_status dmrg_sigma(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, const 
     return guard(ctx, [&] {
         require(mps && mpo && psi && out, "null argument");
         require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
-        require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16X3, "unknown precision");
         const int64_t n = mps->st->ts.n;
         require(psi + n <= out || out + n <= psi, "psi and out overlap");
         use_device(ctx->c);
@@ -763,7 +763,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
         require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
         require(tile == 64 || tile == 32 || tile == 128 || tile == 256, "tile must be 32, 64, 128 or 256");
         require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
-        require(prec >= DMRG_FP64 && prec <= DMRG_BF16, "unknown precision");
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16X3, "unknown precision");
         use_device(ctx->c);
         hipStream_t s = ctx->c.stream;
         const int64_t na = ta ? int64_t(k - 1) * lda + m : int64_t(m - 1) * lda + k;
@@ -953,7 +953,7 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
     return guard(ctx, [&] {
         require(mps && mpo, "null argument");
         require(mps->st->mpo == mpo->m.get(), "state was built with another MPO", E_STATE);
-        require(prec >= DMRG_FP64 && prec <= DMRG_BF16 && reps >= 1, "bad autotune arguments");
+        require(prec >= DMRG_FP64 && prec <= DMRG_BF16X3 && reps >= 1, "bad autotune arguments");
         use_device(ctx->c);
         State& st = *mps->st;
         hipStream_t s = ctx->c.stream;

@@ -196,7 +196,7 @@ struct Bases {
     void* p[kMaxBufs];
 };
 
-enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
 
 // bases: DEVICE array of buffer base pointers indexed by the buffer ids of
 // the tasks and terms; active: DEVICE flags per instance or nullptr

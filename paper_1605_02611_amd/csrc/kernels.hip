@@ -33,6 +33,38 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
     return uint16_t(u >> 16);
 }
 
+// BF16 parts of four FP32 values: NP = 1 rounds each value to BF16; NP = 3
+// writes x = h + m + l (each part the BF16 rounding of what the previous
+// parts leave; the residuals are exact in FP32)
+template <int NP>
+__device__ inline void bf16_parts(float x0, float x1, float x2, float x3, shrt4 (&p)[NP]) {
+    float x[4] = {x0, x1, x2, x3};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float r = x[e];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const uint16_t h = f32_to_bf16_rne(r);
+            p[k][e] = short(h);
+            r -= __uint_as_float(uint32_t(h) << 16);
+        }
+    }
+}
+// BF16 MFMA of one 16x16x16 sub-tile: NP = 1 one product; NP = 3 the six
+// products h h, h m, m h, m m, h l, l h (the smallest first), FP32-like
+// accuracy from BF16 matrix cores
+template <int NP>
+__device__ inline flt4 bf16_mfma(const shrt4 (&a)[NP], const shrt4 (&b)[NP], flt4 acc) {
+    if constexpr (NP == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], acc, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], acc, 0, 0, 0);
+}
+
 // Element load helpers for term operands, zero outside the slice.
 template <class T>
 __device__ inline T ld(const T* base, int64_t idx) {
@@ -60,6 +92,17 @@ struct Cfg<2> {
     using T = float;
     using Acc = flt4;
 };
+// MODE 3: FP32 storage, operands split into three BF16 parts, six BF16 MFMAs
+// per product (bf16x3), FP32 accumulation
+template <>
+struct Cfg<3> {
+    using T = float;
+    using Acc = flt4;
+};
+template <int MODE>
+constexpr int bf16_np() {
+    return MODE == 3 ? 3 : 1;
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
 // b % 8), and each XCD has its own L2.  Give XCD x a contiguous run of the
@@ -165,16 +208,17 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
                 if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
             }
         } else {
-            shrt4 a[2], b[2];
-            for (int i = 0; i < 2; ++i)
-                for (int e = 0; e < 4; ++e) {
-                    a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
-                    b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
-                }
+            constexpr int NP = bf16_np<MODE>();
+            shrt4 a[2][NP], b[2][NP];
+            for (int i = 0; i < 2; ++i) {
+                bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
+                               As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
+                bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
+                               Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
+            }
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j)
-                    if (act[i][j])
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
         }
     };
 
@@ -356,16 +400,17 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
                 }
             } else {
                 // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
-                shrt4 a[2], b[2];
-                for (int i = 0; i < 2; ++i)
-                    for (int e = 0; e < 4; ++e) {
-                        a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
-                        b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
-                    }
+                constexpr int NP = bf16_np<MODE>();
+                shrt4 a[2][NP], b[2][NP];
+                for (int i = 0; i < 2; ++i) {
+                    bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
+                                   As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
+                    bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
+                                   Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
+                }
                 for (int i = 0; i < 2; ++i)
                     for (int j = 0; j < 2; ++j)
-                        if (act[i][j])
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                        if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
             }
             __syncthreads();
         }
@@ -433,16 +478,17 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
                     }
                 } else {
                     // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
-                    shrt4 a[2], b[2];
-                    for (int i = 0; i < 2; ++i)
-                        for (int e = 0; e < 4; ++e) {
-                            a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
-                            b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
-                        }
+                    constexpr int NP = bf16_np<MODE>();
+                    shrt4 a[2][NP], b[2][NP];
+                    for (int i = 0; i < 2; ++i) {
+                        bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
+                                       As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
+                        bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
+                                       Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
+                    }
                     for (int i = 0; i < 2; ++i)
                         for (int j = 0; j < 2; ++j)
-                            if (act[i][j])
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                            if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
                 }
                 __syncthreads();
             }
@@ -536,25 +582,27 @@ __global__ __launch_bounds__(256, TM * TN <= 64 * 128 ? 4 : 2) void wide_gemm(co
             }
         } else {
             // one 16x16x16 BF16 MFMA per tile and 16 K: lane holds k = 4 lk .. 4 lk + 3
+            constexpr int NP = bf16_np<MODE>();
             for (int k16 = 0; k16 < kv; k16 += 16) {
-                shrt4 a[MS], b[NS];
+                shrt4 a[MS][NP], b[NS][NP];
+                const int k4 = k16 + 4 * lk;
 #pragma unroll
                 for (int i = 0; i < MS; ++i)
+                    bf16_parts<NP>(As[k4][16 * i + lr], As[k4 + 1][16 * i + lr], As[k4 + 2][16 * i + lr],
+                                   As[k4 + 3][16 * i + lr], a[i]);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        a[i][e] = short(f32_to_bf16_rne(As[k16 + 4 * lk + e][16 * i + lr]));
-#pragma unroll
-                for (int j = 0; j < NS; ++j)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        b[j][e] = any_col[j] ? short(f32_to_bf16_rne(Bs[k16 + 4 * lk + e][16 * (wave + 4 * j) + lr]))
-                                             : short(0);
+                for (int j = 0; j < NS; ++j) {
+                    const int c = 16 * (wave + 4 * j) + lr;
+                    if (any_col[j])
+                        bf16_parts<NP>(Bs[k4][c], Bs[k4 + 1][c], Bs[k4 + 2][c], Bs[k4 + 3][c], b[j]);
+                    else
+                        bf16_parts<NP>(0.f, 0.f, 0.f, 0.f, b[j]);
+                }
 #pragma unroll
                 for (int i = 0; i < MS; ++i)
 #pragma unroll
                     for (int j = 0; j < NS; ++j)
-                        if (act[i][j])
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                        if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
             }
         }
     };
@@ -814,16 +862,17 @@ __global__ __launch_bounds__(256) void persistent_gemm(const GemmTask* __restric
                 if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
             }
         } else {
-            shrt4 a[2], b[2];
-            for (int i = 0; i < 2; ++i)
-                for (int e = 0; e < 4; ++e) {
-                    a[i][e] = short(f32_to_bf16_rne(As[4 * lk + e][wm + 16 * i + lr]));
-                    b[i][e] = short(f32_to_bf16_rne(Bs[4 * lk + e][wn + 16 * i + lr]));
-                }
+            constexpr int NP = bf16_np<MODE>();
+            shrt4 a[2][NP], b[2][NP];
+            for (int i = 0; i < 2; ++i) {
+                bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
+                               As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
+                bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
+                               Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
+            }
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j)
-                    if (act[i][j])
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
         if (!task_end) {
@@ -884,26 +933,28 @@ __global__ __launch_bounds__(256) void wave_gemm(const GemmTask* __restrict__ ta
         const int64_t sar = ta ? 1 : g.lda, sak = ta ? g.lda : 1;  // A[r][k] = A[r*sar + k*sak]
         const int64_t sbc = tb ? g.ldb : 1, sbk = tb ? 1 : g.ldb;  // B[k][c] = B[c*sbc + k*sbk]
         const T alpha = T(g.alpha);
-        if constexpr (MODE == 2) {
+        if constexpr (MODE >= 2) {
             // BF16: each lane holds 4 consecutive K values of a 16-wide step
+            constexpr int NP = bf16_np<MODE>();
             for (int k0 = 0; k0 < g.k; k0 += 16) {
-                shrt4 a[2], b[2];
+                T va[2][4], vb[2][4];
                 for (int e = 0; e < 4; ++e) {
                     const int kk = k0 + 4 * lk + e;
                     const bool kin = kk < g.k;
-                    const T a0 = (kin && ra < task.m) ? A[ra * sar + kk * sak] * alpha : T(0);
-                    const T a1 = (kin && r1 && rb < task.m) ? A[rb * sar + kk * sak] * alpha : T(0);
-                    const T b0 = (kin && ra < task.n) ? B[ra * sbc + kk * sbk] : T(0);
-                    const T b1 = (kin && c1 && rb < task.n) ? B[rb * sbc + kk * sbk] : T(0);
-                    a[0][e] = short(f32_to_bf16_rne(a0));
-                    a[1][e] = short(f32_to_bf16_rne(a1));
-                    b[0][e] = short(f32_to_bf16_rne(b0));
-                    b[1][e] = short(f32_to_bf16_rne(b1));
+                    va[0][e] = (kin && ra < task.m) ? A[ra * sar + kk * sak] * alpha : T(0);
+                    va[1][e] = (kin && r1 && rb < task.m) ? A[rb * sar + kk * sak] * alpha : T(0);
+                    vb[0][e] = (kin && ra < task.n) ? B[ra * sbc + kk * sbk] : T(0);
+                    vb[1][e] = (kin && c1 && rb < task.n) ? B[rb * sbc + kk * sbk] : T(0);
                 }
-                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], acc[0][0], 0, 0, 0);
-                if (c1) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], acc[0][1], 0, 0, 0);
-                if (r1) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], acc[1][0], 0, 0, 0);
-                if (r1 && c1) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[1], acc[1][1], 0, 0, 0);
+                shrt4 a[2][NP], b[2][NP];
+                for (int i = 0; i < 2; ++i) {
+                    bf16_parts<NP>(va[i][0], va[i][1], va[i][2], va[i][3], a[i]);
+                    bf16_parts<NP>(vb[i][0], vb[i][1], vb[i][2], vb[i][3], b[i]);
+                }
+                acc[0][0] = bf16_mfma<NP>(a[0], b[0], acc[0][0]);
+                if (c1) acc[0][1] = bf16_mfma<NP>(a[0], b[1], acc[0][1]);
+                if (r1) acc[1][0] = bf16_mfma<NP>(a[1], b[0], acc[1][0]);
+                if (r1 && c1) acc[1][1] = bf16_mfma<NP>(a[1], b[1], acc[1][1]);
             }
         } else {
             constexpr int U = 4;  // 4-wide K steps per batch of loads
@@ -1391,6 +1442,9 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
             case Prec::BF16:
                 hipLaunchKernelGGL((grouped_gemm<2, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
+            case Prec::BF16X3:
+                hipLaunchKernelGGL((grouped_gemm<3, ROLE, TS, VAR>), dim3(g), dim3(NT), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
         }
     }
 }
@@ -1412,6 +1466,9 @@ static void launch_wide(Prec p, const GemmTask* tasks, int64_t n_tasks, const Ge
                 break;
             case Prec::BF16:
                 hipLaunchKernelGGL((wide_gemm<2, ROLE, TM, TN>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::BF16X3:
+                hipLaunchKernelGGL((wide_gemm<3, ROLE, TM, TN>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
         }
     }
@@ -1480,6 +1537,11 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
                     hipLaunchKernelGGL((persistent_gemm<2, ROLE>), dim3(grid(fn)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
                     break;
                 }
+                case Prec::BF16X3: {
+                    const void* fn = reinterpret_cast<const void*>(&persistent_gemm<3, ROLE>);
+                    hipLaunchKernelGGL((persistent_gemm<3, ROLE>), dim3(grid(fn)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                    break;
+                }
             }
         } else if (var == 1)
             launch_gemm_tile<ROLE, 64, 1>(p, tasks, n_tasks, terms, b, act, s, xcd);
@@ -1500,6 +1562,9 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
                 break;
             case Prec::BF16:
                 hipLaunchKernelGGL((wave_gemm<2, ROLE>), dim3(unsigned(g)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
+                break;
+            case Prec::BF16X3:
+                hipLaunchKernelGGL((wave_gemm<3, ROLE>), dim3(unsigned(g)), dim3(256), 0, s, tasks, n_tasks, terms, b, act);
                 break;
         }
     }

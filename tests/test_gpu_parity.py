@@ -57,7 +57,7 @@ def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
     Ch = rng.standard_normal((m, n + 1))
     opA = Ah[:, :m].T if ta else Ah[:, :k]
     opB = Bh[:, :k].T if tb else Bh[:, :n]
-    for prec, tol in [(P.DMRG_FP64, 1e-13), (P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2)]:
+    for prec, tol in [(P.DMRG_FP64, 1e-13), (P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2), (P.DMRG_BF16X3, 1e-5)]:
         for acc in (False, True):
             ref = 0.7 * opA @ opB + (Ch[:, :n] if acc else 0)
             Cd = _dev(Ch)
@@ -129,7 +129,7 @@ def test_environments_sigma_diag_match_oracle(ctx, K, N, tsz, M, centers, kind, 
         mps.sigma(xd, yd)
         y = yd.cpu().numpy()
         assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
-        for prec, tol in [(P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2)]:
+        for prec, tol in [(P.DMRG_FP32, 1e-5), (P.DMRG_BF16, 2e-2), (P.DMRG_BF16X3, 1e-5)]:
             yd.zero_()
             mps.sigma(xd, yd, prec)
             assert np.linalg.norm(yd.cpu().numpy() - ref) <= tol * np.linalg.norm(ref)
