@@ -367,10 +367,11 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
  * MPSCform) on n host matrices a (row-major rows[i] x cols[i],
  * concatenated; each dimension in [1, 8192], n in [1, 4096]).  path 0: the
  * library's choice (one-sided Jacobi up to 768 columns — one workgroup per
- * matrix below 160, all rounds of a sweep in one cooperative launch above —
- * rocSOLVER dgesvd beyond); 1: every matrix through rocSOLVER; 2: Jacobi
- * with one launch per round for the matrices of 160 columns or more; 3:
- * Jacobi with the cooperative launch.  Host outputs, r = min(rows, cols):
+ * matrix below 160, one launch per round above (all rounds of a sweep in
+ * one cooperative launch when DMRG_SVD_COOPERATIVE is set) — rocSOLVER
+ * dgesvd beyond); 1: every matrix through rocSOLVER; 2: Jacobi with one
+ * launch per round for the matrices of 160 columns or more; 3: Jacobi with
+ * the cooperative launch.  Host outputs, r = min(rows, cols):
  * S (r per matrix, descending), U (rows x r), Vt (r x cols), concatenated. */
 dmrg_status dmrg_debug_svd(dmrg_ctx* ctx, int n, const int32_t* rows, const int32_t* cols,
                            const double* a, double* S, double* U, double* Vt, int path);

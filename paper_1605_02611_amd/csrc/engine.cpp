@@ -955,12 +955,12 @@ struct SideJoin {
 };
 
 // jacobi_max: sectors with min(rows, cols) above it go to rocSOLVER (-1:
-// 768, or 0 when DMRG_SVD_ROCSOLVER is set); round_launches: the large-
-// sector Jacobi path launches one kernel per round instead of one
-// cooperative kernel per sweep
+// 768, or 0 when DMRG_SVD_ROCSOLVER is set); cooperative: the large-sector
+// Jacobi path runs each sweep's rounds in one cooperative launch (1) or one
+// launch per round (0); -1: the process default (DMRG_SVD_COOPERATIVE)
 static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::pair<int, int>>>& mats,
                       std::vector<SvdOut>& outs, DevBuf& work, DevBuf& info, int jacobi_max = -1,
-                      bool round_launches = false) {
+                      int cooperative = -1) {
     hipStream_t s = ctx->stream;
     outs.clear();
     int64_t tot = 0;
@@ -987,6 +987,10 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
     // small sectors: batched one-sided Jacobi kernel; large ones: rocSOLVER
     static const int jdefault = std::getenv("DMRG_SVD_ROCSOLVER") ? 0 : 768;
     const int jmax = jacobi_max >= 0 ? jacobi_max : jdefault;
+    // the cooperative sweep kernel is used when DMRG_SVD_COOPERATIVE is set
+    // (or asked for by the test hook); by default one launch per round
+    static const bool coop_default = std::getenv("DMRG_SVD_COOPERATIVE") != nullptr;
+    if (cooperative < 0) cooperative = coop_default ? 1 : 0;
     std::vector<char> jac(mats.size(), 0);
     std::vector<SvdJob> jobs;
     int64_t jtot = 0;
@@ -1058,8 +1062,8 @@ static void svd_batch(Ctx* ctx, const std::vector<std::pair<const double*, std::
             for (int sw = 0; sw < 60 && left > 0; ++sw) {
                 DMRG_HIP(hipMemcpyAsync(dlive.p, live.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
                 DMRG_HIP(hipMemsetAsync(drot.p, 0, nb * sizeof(int), s));
-                if (round_launches || !launch_jacobi_sweep(big, dslots.as<int2>(), int64_t(slots.size()), rounds,
-                                                           dlive.as<int>(), drot.as<int>(), s))
+                if (!cooperative || !launch_jacobi_sweep(big, dslots.as<int2>(), int64_t(slots.size()), rounds,
+                                                         dlive.as<int>(), drot.as<int>(), s))
                     for (int rd = 0; rd < rounds; ++rd)
                         launch_jacobi_round(big, dslots.as<int2>(), int64_t(slots.size()), rd, dlive.as<int>(),
                                             drot.as<int>(), s);
@@ -2651,7 +2655,8 @@ void debug_svd(Ctx* ctx, int n, const int32_t* rows, const int32_t* cols, const 
     }
     std::vector<SvdOut> outs;
     DevBuf work, info;
-    svd_batch(ctx, mats, outs, work, info, path == 1 ? 0 : (path >= 2 ? 8192 : -1), path == 2);
+    svd_batch(ctx, mats, outs, work, info, path == 1 ? 0 : (path >= 2 ? 8192 : -1),
+              path == 2 ? 0 : (path == 3 ? 1 : -1));
     int64_t us = 0, ss = 0, vs = 0;
     for (const SvdOut& o : outs) {
         DMRG_HIP(hipMemcpyAsync(U + us, work.as<double>() + o.u_off, sizeof(double) * o.rows * o.r,
