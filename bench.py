@@ -629,7 +629,7 @@ def main():
                      "unit": "TFLOP/s", "frac": gemm_tflops / PEAK[args.prec],
                      "traffic": (None if args.compress else
                                  recorded_traffic(args.prec, args.presweeps + (sweep is not None))),
-                     "kernel": "grouped_gemm<%d,1>" % prec,
+                     "kernel": "lean_gemm<%d,1,*> (both sigma passes)" % prec,
                      "avg_launch_ms": tot["gemm"] / max(1, tot["launches"]) * 1e3,
                      "model_flops_per_launch": tot["flops"] / max(1, tot["launches"])},
         "sweep_seconds": sweep["seconds"] if sweep else None,

@@ -757,11 +757,12 @@ dmrg_status dmrg_debug_svd(dmrg_ctx* ctx, int n, const int32_t* rows, const int3
 
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
-                            double* C, int ldc, int accumulate, int tile) {
+                            double* C, int ldc, int accumulate, int tile, int variant) {
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
         require(tile == 64 || tile == 32 || tile == 128 || tile == 256, "tile must be 32, 64, 128 or 256");
+        require(variant >= -1 && variant <= 4, "unknown grouped-GEMM variant");
         require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
         require(prec >= DMRG_FP64 && prec <= DMRG_BF16X3, "unknown precision");
         use_device(ctx->c);
@@ -772,6 +773,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
         GemmList L;
         L.tile = tile > 64 ? 64 : tile;
         L.tile_n = tile > 64 ? tile : 0;
+        L.variant = variant;
         std::vector<UTerm> terms = {{0, 0, lda, ta != 0, 1, 0, ldb, tb != 0, k, alpha, true}};
         add_unit(L, 2, 0, ldc, m, n, accumulate ? 1 : 0, terms);
         int64_t sz[kMaxBufs] = {na, nb, nc};
@@ -966,9 +968,14 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
                     c.tile1 = t1;
                     c.tile2 = t2;
                     c.pieces = pc;
-                    c.variant = t1 == 32 && t2 == 32 ? 0 : 2;
+                    c.variant = t1 == 32 && t2 == 32 ? 0 : 4;
                     cand.push_back(c);
                 }
+        {
+            SigmaConfig c;  // the generic software pipeline
+            c.variant = 2;
+            cand.push_back(c);
+        }
         // sector-major pass-1 order and aligned pass-2 pieces
         for (int o1 : {0, 1})
             for (int o2 : {0, 1}) {
@@ -976,7 +983,7 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
                 SigmaConfig c;
                 c.order1 = o1;
                 c.order2 = o2;
-                c.variant = 2;
+                c.variant = 4;
                 cand.push_back(c);
             }
         // 64 x 128 tiles in pass 1; 64 x 128 / 128 x 64 / 128 x 128 tiles in pass 2

@@ -201,16 +201,19 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
 // bases: DEVICE array of buffer base pointers indexed by the buffer ids of
 // the tasks and terms; active: DEVICE flags per instance or nullptr
 // tile: output tile edge of every task (64 or 32); variant (tile 64): 0
-// plain, 1 packed K-steps, 2 software pipeline, 3 persistent pipeline, -1
-// the process default (2, or DMRG_GEMM_VARIANT); tile_n > 0 (128 or 256):
-// tiles of 64 rows and tile_n columns (wide_gemm) instead of square ones
+// plain, 1 packed K-steps, 2 software pipeline, 3 persistent pipeline, 4
+// lean pipeline (lists whose terms share one operand layout, uflags >= 0;
+// variant 2 otherwise), -1 the process default (DMRG_GEMM_VARIANT, else 4);
+// tile_n > 0 (128 or 256): tiles of 64 rows and tile_n columns (wide_gemm)
+// instead of square ones; uflags: the GT_TA / GT_TB flags every term
+// shares, -1 if they differ
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                  void* const* bases, const int* active, hipStream_t s, int tile = kTile, int variant = -1,
-                 int tile_n = 0);
+                 int tile_n = 0, int uflags = -1);
 // same kernel, separate symbol for the two passes of the sigma vector
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
                        void* const* bases, const int* active, hipStream_t s, int tile = kTile,
-                       int variant = -1, int tile_n = 0);
+                       int variant = -1, int tile_n = 0, int uflags = -1);
 
 // Launch configuration of the two sigma passes (chosen by the autotuner).
 struct SigmaConfig {

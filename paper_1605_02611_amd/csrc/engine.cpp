@@ -146,6 +146,19 @@ void add_unit(GemmList& L, int c_buf, int64_t c_off, int ldc, int m, int n, int 
 }
 
 void GemmList::upload(hipStream_t s) {
+    uflags = terms.empty() ? 0 : terms[0].flags;
+    constexpr int64_t kLeanExtent = int64_t(1) << 29;
+    for (const GemmTask& t : tasks) {
+        for (int l = t.l_begin; l < t.l_end && uflags >= 0; ++l) {
+            const GemmTerm& g = terms[l];
+            const int64_t ea = (g.flags & GT_TA) ? int64_t(g.k - 1) * g.lda + t.m : int64_t(t.m - 1) * g.lda + g.k;
+            const int64_t eb = (g.flags & GT_TB) ? int64_t(t.n - 1) * g.ldb + g.k : int64_t(g.k - 1) * g.ldb + t.n;
+            if (g.flags != uflags || ea >= kLeanExtent || eb >= kLeanExtent || g.lda >= (1 << 24) ||
+                g.ldb >= (1 << 24) || g.k >= (1 << 24))
+                uflags = -1;
+        }
+        if (uflags < 0) break;
+    }
     dtasks.alloc(std::max<size_t>(1, tasks.size()) * sizeof(GemmTask), s);
     dterms.alloc(std::max<size_t>(1, terms.size()) * sizeof(GemmTerm), s);
     if (!tasks.empty())
@@ -166,10 +179,10 @@ void GemmList::launch(Prec p, const Bases& b, hipStream_t s) {
 void GemmList::launch_dev(Prec p, void* const* dev_bases, const int* active, hipStream_t s) const {
     if (sigma_role)
         launch_gemm_sigma(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                          dev_bases, active, s, tile, variant, tile_n);
+                          dev_bases, active, s, tile, variant, tile_n, uflags);
     else
         launch_gemm(p, dtasks.as<GemmTask>(), int64_t(tasks.size()), dterms.as<GemmTerm>(),
-                    dev_bases, active, s, tile, variant, tile_n);
+                    dev_bases, active, s, tile, variant, tile_n, uflags);
 }
 
 void validate_list(const GemmList& L, const int64_t* sizes) {
@@ -2430,7 +2443,7 @@ void tune_load(const std::string& js) {
                 break;
             }
             require((c.tile1 == 32 || c.tile1 == 64 || c.tile1 == 128) && (c.tile2 == 32 || c.tile2 == 64 || c.tile2 == 128) && c.pieces >= 256 &&
-                        c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 3 &&
+                        c.pieces <= 1e7 && c.variant >= -1 && c.variant <= 4 &&
                         (c.wide1 == 0 || c.wide1 == 128 || c.wide1 == 256) &&
                         (c.wide2 == 0 || (c.rows2 == 64 && (c.wide2 == 128 || c.wide2 == 256)) ||
                          (c.rows2 == 128 && (c.wide2 == 64 || c.wide2 == 128))) &&

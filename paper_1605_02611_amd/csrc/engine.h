@@ -145,6 +145,10 @@ struct GemmList {
     int tile = kTile;         // output tile edge of the tasks (64 or 32)
     int tile_n = 0;           // > 0: tiles of `tile` rows and tile_n columns
     int variant = -1;         // grouped-GEMM variant (-1: process default)
+    // operand layout flags shared by every term (set by upload: -1 when the
+    // terms differ or a slice spans 2^29 elements or more, which the lean
+    // kernel's 32-bit offsets do not address)
+    int uflags = -1;
     DevBuf dbases;            // device copy of the buffer table
     Bases hbases{};           // host copy (kept alive for the async upload)
     void upload(hipStream_t s);

@@ -71,6 +71,30 @@ __device__ inline T ld(const T* base, int64_t idx) {
     return base[idx];
 }
 
+// Operand and result buffers are device global memory, but the pointers
+// read from the kernels' buffer tables are generic, and generic accesses
+// compile to FLAT instructions.  A FLAT load counts against the LDS wait
+// counter as well, so a wait for the LDS reads of the MFMA operands would
+// also wait for the operand prefetch meant to be in flight meanwhile.  These
+// casts make the accesses global loads and stores.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ inline const gmem<T>* gin(const void* p) {
+    return (const gmem<T>*)p;
+}
+template <class T>
+__device__ inline gmem<T>* gout(void* p) {
+    return (gmem<T>*)p;
+}
+// Element e of a term slice: a wave-uniform base (scalar registers) plus a
+// 32-bit byte offset per lane (the host keeps every slice below 2^32 bytes),
+// one address register per load.
+template <class T>
+__device__ inline T gld(const gmem<T>* base, uint32_t e) {
+    return *(const gmem<T>*)((const gmem<char>*)base + e * uint32_t(sizeof(T)));
+}
+
 // LDS tile holder per compute type.
 template <int MODE>
 struct Cfg;
@@ -505,6 +529,189 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
                 const int c = wn + 16 * j + lr;
                 if (r < task.m && c < task.n) {
                     T* p = C + int64_t(r) * task.ldc + c;
+                    T v = T(acc[i][j][e]);
+                    *p = task.accumulate ? *p + v : v;
+                }
+            }
+}
+
+// Lean 64x64 tile kernel for lists whose terms all share one operand layout
+// (TA: A stored transposed, TB: B stored transposed, fixed at compile time).
+// The same staging as grouped_gemm VAR 2 (K-steps of KS through LDS, the next
+// step's operands loaded into registers during the current step's MFMAs),
+// written for few instructions per MFMA: every lane loads (elements outside
+// the slice read the slice's nearest element and are zeroed at the store, so
+// no branch waits on a load), global loads from a wave-uniform base with one
+// 32-bit offset register, per-thread row clamps fixed per task, wave-uniform
+// sub-tile flags, and whole K-steps of fully active waves as straight-line
+// MFMAs.  Thread tid stages, per K-step, four elements of A and four of B:
+//   A, TA false: rows (tid >> 4) + 16 i, column tid & 15 of the step
+//   A, TA true:  row tid & 63, columns (tid >> 6) + 4 i
+//   B, TB true:  columns (tid >> 4) + 16 i, row tid & 15 of the step
+//   B, TB false: column tid & 63, rows (tid >> 6) + 4 i
+template <int MODE>
+__device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_pitch<MODE>(64)],
+                                      const typename Cfg<MODE>::T (&Bs)[KS][lds_pitch<MODE>(64)],
+                                      typename Cfg<MODE>::Acc (&acc)[2][2], int kv, const bool (&act)[2][2],
+                                      int wm, int wn, int lr, int lk) {
+    if constexpr (MODE == 0) {
+        for (int ks = 0; ks < kv; ks += 4) {
+            const double a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
+            const double b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
+            if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    } else if constexpr (MODE == 1) {
+        for (int ks = 0; ks < kv; ks += 4) {
+            const float a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
+            const float b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
+            if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    } else {
+        // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
+        constexpr int NP = bf16_np<MODE>();
+        shrt4 a[2][NP], b[2][NP];
+        for (int i = 0; i < 2; ++i) {
+            bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
+                           As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
+            bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
+                           Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
+        }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
+    }
+}
+
+#ifndef LEAN_WAVES
+#define LEAN_WAVES 6
+#endif
+template <int MODE, int ROLE, bool TA, bool TB>
+__global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __restrict__ tasks, const GemmTerm* __restrict__ terms,
+                                                     void* const* __restrict__ bases, const int* __restrict__ active,
+                                                     int xcd, int64_t n_tasks) {
+    using T = typename Cfg<MODE>::T;
+    using Acc = typename Cfg<MODE>::Acc;
+    constexpr int TS = 64, P = lds_pitch<MODE>(TS);
+    __shared__ T As[KS][P];
+    __shared__ T Bs[KS][P];
+
+    const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
+                       : xcd == 1 ? xcd_task(blockIdx.x, gridDim.x)
+                                  : xcd_chunk_task(blockIdx.x, xcd);
+    if (ti >= n_tasks) return;  // padding of the chunked grid (before any barrier)
+    const GemmTask task = tasks[ti];
+    if (active && !active[task.inst]) return;  // uniform per workgroup
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    Acc acc[2][2];
+    bool act[2][2];  // 16x16 sub-tile overlaps the task's m x n (uniform per wave)
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = Acc{0, 0, 0, 0};
+            act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
+        }
+
+    // Staging coordinates of this thread (see above).  Rows of A past the
+    // task's m and columns of B past its n are read clamped to the last one
+    // and left in the tile: they reach only outputs that are not written.
+    // Columns of the K-step past the term's K are clamped too, and zeroed in
+    // B, which is all the sum over the step needs.
+    const int a_r = TA ? (tid & 63) : (tid >> 4), a_k = TA ? (tid >> 6) : (tid & 15);
+    const int b_c = TB ? (tid >> 4) : (tid & 63), b_k = TB ? (tid & 15) : (tid >> 6);
+    const int m1 = task.m - 1, n1 = task.n - 1;
+
+    T ra[4], rb[4];
+    unsigned kmask = 0;  // bit i: rb[i] inside the term's K range
+    auto load = [&](const GemmTerm& t, int k0) {
+        const gmem<T>* A = gin<T>(bases[t.a_buf]) + t.a_off;
+        const gmem<T>* B = gin<T>(bases[t.b_buf]) + t.b_off;
+        const int km = t.k - 1 - k0;  // last K offset of the slice in this step (>= 0)
+        const uint32_t lda = uint32_t(t.lda), ldb = uint32_t(t.ldb);
+        if (!TA) {
+            const uint32_t kc = uint32_t(k0 + min(a_k, km));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = gld(A, __umul24(uint32_t(min(a_r + 16 * i, m1)), lda) + kc);
+        } else {
+            const uint32_t rc = uint32_t(min(a_r, m1));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra[i] = gld(A, __umul24(uint32_t(k0 + min(a_k + 4 * i, km)), lda) + rc);
+        }
+        if (TB) {
+            const uint32_t kc = uint32_t(k0 + min(b_k, km));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rb[i] = gld(B, __umul24(uint32_t(min(b_c + 16 * i, n1)), ldb) + kc);
+            kmask = b_k <= km ? 0xfu : 0u;
+        } else {
+            const uint32_t cc = uint32_t(min(b_c, n1));
+            unsigned m = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                rb[i] = gld(B, __umul24(uint32_t(k0 + min(b_k + 4 * i, km)), ldb) + cc);
+                m |= unsigned(b_k + 4 * i <= km) << i;
+            }
+            kmask = m;
+        }
+    };
+    auto store = [&](const GemmTerm& t) {
+        const T alpha = T(t.alpha);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T vb = (kmask >> i) & 1u ? rb[i] * alpha : T(0);
+            if (TA) As[a_k + 4 * i][a_r] = ra[i];
+            else As[a_k][a_r + 16 * i] = ra[i];
+            if (TB) Bs[b_k][b_c + 16 * i] = vb;
+            else Bs[b_k + 4 * i][b_c] = vb;
+        }
+    };
+
+    int l = task.l_begin, k0 = 0;
+    if (l < task.l_end) {
+        GemmTerm g = terms[l], gn = g;
+        if (l + 1 < task.l_end) gn = terms[l + 1];
+        load(g, 0);
+        while (true) {
+            store(g);
+            __syncthreads();
+            const int kv = min(KS, g.k - k0);
+            int nk = k0 + KS;
+            bool more = true;
+            if (nk >= g.k) {
+                nk = 0;
+                ++l;
+                if (l < task.l_end) {
+                    g = gn;
+                    if (l + 1 < task.l_end) gn = terms[l + 1];
+                } else {
+                    more = false;
+                }
+            }
+            if (more) load(g, nk);  // in flight during the MFMAs
+            tile_mfma_step<MODE>(As, Bs, acc, kv, act, wm, wn, lr, lk);
+            __syncthreads();
+            if (!more) break;
+            k0 = nk;
+        }
+    }
+    // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds
+    // row 4 lk + e for the FP32 MFMAs but row 4 e + lk for the FP64 MFMA
+    gmem<T>* C = gout<T>(bases[task.c_buf]) + task.c_off;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int r = wm + 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
+                const int c = wn + 16 * j + lr;
+                if (r < task.m && c < task.n) {
+                    gmem<T>* p = C + int64_t(r) * task.ldc + c;
                     T v = T(acc[i][j][e]);
                     *p = task.accumulate ? *p + v : v;
                 }
@@ -1415,7 +1622,8 @@ inline unsigned grid_for(int64_t n, int block = 256, int cap = 8192) {
 
 // Kernel variant switches (environment, read once): DMRG_GEMM_VARIANT
 // (0 plain, 1 packed K-steps, 2 software pipeline, 3 persistent software
-// pipeline) and DMRG_GEMM_XCD, the task order over the XCDs (0 block order,
+// pipeline, 4 lean software pipeline for lists of one operand layout, 2 for
+// the others; default 4) and DMRG_GEMM_XCD, the task order over the XCDs (0 block order,
 // 1 one contiguous run per XCD, c > 1 runs of c consecutive tasks per XCD:
 // the tiles of one operand panel then share an L2; default 4).
 static int gemm_env(const char* name, int dflt) {
@@ -1449,6 +1657,31 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     }
 }
 
+template <int ROLE, bool TA, bool TB>
+static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
+                        const int* act, hipStream_t s, int xcd) {
+    const int64_t kMaxGrid = 1 << 30;
+    for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
+        const int64_t nt = std::min<int64_t>(kMaxGrid, n_tasks - off);
+        const int64_t step = xcd > 1 ? 8 * int64_t(xcd) : 1;
+        const unsigned g = unsigned((nt + step - 1) / step * step);
+        switch (p) {
+            case Prec::F64:
+                hipLaunchKernelGGL((lean_gemm<0, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::F32:
+                hipLaunchKernelGGL((lean_gemm<1, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::BF16:
+                hipLaunchKernelGGL((lean_gemm<2, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+            case Prec::BF16X3:
+                hipLaunchKernelGGL((lean_gemm<3, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                break;
+        }
+    }
+}
+
 template <int ROLE, int TM, int TN>
 static void launch_wide(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
                         const int* act, hipStream_t s, int xcd) {
@@ -1476,7 +1709,8 @@ static void launch_wide(Prec p, const GemmTask* tasks, int64_t n_tasks, const Ge
 
 template <int ROLE>
 static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                             void* const* b, const int* act, int tile, hipStream_t s, int variant, int tile_n) {
+                             void* const* b, const int* act, int tile, hipStream_t s, int variant, int tile_n,
+                             int uflags) {
     if (n_tasks <= 0) return;
     if (tile_n > 0) {
         // tiles of `tile` rows and tile_n columns
@@ -1496,9 +1730,23 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     }
 
     require(tile == 128 || tile == 64 || tile == 32, "grouped GEMM: tile must be 128, 64 or 32");
-    static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 2), xcd = gemm_env("DMRG_GEMM_XCD", 4);
-    const int var = variant >= 0 ? variant : var_env;
-    require(var >= 0 && var <= 3, "grouped GEMM: unknown variant");
+    static const int var_env = gemm_env("DMRG_GEMM_VARIANT", 4), xcd = gemm_env("DMRG_GEMM_XCD", 4);
+    int var = variant >= 0 ? variant : var_env;
+    require(var >= 0 && var <= 4, "grouped GEMM: unknown variant");
+    if (var == 4 && tile == 64) {
+        switch (uflags) {
+            case 0: launch_lean<ROLE, false, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TA: launch_lean<ROLE, true, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TB: launch_lean<ROLE, false, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TA | GT_TB: launch_lean<ROLE, true, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            default: var = 2;  // mixed operand layouts: the generic pipeline
+        }
+        if (var == 4) {
+            DMRG_HIP(hipGetLastError());
+            return;
+        }
+    }
+    if (var == 4) var = 2;
     if (tile == 128) {
         // sixteen waves of 32 x 32; the software-pipelined body
         launch_gemm_tile<ROLE, 128, 2>(p, tasks, n_tasks, terms, b, act, s, xcd);
@@ -1572,12 +1820,13 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
 }
 
 void launch_gemm(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                 void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n) {
-    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n);
+                 void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n, int uflags) {
+    launch_gemm_role<0>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n, uflags);
 }
 void launch_gemm_sigma(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms,
-                       void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n) {
-    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n);
+                       void* const* b, const int* act, hipStream_t s, int tile, int variant, int tile_n,
+                       int uflags) {
+    launch_gemm_role<1>(p, tasks, n_tasks, terms, b, act, tile, s, variant, tile_n, uflags);
 }
 
 void launch_wsum(const SumItem* items, int64_t n_items, const SumTerm* terms, hipStream_t s) {

@@ -46,11 +46,13 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (16, 16, 4), (17, 33, 19), (64, 64, 16), (65, 63
           (70, 130, 50), (130, 65, 200), (3, 300, 2)]
 
 
-@pytest.mark.parametrize("tile", [64, 32, 128, 256])
+@pytest.mark.parametrize("tile,variant", [(64, -1), (64, 2), (64, 0), (32, -1), (128, -1), (256, -1)])
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
-    _log("gemm", m, n, k, ta, tb, tile)
+def test_gemm_kernel(ctx, m, n, k, ta, tb, tile, variant):
+    """Tile 64 runs the default (the lean pipeline for these one-layout
+    lists), the generic software pipeline (2) and the plain kernel (0)."""
+    _log("gemm", m, n, k, ta, tb, tile, variant)
     rng = np.random.default_rng(m * 1000 + n * 10 + k + 7 * ta + 3 * tb)
     Ah = rng.standard_normal((k, m + 3) if ta else (m, k + 3))
     Bh = rng.standard_normal((n, k + 2) if tb else (k, n + 2))
@@ -62,7 +64,7 @@ def test_gemm_kernel(ctx, m, n, k, ta, tb, tile):
             ref = 0.7 * opA @ opB + (Ch[:, :n] if acc else 0)
             Cd = _dev(Ch)
             ctx.gemm(_dev(Ah), _dev(Bh), Cd, m, n, k, ta=bool(ta), tb=bool(tb), alpha=0.7,
-                     accumulate=acc, prec=prec, tile=tile)
+                     accumulate=acc, prec=prec, tile=tile, variant=variant)
             out = Cd.cpu().numpy()
             err = np.abs(out[:, :n] - ref).max() / max(1.0, np.abs(ref).max())
             assert err <= tol, (prec, acc, err)
