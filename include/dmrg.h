@@ -358,13 +358,15 @@ dmrg_status dmrg_env_import(dmrg_ctx* ctx, dmrg_mps* mps, int side, int bond, co
  * dimensions lda, ldb, ldc; op(A) is m x k (ta != 0: A is stored k x m),
  * op(B) is k x n (tb != 0: B is stored n x k).  With DMRG_FP32 / DMRG_BF16
  * the operands are rounded to FP32 first and the result converted back.
- * tile: 64 (workgroup tiles staged through LDS), 32 (one task per wave,
- * operands loaded straight into registers), 128 or 256 (64-row tiles of that
- * many columns).  variant (tile 64): the grouped-GEMM variant of the launch
- * autotuner below (0-4), -1 the process default. */
+ * tile: column count of the output tiles: 64 (workgroup tiles staged
+ * through LDS), 32 (one task per wave, operands loaded straight into
+ * registers), 128 or 256; rows: their row count, 0 for 64 (32 with tile 32)
+ * or 128 (with tile 64 or 128).  variant: the grouped-GEMM variant of the
+ * launch autotuner below (0-4; tiles of 64 or 128 x 64), -1 the process
+ * default. */
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
-                            double* C, int ldc, int accumulate, int tile, int variant);
+                            double* C, int ldc, int accumulate, int tile, int rows, int variant);
 /* Test hook: the sector SVD of the truncation (Eqs. blockdecimation,
  * MPSCform) on n host matrices a (row-major rows[i] x cols[i],
  * concatenated; each dimension in [1, 8192], n in [1, 4096]).  path 0: the
@@ -487,7 +489,8 @@ dmrg_status dmrg_mps_apply(dmrg_ctx* ctx, dmrg_mps* ket, const dmrg_mpo* ket_mpo
  * one operand layout, else 2).  A process-wide tuning table maps a state's
  * shape (K, bond dimension rounded up to a power of two, distance of the
  * pair from the nearer end in power-of-two buckets) to a configuration;
- * states without an entry use tile 64/64, 16384 pieces, variant 4.  Batched sweeps
+ * states without an entry use 64 x 64 tiles in the first pass and 128 x 64
+ * tiles in the second, 16384 pieces, variant 4.  Batched sweeps
  * use the first instance's configuration for the whole batch. */
 /* Time every candidate configuration on `reps` sigma applications (after
  * one warm-up) at the current center in precision prec, store the fastest

@@ -89,7 +89,7 @@ SIGNATURES = {
     "dmrg_env_size": (c_int, [c_void_p, c_int, c_int, P(c_int64)]),
     "dmrg_env_import": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double), c_int64]),
     "dmrg_debug_gemm": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_double,
-                                c_void_p, c_int, c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_int]),
+                                c_void_p, c_int, c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "dmrg_sweep_opts_default": (None, [P(SweepOpts)]),
     "dmrg_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, P(SweepOpts),
                            P(SweepStat), P(c_double)]),

@@ -102,17 +102,18 @@ class Context:
         self.h = h
 
     def gemm(self, A, B, C, m, n, k, ta=False, tb=False, alpha=1.0, accumulate=False,
-             prec=L.DMRG_FP64, tile=64, variant=-1):
+             prec=L.DMRG_FP64, tile=64, variant=-1, rows=0):
         """C[:m, :n] = alpha op(A) op(B) (+ C) on 2-D float64 device tensors (test hook);
-        tile 64: workgroup-tiled kernel (variant: grouped-GEMM variant, -1 the
-        default), 32: one task per wave, 128 / 256: 64-row tiles that wide."""
+        tile: column count of the tiles (64: workgroup-tiled kernel, 32: one task
+        per wave, 128 / 256 wide tiles); rows: 0 (64 rows) or 128; variant: the
+        grouped-GEMM variant, -1 the default."""
         assert C.shape[0] >= m and C.shape[1] >= n
         assert A.shape == ((k, A.shape[1]) if ta else (m, A.shape[1]))
         assert B.shape == ((n, B.shape[1]) if tb else (k, B.shape[1]))
         _torch_sync()
         self.check(self.lib.dmrg_debug_gemm(
             self.h, prec, m, n, k, int(ta), int(tb), alpha, C_void(A), A.stride(0), C_void(B),
-            B.stride(0), C_void(C), C.stride(0), int(accumulate), int(tile), int(variant)))
+            B.stride(0), C_void(C), C.stride(0), int(accumulate), int(tile), int(rows), int(variant)))
 
     def debug_svd(self, mats, path=0):
         """dmrg_debug_svd on a list of 2-D arrays: [(U, S, Vt)]."""

@@ -757,11 +757,12 @@ dmrg_status dmrg_debug_svd(dmrg_ctx* ctx, int n, const int32_t* rows, const int3
 
 dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, int ta, int tb,
                             double alpha, const double* A, int lda, const double* B, int ldb,
-                            double* C, int ldc, int accumulate, int tile, int variant) {
+                            double* C, int ldc, int accumulate, int tile, int rows, int variant) {
     if (!ctx) return DMRG_E_INVAL;
     return guard(ctx, [&] {
         require(A && B && C && m >= 1 && n >= 1 && k >= 1, "bad GEMM arguments");
         require(tile == 64 || tile == 32 || tile == 128 || tile == 256, "tile must be 32, 64, 128 or 256");
+        require(rows == 0 || (rows == 128 && (tile == 64 || tile == 128)), "rows must be 0, or 128 with tile 64 or 128");
         require(variant >= -1 && variant <= 4, "unknown grouped-GEMM variant");
         require(lda >= (ta ? m : k) && ldb >= (tb ? k : n) && ldc >= n, "leading dimension too small");
         require(prec >= DMRG_FP64 && prec <= DMRG_BF16X3, "unknown precision");
@@ -771,8 +772,8 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx* ctx, dmrg_prec prec, int m, int n, int k, 
         const int64_t nb = tb ? int64_t(n - 1) * ldb + k : int64_t(k - 1) * ldb + n;
         const int64_t nc = int64_t(m - 1) * ldc + n;
         GemmList L;
-        L.tile = tile > 64 ? 64 : tile;
-        L.tile_n = tile > 64 ? tile : 0;
+        L.tile = rows == 128 ? 128 : tile > 64 ? 64 : tile;
+        L.tile_n = rows == 128 || tile > 64 ? tile : 0;
         L.variant = variant;
         std::vector<UTerm> terms = {{0, 0, lda, ta != 0, 1, 0, ldb, tb != 0, k, alpha, true}};
         add_unit(L, 2, 0, ldc, m, n, accumulate ? 1 : 0, terms);
@@ -960,6 +961,12 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
         State& st = *mps->st;
         hipStream_t s = ctx->c.stream;
         std::vector<SigmaConfig> cand;
+        // the default (128 x 64 tiles in pass 2), two split-K targets
+        for (double pc : {16384.0, 65536.0}) {
+            SigmaConfig c;
+            c.pieces = pc;
+            cand.push_back(c);
+        }
         // square tiles of 64 or 32 in either pass, two split-K targets
         for (int t1 : {64, 32})
             for (int t2 : {64, 32})
@@ -967,12 +974,14 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
                     SigmaConfig c;
                     c.tile1 = t1;
                     c.tile2 = t2;
+                    c.wide2 = 0;
                     c.pieces = pc;
                     c.variant = t1 == 32 && t2 == 32 ? 0 : 4;
                     cand.push_back(c);
                 }
         {
             SigmaConfig c;  // the generic software pipeline
+            c.wide2 = 0;
             c.variant = 2;
             cand.push_back(c);
         }
@@ -990,7 +999,7 @@ dmrg_status dmrg_autotune(dmrg_ctx* ctx, dmrg_mps* mps, const dmrg_mpo* mpo, dmr
         const int p2[4][2] = {{64, 0}, {64, 128}, {128, 64}, {128, 128}};  // (rows, cols), cols 0: square 64
         for (int w1 : {0, 128})
             for (const auto& r2 : p2) {
-                if (w1 == 0 && r2[1] == 0) continue;  // square in both passes: above
+                if (w1 == 0 && (r2[1] == 0 || r2[0] == 128 && r2[1] == 64)) continue;  // above
                 SigmaConfig c;
                 c.wide1 = w1;
                 c.rows2 = r2[0];

@@ -220,8 +220,9 @@ struct SigmaConfig {
     int tile1 = kTile, tile2 = kTile;  // output tile edges of pass 1 and pass 2
     double pieces = 16384;             // target split-K pieces of pass 2
     int variant = -1;                  // grouped-GEMM variant of the tile-64 passes
-    int wide1 = 0, wide2 = 0;          // > 0: 64-row tiles of this many columns (128 or 256)
-    int rows2 = 64;                    // rows of the pass-2 tiles when wide2 > 0 (64 or 128)
+    int wide1 = 0;                     // > 0: pass-1 tiles of 64 rows and this many columns (128 or 256)
+    int wide2 = 64, rows2 = 128;       // wide2 > 0: pass-2 tiles of rows2 (64 or 128) rows and wide2
+                                       // columns; 0: square tiles of tile2
     int order1 = 0;                    // pass-1 task order: 0 channel-major, 1 sector-major
     int order2 = 0;                    // pass 2: 0 unit by unit, 1 pieces aligned across the units of a sector
 };

@@ -1354,6 +1354,13 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
     std::vector<char> hy(nch, 0), hz(nch, 0);
     for (const BRow& r : Y.rows) hy[r.y] = 1;
     for (const BRow& r : Z.rows) hz[r.y] = 1;
+    // T_y(q) is stored row-major with its row length rounded up to a
+    // multiple of kTAlign elements and every block starting at such a
+    // multiple, so that the rows of a block are equally aligned: the second
+    // pass then reads whole 128-byte lines of T (its K-steps start at the
+    // alignment of the segment, see lean_gemm)
+    constexpr int kTAlign = 16;
+    auto t_ld = [&](int iq) { return int64_t((ts.env[iq].dim + kTAlign - 1) / kTAlign * kTAlign); };
     t_off.assign(size_t(nch) * nq, -1);
     t_total = 0;
     for (int y = 0; y < nch; ++y) {
@@ -1363,7 +1370,7 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
             const int iq2 = dv[iq];
             if (iq2 < 0) continue;
             t_off[size_t(y) * nq + iq] = t_total;
-            t_total += int64_t(ts.sys[iq2].dim) * ts.env[iq].dim;
+            t_total += int64_t(ts.sys[iq2].dim) * t_ld(iq);
         }
     }
     pass1.clear();
@@ -1389,7 +1396,7 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
             const int64_t to = t_off[size_t(y) * nq + iq];
             if (to < 0) continue;
             const int iq2 = dv[iq];
-            const int ncol = ts.env[iq].dim;
+            const int ncol = ts.env[iq].dim, ldt = int(t_ld(iq));
             for (const Seg& so : ts.sys[iq2].segs) {
                 terms.clear();
                 for (int st = 0; st < 4; ++st) {
@@ -1407,7 +1414,7 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
                                      ts.off[iq] + int64_t(sg.off) * ncol, ncol, false, blk.cols, 1.0,
                                      !r.identity});
                 }
-                add_unit(pass1, 2, to + int64_t(so.off) * ncol, ncol, so.dim, ncol, 0, terms);
+                add_unit(pass1, 2, to + int64_t(so.off) * ldt, ldt, so.dim, ncol, 0, terms);
             }
         }
     }
@@ -1441,7 +1448,7 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
                     if (bi < 0) continue;
                     const OpBlock& blk = r.lay->blocks[bi];
                     if (blk.out != so.sec) continue;
-                    uterms[unit_base[iq2] + ui].push_back({0, to + sg.off, ts.env[iq].dim, false, 1,
+                    uterms[unit_base[iq2] + ui].push_back({0, to + sg.off, int(t_ld(iq)), false, 1,
                                                            r.off + blk.off, blk.cols, true, blk.cols,
                                                            1.0, !r.identity});
                     uchan[unit_base[iq2] + ui].push_back(y);

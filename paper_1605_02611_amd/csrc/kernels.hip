@@ -535,54 +535,63 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
             }
 }
 
-// Lean 64x64 tile kernel for lists whose terms all share one operand layout
-// (TA: A stored transposed, TB: B stored transposed, fixed at compile time).
-// The same staging as grouped_gemm VAR 2 (K-steps of KS through LDS, the next
-// step's operands loaded into registers during the current step's MFMAs),
-// written for few instructions per MFMA: every lane loads (elements outside
-// the slice read the slice's nearest element and are zeroed at the store, so
-// no branch waits on a load), global loads from a wave-uniform base with one
-// 32-bit offset register, per-thread row clamps fixed per task, wave-uniform
-// sub-tile flags, and whole K-steps of fully active waves as straight-line
-// MFMAs.  Thread tid stages, per K-step, four elements of A and four of B:
+// Lean tile kernel for lists whose terms all share one operand layout (TA: A
+// stored transposed, TB: B stored transposed, fixed at compile time); tiles
+// of TM = 64 or 128 rows and 64 columns, four waves of (TM/2) x 32.  The same
+// staging as grouped_gemm VAR 2 (K-steps of KS through LDS, the next step's
+// operands loaded into registers during the current step's MFMAs), written
+// for few instructions per MFMA: every lane loads (elements outside the slice
+// read the slice's nearest element, see below, so that no branch waits on a
+// load), global loads from a wave-uniform base with one 32-bit offset
+// register, and wave-uniform sub-tile guards.  Thread tid stages, per
+// K-step, TM/16 elements of A and four of B:
 //   A, TA false: rows (tid >> 4) + 16 i, column tid & 15 of the step
-//   A, TA true:  row tid & 63, columns (tid >> 6) + 4 i
+//   A, TA true:  rows (tid & 63) + 64 (i % (TM/64)), columns (tid >> 6) + 4 (i / (TM/64))
 //   B, TB true:  columns (tid >> 4) + 16 i, row tid & 15 of the step
 //   B, TB false: column tid & 63, rows (tid >> 6) + 4 i
-template <int MODE>
-__device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_pitch<MODE>(64)],
+template <int MODE, int TM>
+__device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_pitch<MODE>(TM)],
                                       const typename Cfg<MODE>::T (&Bs)[KS][lds_pitch<MODE>(64)],
-                                      typename Cfg<MODE>::Acc (&acc)[2][2], int kv, const bool (&act)[2][2],
-                                      int wm, int wn, int lr, int lk) {
+                                      typename Cfg<MODE>::Acc (&acc)[TM / 32][2], int ks0, int kv,
+                                      const bool (&act)[TM / 32][2], int wm, int wn, int lr, int lk) {
+    constexpr int NR = TM / 32;  // 16-row blocks of a wave
     if constexpr (MODE == 0) {
-        for (int ks = 0; ks < kv; ks += 4) {
-            const double a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
-            const double b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
-            if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        for (int ks = ks0; ks < kv; ks += 4) {
+            double a[NR], b[2];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) a[i] = As[ks + lk][wm + 16 * i + lr];
+            b[0] = Bs[ks + lk][wn + lr];
+            b[1] = Bs[ks + lk][wn + 16 + lr];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (act[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     } else if constexpr (MODE == 1) {
-        for (int ks = 0; ks < kv; ks += 4) {
-            const float a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
-            const float b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
-            if (act[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-            if (act[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-            if (act[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-            if (act[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        for (int ks = ks0; ks < kv; ks += 4) {
+            float a[NR], b[2];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) a[i] = As[ks + lk][wm + 16 * i + lr];
+            b[0] = Bs[ks + lk][wn + lr];
+            b[1] = Bs[ks + lk][wn + 16 + lr];
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (act[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     } else {
         // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
         constexpr int NP = bf16_np<MODE>();
-        shrt4 a[2][NP], b[2][NP];
-        for (int i = 0; i < 2; ++i) {
+        shrt4 a[NR][NP], b[2][NP];
+        for (int i = 0; i < NR; ++i)
             bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
                            As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
-            bf16_parts<NP>(Bs[4 * lk][wn + 16 * i + lr], Bs[4 * lk + 1][wn + 16 * i + lr],
-                           Bs[4 * lk + 2][wn + 16 * i + lr], Bs[4 * lk + 3][wn + 16 * i + lr], b[i]);
-        }
-        for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            bf16_parts<NP>(Bs[4 * lk][wn + 16 * j + lr], Bs[4 * lk + 1][wn + 16 * j + lr],
+                           Bs[4 * lk + 2][wn + 16 * j + lr], Bs[4 * lk + 3][wn + 16 * j + lr], b[j]);
+        for (int i = 0; i < NR; ++i)
             for (int j = 0; j < 2; ++j)
                 if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
     }
@@ -591,15 +600,17 @@ __device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_
 #ifndef LEAN_WAVES
 #define LEAN_WAVES 6
 #endif
-template <int MODE, int ROLE, bool TA, bool TB>
-__global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __restrict__ tasks, const GemmTerm* __restrict__ terms,
-                                                     void* const* __restrict__ bases, const int* __restrict__ active,
-                                                     int xcd, int64_t n_tasks) {
+template <int MODE, int ROLE, int TM, bool TA, bool TB>
+__global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(const GemmTask* __restrict__ tasks,
+                                                                             const GemmTerm* __restrict__ terms,
+                                                                             void* const* __restrict__ bases,
+                                                                             const int* __restrict__ active, int xcd,
+                                                                             int64_t n_tasks) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
-    constexpr int TS = 64, P = lds_pitch<MODE>(TS);
-    __shared__ T As[KS][P];
-    __shared__ T Bs[KS][P];
+    constexpr int NR = TM / 32, PA = TM / 16;  // row blocks per wave, A elements per thread
+    __shared__ T As[KS][lds_pitch<MODE>(TM)];
+    __shared__ T Bs[KS][lds_pitch<MODE>(64)];
 
     const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
                        : xcd == 1 ? xcd_task(blockIdx.x, gridDim.x)
@@ -610,12 +621,12 @@ __global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __r
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
 
-    Acc acc[2][2];
-    bool act[2][2];  // 16x16 sub-tile overlaps the task's m x n (uniform per wave)
-    for (int i = 0; i < 2; ++i)
+    Acc acc[NR][2];
+    bool act[NR][2];  // 16x16 sub-tile overlaps the task's m x n (uniform per wave)
+    for (int i = 0; i < NR; ++i)
         for (int j = 0; j < 2; ++j) {
             acc[i][j] = Acc{0, 0, 0, 0};
             act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
@@ -624,40 +635,51 @@ __global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __r
     // Staging coordinates of this thread (see above).  Rows of A past the
     // task's m and columns of B past its n are read clamped to the last one
     // and left in the tile: they reach only outputs that are not written.
-    // Columns of the K-step past the term's K are clamped too, and zeroed in
-    // B, which is all the sum over the step needs.
+    // Columns of the K-step outside the term's K range are clamped too, and
+    // zeroed in B, which is all the sum over the step needs.  When the rows of
+    // a K-contiguous A are equally aligned (lda a multiple of KS), a term's
+    // K-steps start at the KS-element boundary at or before its first column
+    // (k0 <= 0), so that every row of every step is one aligned run of KS
+    // elements rather than two part lines.
     const int a_r = TA ? (tid & 63) : (tid >> 4), a_k = TA ? (tid >> 6) : (tid & 15);
     const int b_c = TB ? (tid >> 4) : (tid & 63), b_k = TB ? (tid & 15) : (tid >> 6);
     const int m1 = task.m - 1, n1 = task.n - 1;
+    auto a_row = [&](int i) { return TA ? a_r + 64 * (i % (TM / 64)) : a_r + 16 * i; };
+    auto a_col = [&](int i) { return TA ? a_k + 4 * (i / (TM / 64)) : a_k; };
 
-    T ra[4], rb[4];
+    auto kstart = [&](const GemmTerm& t) { return !TA && t.lda % KS == 0 ? -int(t.a_off % KS) : 0; };
+
+    T ra[PA], rb[4];
     unsigned kmask = 0;  // bit i: rb[i] inside the term's K range
     auto load = [&](const GemmTerm& t, int k0) {
         const gmem<T>* A = gin<T>(bases[t.a_buf]) + t.a_off;
         const gmem<T>* B = gin<T>(bases[t.b_buf]) + t.b_off;
-        const int km = t.k - 1 - k0;  // last K offset of the slice in this step (>= 0)
+        // K offsets of the slice in this step: klo .. km (klo > 0 only in the
+        // first step of an aligned term, km >= 0)
+        const int klo = -k0, km = t.k - 1 - k0;
         const uint32_t lda = uint32_t(t.lda), ldb = uint32_t(t.ldb);
         if (!TA) {
-            const uint32_t kc = uint32_t(k0 + min(a_k, km));
+            const uint32_t kc = uint32_t(k0 + min(max(a_k, klo), km));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = gld(A, __umul24(uint32_t(min(a_r + 16 * i, m1)), lda) + kc);
+            for (int i = 0; i < PA; ++i) ra[i] = gld(A, __umul24(uint32_t(min(a_row(i), m1)), lda) + kc);
         } else {
-            const uint32_t rc = uint32_t(min(a_r, m1));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ra[i] = gld(A, __umul24(uint32_t(k0 + min(a_k + 4 * i, km)), lda) + rc);
+            for (int i = 0; i < PA; ++i)
+                ra[i] = gld(A, __umul24(uint32_t(k0 + min(a_col(i), km)), lda) + uint32_t(min(a_row(i), m1)));
         }
         if (TB) {
-            const uint32_t kc = uint32_t(k0 + min(b_k, km));
+            const uint32_t kc = uint32_t(k0 + min(max(b_k, klo), km));
 #pragma unroll
             for (int i = 0; i < 4; ++i) rb[i] = gld(B, __umul24(uint32_t(min(b_c + 16 * i, n1)), ldb) + kc);
-            kmask = b_k <= km ? 0xfu : 0u;
+            kmask = b_k >= klo && b_k <= km ? 0xfu : 0u;
         } else {
             const uint32_t cc = uint32_t(min(b_c, n1));
             unsigned m = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                rb[i] = gld(B, __umul24(uint32_t(k0 + min(b_k + 4 * i, km)), ldb) + cc);
-                m |= unsigned(b_k + 4 * i <= km) << i;
+                const int kk = b_k + 4 * i;
+                rb[i] = gld(B, __umul24(uint32_t(k0 + min(max(kk, klo), km)), ldb) + cc);
+                m |= unsigned(kk >= klo && kk <= km) << i;
             }
             kmask = m;
         }
@@ -665,38 +687,39 @@ __global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __r
     auto store = [&](const GemmTerm& t) {
         const T alpha = T(t.alpha);
 #pragma unroll
+        for (int i = 0; i < PA; ++i) As[a_col(i)][a_row(i)] = ra[i];
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
             const T vb = (kmask >> i) & 1u ? rb[i] * alpha : T(0);
-            if (TA) As[a_k + 4 * i][a_r] = ra[i];
-            else As[a_k][a_r + 16 * i] = ra[i];
             if (TB) Bs[b_k][b_c + 16 * i] = vb;
             else Bs[b_k + 4 * i][b_c] = vb;
         }
     };
 
-    int l = task.l_begin, k0 = 0;
+    int l = task.l_begin;
     if (l < task.l_end) {
         GemmTerm g = terms[l], gn = g;
         if (l + 1 < task.l_end) gn = terms[l + 1];
-        load(g, 0);
+        int k0 = kstart(g);
+        load(g, k0);
         while (true) {
             store(g);
             __syncthreads();
-            const int kv = min(KS, g.k - k0);
+            const int kv = min(KS, g.k - k0), ks0 = k0 < 0 ? (-k0) & ~3 : 0;
             int nk = k0 + KS;
             bool more = true;
             if (nk >= g.k) {
-                nk = 0;
                 ++l;
                 if (l < task.l_end) {
                     g = gn;
+                    nk = kstart(g);
                     if (l + 1 < task.l_end) gn = terms[l + 1];
                 } else {
                     more = false;
                 }
             }
             if (more) load(g, nk);  // in flight during the MFMAs
-            tile_mfma_step<MODE>(As, Bs, acc, kv, act, wm, wn, lr, lk);
+            tile_mfma_step<MODE, TM>(As, Bs, acc, ks0, kv, act, wm, wn, lr, lk);
             __syncthreads();
             if (!more) break;
             k0 = nk;
@@ -705,7 +728,7 @@ __global__ __launch_bounds__(256, LEAN_WAVES) void lean_gemm(const GemmTask* __r
     // D layout of a 16x16 tile: register e of lane (lr + 16 lk) holds
     // row 4 lk + e for the FP32 MFMAs but row 4 e + lk for the FP64 MFMA
     gmem<T>* C = gout<T>(bases[task.c_buf]) + task.c_off;
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NR; ++i)
         for (int j = 0; j < 2; ++j)
             for (int e = 0; e < 4; ++e) {
                 const int r = wm + 16 * i + (MODE == 0 ? 4 * e + lk : 4 * lk + e);
@@ -1657,7 +1680,7 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     }
 }
 
-template <int ROLE, bool TA, bool TB>
+template <int ROLE, int TM, bool TA, bool TB>
 static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
                         const int* act, hipStream_t s, int xcd) {
     const int64_t kMaxGrid = 1 << 30;
@@ -1667,16 +1690,16 @@ static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const Ge
         const unsigned g = unsigned((nt + step - 1) / step * step);
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((lean_gemm<0, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<0, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((lean_gemm<1, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<1, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((lean_gemm<2, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<2, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::BF16X3:
-                hipLaunchKernelGGL((lean_gemm<3, ROLE, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<3, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
         }
     }
@@ -1719,8 +1742,20 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
             launch_wide<ROLE, 64, 128>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
         else if (tile == 64 && tile_n == 256)
             launch_wide<ROLE, 64, 256>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
-        else if (tile == 128 && tile_n == 64)
-            launch_wide<ROLE, 128, 64>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        else if (tile == 128 && tile_n == 64) {
+            static const int var_w = gemm_env("DMRG_GEMM_VARIANT", 4);
+            const int vw = variant >= 0 ? variant : var_w;
+            if (vw == 4 && uflags == 0)
+                launch_lean<ROLE, 128, false, false>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+            else if (vw == 4 && uflags == GT_TA)
+                launch_lean<ROLE, 128, true, false>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+            else if (vw == 4 && uflags == GT_TB)
+                launch_lean<ROLE, 128, false, true>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+            else if (vw == 4 && uflags == (GT_TA | GT_TB))
+                launch_lean<ROLE, 128, true, true>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+            else
+                launch_wide<ROLE, 128, 64>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
+        }
         else if (tile == 128 && tile_n == 128)
             launch_wide<ROLE, 128, 128>(p, tasks, n_tasks, terms, b, act, s, xcd_w);
         else
@@ -1735,10 +1770,10 @@ static void launch_gemm_role(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     require(var >= 0 && var <= 4, "grouped GEMM: unknown variant");
     if (var == 4 && tile == 64) {
         switch (uflags) {
-            case 0: launch_lean<ROLE, false, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
-            case GT_TA: launch_lean<ROLE, true, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
-            case GT_TB: launch_lean<ROLE, false, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
-            case GT_TA | GT_TB: launch_lean<ROLE, true, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case 0: launch_lean<ROLE, 64, false, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TA: launch_lean<ROLE, 64, true, false>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TB: launch_lean<ROLE, 64, false, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
+            case GT_TA | GT_TB: launch_lean<ROLE, 64, true, true>(p, tasks, n_tasks, terms, b, act, s, xcd); break;
             default: var = 2;  // mixed operand layouts: the generic pipeline
         }
         if (var == 4) {

@@ -137,7 +137,7 @@ def test_gpu_calls_on_host_context_fail_cleanly(hctx):
 
 def test_tuning_table_round_trip_and_validation():
     base = P.tune_table()
-    defaults = {"wide1": 0, "wide2": 0, "rows2": 64, "order1": 0, "order2": 0}
+    defaults = {"wide1": 0, "wide2": 64, "rows2": 128, "order1": 0, "order2": 0}
     entry = {"K99_M1024_d3": {"tile1": 64, "tile2": 32, "pieces": 4096.0, "variant": 2}}
     P.tune_table_load(entry)
     t = P.tune_table()

@@ -46,13 +46,15 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (16, 16, 4), (17, 33, 19), (64, 64, 16), (65, 63
           (70, 130, 50), (130, 65, 200), (3, 300, 2)]
 
 
-@pytest.mark.parametrize("tile,variant", [(64, -1), (64, 2), (64, 0), (32, -1), (128, -1), (256, -1)])
+@pytest.mark.parametrize("tile,rows,variant", [(64, 0, -1), (64, 0, 2), (64, 0, 0), (32, 0, -1), (128, 0, -1),
+                                               (256, 0, -1), (64, 128, -1), (64, 128, 2), (128, 128, -1)])
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_gemm_kernel(ctx, m, n, k, ta, tb, tile, variant):
-    """Tile 64 runs the default (the lean pipeline for these one-layout
-    lists), the generic software pipeline (2) and the plain kernel (0)."""
-    _log("gemm", m, n, k, ta, tb, tile, variant)
+def test_gemm_kernel(ctx, m, n, k, ta, tb, tile, rows, variant):
+    """Tiles of 64 and 128 x 64 run the default (the lean pipeline for
+    these one-layout lists) and the generic kernels (variants 2 and 0; the
+    wide kernel for 128 x 64)."""
+    _log("gemm", m, n, k, ta, tb, tile, rows, variant)
     rng = np.random.default_rng(m * 1000 + n * 10 + k + 7 * ta + 3 * tb)
     Ah = rng.standard_normal((k, m + 3) if ta else (m, k + 3))
     Bh = rng.standard_normal((n, k + 2) if tb else (k, n + 2))
@@ -64,7 +66,7 @@ def test_gemm_kernel(ctx, m, n, k, ta, tb, tile, variant):
             ref = 0.7 * opA @ opB + (Ch[:, :n] if acc else 0)
             Cd = _dev(Ch)
             ctx.gemm(_dev(Ah), _dev(Bh), Cd, m, n, k, ta=bool(ta), tb=bool(tb), alpha=0.7,
-                     accumulate=acc, prec=prec, tile=tile, variant=variant)
+                     accumulate=acc, prec=prec, tile=tile, rows=rows, variant=variant)
             out = Cd.cpu().numpy()
             err = np.abs(out[:, :n] - ref).max() / max(1.0, np.abs(ref).max())
             assert err <= tol, (prec, acc, err)
@@ -428,7 +430,7 @@ def test_autotune_picks_a_configuration_that_gives_the_same_sweeps(ctx):
     a = P.Mps.random(ctx, mpo, M, vals)
     b = P.Mps.random(ctx, mpo, M, vals)
     sa, _ = a.sweep(M, 2, P.default_opts(dav_tol=1e-10))
-    P.tune_table_load({k: {"tile1": 32, "tile2": 32, "pieces": 4096, "variant": 0}
+    P.tune_table_load({k: {"tile1": 32, "tile2": 32, "pieces": 4096, "variant": 0, "wide2": 0}
                        for k in ["K8_M32_d0", "K8_M32_d1", "K8_M32_d2"]})
     sb, _ = b.sweep(M, 2, P.default_opts(dav_tol=1e-10))
     assert abs(a.energy() - b.energy()) < 1e-10
