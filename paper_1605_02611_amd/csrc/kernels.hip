@@ -549,9 +549,9 @@ __global__ __launch_bounds__((TS / 32) * (TS / 32) * 64, TS == 64 ? 7 : 1) void 
 //   A, TA true:  rows (tid & 63) + 64 (i % (TM/64)), columns (tid >> 6) + 4 (i / (TM/64))
 //   B, TB true:  columns (tid >> 4) + 16 i, row tid & 15 of the step
 //   B, TB false: column tid & 63, rows (tid >> 6) + 4 i
-template <int MODE, int TM>
-__device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_pitch<MODE>(TM)],
-                                      const typename Cfg<MODE>::T (&Bs)[KS][lds_pitch<MODE>(64)],
+template <int MODE, int TM, int KL>
+__device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KL][lds_pitch<MODE>(TM)],
+                                      const typename Cfg<MODE>::T (&Bs)[KL][lds_pitch<MODE>(64)],
                                       typename Cfg<MODE>::Acc (&acc)[TM / 32][2], int ks0, int kv,
                                       const bool (&act)[TM / 32][2], int wm, int wn, int lr, int lk) {
     constexpr int NR = TM / 32;  // 16-row blocks of a wave
@@ -582,35 +582,48 @@ __device__ inline void tile_mfma_step(const typename Cfg<MODE>::T (&As)[KS][lds_
                     if (act[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     } else {
-        // one 16x16x16 BF16 MFMA per output tile: lane holds k = 4*lk .. 4*lk+3
+        // one 16x16x16 BF16 MFMA per output tile and 16 columns of the step:
+        // lane holds k = kb + 4*lk .. kb + 4*lk + 3
         constexpr int NP = bf16_np<MODE>();
-        shrt4 a[NR][NP], b[2][NP];
-        for (int i = 0; i < NR; ++i)
-            bf16_parts<NP>(As[4 * lk][wm + 16 * i + lr], As[4 * lk + 1][wm + 16 * i + lr],
-                           As[4 * lk + 2][wm + 16 * i + lr], As[4 * lk + 3][wm + 16 * i + lr], a[i]);
-        for (int j = 0; j < 2; ++j)
-            bf16_parts<NP>(Bs[4 * lk][wn + 16 * j + lr], Bs[4 * lk + 1][wn + 16 * j + lr],
-                           Bs[4 * lk + 2][wn + 16 * j + lr], Bs[4 * lk + 3][wn + 16 * j + lr], b[j]);
-        for (int i = 0; i < NR; ++i)
+        for (int kb = ks0 & ~15; kb < kv; kb += 16) {
+            shrt4 a[NR][NP], b[2][NP];
+            for (int i = 0; i < NR; ++i)
+                bf16_parts<NP>(As[kb + 4 * lk][wm + 16 * i + lr], As[kb + 4 * lk + 1][wm + 16 * i + lr],
+                               As[kb + 4 * lk + 2][wm + 16 * i + lr], As[kb + 4 * lk + 3][wm + 16 * i + lr], a[i]);
             for (int j = 0; j < 2; ++j)
-                if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
+                bf16_parts<NP>(Bs[kb + 4 * lk][wn + 16 * j + lr], Bs[kb + 4 * lk + 1][wn + 16 * j + lr],
+                               Bs[kb + 4 * lk + 2][wn + 16 * j + lr], Bs[kb + 4 * lk + 3][wn + 16 * j + lr], b[j]);
+            for (int i = 0; i < NR; ++i)
+                for (int j = 0; j < 2; ++j)
+                    if (act[i][j]) acc[i][j] = bf16_mfma<NP>(a[i], b[j], acc[i][j]);
+        }
     }
 }
 
+// Waves per SIMD the lean kernel is built for (registers): 64-row tiles
+// with K-steps of 16 six, 128-row tiles four, K-steps of 32 (twice the LDS)
+// two.
 #ifndef LEAN_WAVES
 #define LEAN_WAVES 6
 #endif
-template <int MODE, int ROLE, int TM, bool TA, bool TB>
-__global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(const GemmTask* __restrict__ tasks,
-                                                                             const GemmTerm* __restrict__ terms,
-                                                                             void* const* __restrict__ bases,
-                                                                             const int* __restrict__ active, int xcd,
-                                                                             int64_t n_tasks) {
+template <int TM, int KL>
+constexpr int lean_waves() {
+    return KL == 32 ? 2 : TM == 64 ? LEAN_WAVES : 4;
+}
+
+template <int MODE, int ROLE, int TM, int KL, bool TA, bool TB>
+__global__ __launch_bounds__(256, (lean_waves<TM, KL>())) void lean_gemm(const GemmTask* __restrict__ tasks,
+                                                                        const GemmTerm* __restrict__ terms,
+                                                                        void* const* __restrict__ bases,
+                                                                        const int* __restrict__ active, int xcd,
+                                                                        int64_t n_tasks) {
     using T = typename Cfg<MODE>::T;
     using Acc = typename Cfg<MODE>::Acc;
-    constexpr int NR = TM / 32, PA = TM / 16;  // row blocks per wave, A elements per thread
-    __shared__ T As[KS][lds_pitch<MODE>(TM)];
-    __shared__ T Bs[KS][lds_pitch<MODE>(64)];
+    constexpr int NR = TM / 32;                        // row blocks per wave
+    constexpr int PA = TM * KL / 256, PB = 64 * KL / 256;  // A and B elements per thread and K-step
+    constexpr int RS = 256 / KL;                        // rows (columns) staged per pass of the threads
+    __shared__ T As[KL][lds_pitch<MODE>(TM)];
+    __shared__ T Bs[KL][lds_pitch<MODE>(64)];
 
     const int64_t ti = xcd == 0 ? int64_t(blockIdx.x)
                        : xcd == 1 ? xcd_task(blockIdx.x, gridDim.x)
@@ -632,24 +645,24 @@ __global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(cons
             act[i][j] = (wm + 16 * i < task.m) && (wn + 16 * j < task.n);
         }
 
-    // Staging coordinates of this thread (see above).  Rows of A past the
-    // task's m and columns of B past its n are read clamped to the last one
-    // and left in the tile: they reach only outputs that are not written.
-    // Columns of the K-step outside the term's K range are clamped too, and
-    // zeroed in B, which is all the sum over the step needs.  When the rows of
-    // a K-contiguous A are equally aligned (lda a multiple of KS), a term's
-    // K-steps start at the KS-element boundary at or before its first column
-    // (k0 <= 0), so that every row of every step is one aligned run of KS
-    // elements rather than two part lines.
-    const int a_r = TA ? (tid & 63) : (tid >> 4), a_k = TA ? (tid >> 6) : (tid & 15);
-    const int b_c = TB ? (tid >> 4) : (tid & 63), b_k = TB ? (tid & 15) : (tid >> 6);
+    // Staging coordinates of this thread (see above; with K-steps of KL the
+    // K-contiguous operands take KL lanes per row and 256 / KL rows per pass).
+    // Rows of A past the task's m and columns of B past its n are read clamped
+    // to the last one and left in the tile: they reach only outputs that are
+    // not written.  Columns of the K-step outside the term's K range are
+    // clamped too, and zeroed in B, which is all the sum over the step needs.
+    // When the rows of a K-contiguous A are equally aligned (lda a multiple of
+    // 16), a term's K-steps start at the 16-element boundary at or before its
+    // first column (k0 <= 0), so that every row of every step is made of whole
+    // aligned 16-element runs rather than part lines.
+    const int a_r = TA ? (tid & 63) : (tid / KL), a_k = TA ? (tid >> 6) : (tid % KL);
+    const int b_c = TB ? (tid / KL) : (tid & 63), b_k = TB ? (tid % KL) : (tid >> 6);
     const int m1 = task.m - 1, n1 = task.n - 1;
-    auto a_row = [&](int i) { return TA ? a_r + 64 * (i % (TM / 64)) : a_r + 16 * i; };
+    auto a_row = [&](int i) { return TA ? a_r + 64 * (i % (TM / 64)) : a_r + RS * i; };
     auto a_col = [&](int i) { return TA ? a_k + 4 * (i / (TM / 64)) : a_k; };
+    auto kstart = [&](const GemmTerm& t) { return !TA && t.lda % 16 == 0 ? -int(t.a_off % 16) : 0; };
 
-    auto kstart = [&](const GemmTerm& t) { return !TA && t.lda % KS == 0 ? -int(t.a_off % KS) : 0; };
-
-    T ra[PA], rb[4];
+    T ra[PA], rb[PB];
     unsigned kmask = 0;  // bit i: rb[i] inside the term's K range
     auto load = [&](const GemmTerm& t, int k0) {
         const gmem<T>* A = gin<T>(bases[t.a_buf]) + t.a_off;
@@ -670,13 +683,13 @@ __global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(cons
         if (TB) {
             const uint32_t kc = uint32_t(k0 + min(max(b_k, klo), km));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) rb[i] = gld(B, __umul24(uint32_t(min(b_c + 16 * i, n1)), ldb) + kc);
-            kmask = b_k >= klo && b_k <= km ? 0xfu : 0u;
+            for (int i = 0; i < PB; ++i) rb[i] = gld(B, __umul24(uint32_t(min(b_c + RS * i, n1)), ldb) + kc);
+            kmask = b_k >= klo && b_k <= km ? ~0u : 0u;
         } else {
             const uint32_t cc = uint32_t(min(b_c, n1));
             unsigned m = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < PB; ++i) {
                 const int kk = b_k + 4 * i;
                 rb[i] = gld(B, __umul24(uint32_t(k0 + min(max(kk, klo), km)), ldb) + cc);
                 m |= unsigned(kk >= klo && kk <= km) << i;
@@ -689,9 +702,9 @@ __global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(cons
 #pragma unroll
         for (int i = 0; i < PA; ++i) As[a_col(i)][a_row(i)] = ra[i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < PB; ++i) {
             const T vb = (kmask >> i) & 1u ? rb[i] * alpha : T(0);
-            if (TB) Bs[b_k][b_c + 16 * i] = vb;
+            if (TB) Bs[b_k][b_c + RS * i] = vb;
             else Bs[b_k + 4 * i][b_c] = vb;
         }
     };
@@ -705,8 +718,8 @@ __global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(cons
         while (true) {
             store(g);
             __syncthreads();
-            const int kv = min(KS, g.k - k0), ks0 = k0 < 0 ? (-k0) & ~3 : 0;
-            int nk = k0 + KS;
+            const int kv = min(KL, g.k - k0), ks0 = k0 < 0 ? (-k0) & ~3 : 0;
+            int nk = k0 + KL;
             bool more = true;
             if (nk >= g.k) {
                 ++l;
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(256, TM == 64 ? LEAN_WAVES : 4) void lean_gemm(cons
                 }
             }
             if (more) load(g, nk);  // in flight during the MFMAs
-            tile_mfma_step<MODE, TM>(As, Bs, acc, ks0, kv, act, wm, wn, lr, lk);
+            tile_mfma_step<MODE, TM, KL>(As, Bs, acc, ks0, kv, act, wm, wn, lr, lk);
             __syncthreads();
             if (!more) break;
             k0 = nk;
@@ -1680,9 +1693,9 @@ static void launch_gemm_tile(Prec p, const GemmTask* tasks, int64_t n_tasks, con
     }
 }
 
-template <int ROLE, int TM, bool TA, bool TB>
-static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
-                        const int* act, hipStream_t s, int xcd) {
+template <int ROLE, int TM, int KL, bool TA, bool TB>
+static void launch_lean_k(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
+                          const int* act, hipStream_t s, int xcd) {
     const int64_t kMaxGrid = 1 << 30;
     for (int64_t off = 0; off < n_tasks; off += kMaxGrid) {
         const int64_t nt = std::min<int64_t>(kMaxGrid, n_tasks - off);
@@ -1690,19 +1703,28 @@ static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const Ge
         const unsigned g = unsigned((nt + step - 1) / step * step);
         switch (p) {
             case Prec::F64:
-                hipLaunchKernelGGL((lean_gemm<0, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<0, ROLE, TM, KL, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::F32:
-                hipLaunchKernelGGL((lean_gemm<1, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<1, ROLE, TM, KL, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::BF16:
-                hipLaunchKernelGGL((lean_gemm<2, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<2, ROLE, TM, KL, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
             case Prec::BF16X3:
-                hipLaunchKernelGGL((lean_gemm<3, ROLE, TM, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
+                hipLaunchKernelGGL((lean_gemm<3, ROLE, TM, KL, TA, TB>), dim3(g), dim3(256), 0, s, tasks + off, terms, b, act, xcd, nt);
                 break;
         }
     }
+}
+
+// The lean kernel with K-steps of 16 (steps of 32 halve the barriers per
+// MFMA but double the LDS of a workgroup; they measured slower in both sigma
+// passes and on plain GEMMs).
+template <int ROLE, int TM, bool TA, bool TB>
+static void launch_lean(Prec p, const GemmTask* tasks, int64_t n_tasks, const GemmTerm* terms, void* const* b,
+                        const int* act, hipStream_t s, int xcd) {
+    launch_lean_k<ROLE, TM, KS, TA, TB>(p, tasks, n_tasks, terms, b, act, s, xcd);
 }
 
 template <int ROLE, int TM, int TN>
