@@ -1576,8 +1576,57 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_svd_kernel(const SvdJob
     jacobi_output(job, d, A, V, nrm, perm, tid, blockDim.x, converged ? sweep : -1);
 }
 
+// One Jacobi rotation of columns p and q by a workgroup of four waves (the
+// round kernel of the large sectors): the three column sums are split over
+// 256 lanes and combined in a fixed order through LDS, so every thread takes
+// the same decision; then the rotation of A's and V's columns is split the
+// same way.
+__device__ inline bool jacobi_rotate_wg(double* A, double* V, int m, int n, int p, int q, int tid) {
+    __shared__ double part[3][4];
+    double* a = A + int64_t(p) * m;
+    double* b = A + int64_t(q) * m;
+    double al = 0, be = 0, ga = 0;
+    for (int i = tid; i < m; i += 256) {
+        const double x = a[i], y = b[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = al;
+        part[1][tid >> 6] = be;
+        part[2][tid >> 6] = ga;
+    }
+    __syncthreads();
+    al = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
+    be = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+    ga = (part[2][0] + part[2][1]) + (part[2][2] + part[2][3]);
+    if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return false;
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = zeta == 0.0 ? 1.0 : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+    for (int i = tid; i < m; i += 256) {
+        const double x = a[i], y = b[i];
+        a[i] = c * x - s * y;
+        b[i] = s * x + c * y;
+    }
+    double* vp = V + int64_t(p) * n;
+    double* vq = V + int64_t(q) * n;
+    for (int i = tid; i < n; i += 256) {
+        const double x = vp[i], y = vq[i];
+        vp[i] = c * x - s * y;
+        vq[i] = s * x + c * y;
+    }
+    return true;
+}
+
 // Large sectors: the working set in global memory, one launch per round
-// covering the pairs of every sector (one wave per pair).
+// covering the pairs of every sector (one workgroup of four waves per pair:
+// a round has a few hundred to a few thousand pairs, so a wave per pair left
+// most of the chip idle and each wave walking a whole column).
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_init_kernel(const SvdJob* __restrict__ jobs) {
     const SvdJob job = jobs[blockIdx.x];
     const JacobiDims d = jacobi_dims(job);
@@ -1588,7 +1637,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const SvdJob* __restr
                                                            const int2* __restrict__ slots, int64_t n_slots,
                                                            int rd, const int* __restrict__ live,
                                                            int* __restrict__ rotated) {
-    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    // every exit below is uniform per workgroup (one slot per workgroup)
+    const int64_t w = blockIdx.x;
     if (w >= n_slots) return;
     const int2 sl = slots[w];
     if (!live[sl.x]) return;
@@ -1601,7 +1651,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const SvdJob* __restr
     if (p >= d.n || q >= d.n) return;
     double* A = job.work;
     double* V = job.work + int64_t(d.m) * d.n;
-    if (jacobi_rotate(A, V, d.m, d.n, p, q, threadIdx.x & 63) && (threadIdx.x & 63) == 0) rotated[sl.x] = 1;
+    if (jacobi_rotate_wg(A, V, d.m, d.n, p, q, threadIdx.x) && threadIdx.x == 0) rotated[sl.x] = 1;
 }
 
 // All rounds of one Jacobi sweep of the large sectors in one cooperative
@@ -1996,8 +2046,9 @@ void launch_jacobi_init(const SvdJob* jobs, int n_jobs, hipStream_t s) {
 void launch_jacobi_round(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rd, const int* live,
                          int* rotated, hipStream_t s) {
     if (n_slots <= 0) return;
-    hipLaunchKernelGGL(jacobi_round_kernel, dim3(unsigned((n_slots + 3) / 4)), dim3(256), 0, s, jobs, slots,
-                       n_slots, rd, live, rotated);
+    require(n_slots < (int64_t(1) << 31), "Jacobi round: too many column pairs");
+    hipLaunchKernelGGL(jacobi_round_kernel, dim3(unsigned(n_slots)), dim3(256), 0, s, jobs, slots, n_slots, rd,
+                       live, rotated);
     DMRG_HIP(hipGetLastError());
 }
 bool launch_jacobi_sweep(const SvdJob* jobs, const int2* slots, int64_t n_slots, int rounds, const int* live,
