@@ -224,7 +224,8 @@ struct SigmaConfig {
     int wide2 = 64, rows2 = 128;       // wide2 > 0: pass-2 tiles of rows2 (64 or 128) rows and wide2
                                        // columns; 0: square tiles of tile2
     int order1 = 0;                    // pass-1 task order: 0 channel-major, 1 sector-major
-    int order2 = 0;                    // pass 2: 0 unit by unit, 1 pieces aligned across the units of a sector
+    int order2 = 0;                    // pass 2: 0 unit by unit, then longest task first; 1 pieces
+                                       // aligned across the units of a sector
 };
 
 // Weighted sums of equally shaped buffers: out[e] = sum_t coef_t src_t[e]

@@ -1489,6 +1489,22 @@ void build_sigma_lists(const MPO& mpo, int j, const TwoSite& ts, const Blocked& 
                 add_unit(pass2, 2, ts.off[iq2] + so.off, ld2, nrow, so.dim, 0, uterms[u], su[u], ts.n);
             }
         }
+        // Longest first: the split-K pieces leave tasks of unequal length, and
+        // with about eight tasks per workgroup slot of the chip, short tasks
+        // at the end fill the last round where long ones would leave slots
+        // idle.  Length = K-steps of 16 over the task's terms (plus one for
+        // the aligned start); ties keep the unit order.  The tasks write
+        // disjoint outputs, so their order changes no result.
+        std::vector<int64_t> key(pass2.tasks.size(), 0);
+        for (size_t i = 0; i < key.size(); ++i)
+            for (int l = pass2.tasks[i].l_begin; l < pass2.tasks[i].l_end; ++l)
+                key[i] += (pass2.terms[size_t(l)].k + 15) / 16 + 1;
+        std::vector<size_t> idx(key.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key[a] > key[b]; });
+        std::vector<GemmTask> sorted(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) sorted[i] = pass2.tasks[idx[i]];
+        pass2.tasks.swap(sorted);
     } else {
         // The units of one destination sector (its column segments t') read
         // the same panels T_y(q): cut their K ranges at common channel

@@ -664,9 +664,8 @@ __global__ __launch_bounds__(256, (lean_waves<TM, KL>())) void lean_gemm(const G
 
     T ra[PA], rb[PB];
     unsigned kmask = 0;  // bit i: rb[i] inside the term's K range
-    auto load = [&](const GemmTerm& t, int k0) {
-        const gmem<T>* A = gin<T>(bases[t.a_buf]) + t.a_off;
-        const gmem<T>* B = gin<T>(bases[t.b_buf]) + t.b_off;
+    // A, B: the term's operands (read from the buffer table once per term)
+    auto load = [&](const GemmTerm& t, const gmem<T>* A, const gmem<T>* B, int k0) {
         // K offsets of the slice in this step: klo .. km (klo > 0 only in the
         // first step of an aligned term, km >= 0)
         const int klo = -k0, km = t.k - 1 - k0;
@@ -713,8 +712,10 @@ __global__ __launch_bounds__(256, (lean_waves<TM, KL>())) void lean_gemm(const G
     if (l < task.l_end) {
         GemmTerm g = terms[l], gn = g;
         if (l + 1 < task.l_end) gn = terms[l + 1];
+        const gmem<T>* pa = gin<T>(bases[g.a_buf]) + g.a_off;
+        const gmem<T>* pb = gin<T>(bases[g.b_buf]) + g.b_off;
         int k0 = kstart(g);
-        load(g, k0);
+        load(g, pa, pb, k0);
         while (true) {
             store(g);
             __syncthreads();
@@ -725,13 +726,15 @@ __global__ __launch_bounds__(256, (lean_waves<TM, KL>())) void lean_gemm(const G
                 ++l;
                 if (l < task.l_end) {
                     g = gn;
+                    pa = gin<T>(bases[g.a_buf]) + g.a_off;
+                    pb = gin<T>(bases[g.b_buf]) + g.b_off;
                     nk = kstart(g);
                     if (l + 1 < task.l_end) gn = terms[l + 1];
                 } else {
                     more = false;
                 }
             }
-            if (more) load(g, nk);  // in flight during the MFMAs
+            if (more) load(g, pa, pb, nk);  // in flight during the MFMAs
             tile_mfma_step<MODE, TM, KL>(As, Bs, acc, ks0, kv, act, wm, wn, lr, lk);
             __syncthreads();
             if (!more) break;
